@@ -1,0 +1,175 @@
+"""Time-to-tolerance benchmark of IterativeCUR on one MI355X.
+
+Default workload: the dense RBF kernel matrix A_ij = exp(-||x_i - y_j||^2 / (2 * 0.5^2)),
+40000 x 40000, x_i, y_j seeded U[0,1]^3, stored FP32 in HBM; tolerance 1e-4, block
+b = 100 (c = 110 sketch rows), sparse-sign sketch with 8 nonzeros per column, plain FP32
+form.  One step is one complete icur_run call (sketch, every selection and residual
+iteration until rho <= tol, and the FP64 core), with A already resident on the device.
+
+Prints one JSON line (the contract described in the repository's design doc):
+  value        mean time-to-tolerance over the timed steps, seconds (lower is better)
+  roofline     the sketch product (the dominant kernel) against HBM bandwidth, from
+               device events around its launches inside the timed calls
+  cpu_baseline the FP64 NumPy oracle timed on the host on a bounded sample (a smaller
+               RBF matrix of the same recipe), extrapolated to the full size by the
+               O(m n) cost of its sketch
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--form fp32|bf16]
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-tol (s) + sketch TFLOP/s|GB/s, BF16-split/batched vs FP32 plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("icur_wide_kernel.h", "icur_gemm.hip", "icur_wide_f64.hip"):
+        with open(os.path.join(ROOT, "paper_2509_21963_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key):
+    """HBM bytes per launch of the sketch product from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sketch_product_%s_traffic.json" % workload_key)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(m_sample=16000, n_sample=16000, m_full=40000, n_full=40000, tol=1e-4, b=100):
+    """The FP64 oracle on an m_sample x n_sample RBF matrix of the same recipe."""
+    import numpy as np
+    from oracle.icur import iterative_cur
+    from paper_2509_21963_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    A32, A64 = W.to_f32(W.rbf(m_sample, n_sample, seed=0))
+    del A32
+    t0 = time.perf_counter()
+    out = iterative_cur(A64, tol, b, kind=1, seed=0)
+    dt = time.perf_counter() - t0
+    scale = (m_full * n_full) / float(m_sample * n_sample)
+    return {"value": dt * scale, "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": ("FP64 NumPy oracle on the %dx%d RBF matrix of the same recipe (tol %g, b %d, "
+                       "sparse-sign): %.2f s measured, rank %d, rho %.2e; extrapolated x%.0f by the "
+                       "O(mn) sketch cost to %dx%d" % (m_sample, n_sample, tol, b, dt, out["rank"],
+                                                       out["rho"], scale, m_full, n_full)),
+            "sample_seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--form", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--size", type=int, default=40000)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path (requested %d)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_21963_amd import icur
+    from paper_2509_21963_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    icur.load()
+    m = n = a.size
+    tol, b, kind, zeta = 1e-4, 100, icur.SPARSE_SIGN, 8
+    precision = icur.FP32 if a.form == "fp32" else icur.BF16_SPLIT
+    print("generating RBF %dx%d on the device" % (m, n), file=sys.stderr, flush=True)
+    A = W.rbf_torch(m, n, seed=0)
+    torch.cuda.synchronize()
+
+    results = []
+    for i in range(a.warmup):
+        icur.run(A, tol, b, kind, seed=i, precision=precision, zeta=zeta)
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    times, sketch_ms = [], []
+    t_all = time.perf_counter()
+    for i in range(a.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = icur.run(A, tol, b, kind, seed=i, precision=precision, zeta=zeta)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        sketch_ms.append(out["info"]["ms_sketch_product"])
+        results.append(out)
+        print("step %d: %.2f ms, rank %d, rho %.3e, %d iterations" % (
+            i, times[-1] * 1e3, out["rank"], out["rho"], out["info"]["iterations"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_all
+    value = sum(times) / len(times)
+    last = results[-1]
+    # roofline of the sketch product: algorithmic bytes = read A once (4 m n), read the
+    # dense BF16 G (2 c m), write X0 in FP64 (8 c n)
+    c = (11 * b) // 10
+    alg_bytes = 4.0 * m * n + 2.0 * c * m + 8.0 * c * n
+    avg_ms = statistics.mean(sketch_ms)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    traffic = measured_traffic("rbf%d" % m)
+    info = last["info"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": value * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "RBF kernel matrix %dx%d FP32 (h=0.5, x,y ~ U[0,1]^3 seed 0), tol %g, block %d, "
+                        "sparse-sign sketch zeta=%d, %s form" % (m, n, tol, b, zeta, a.form),
+            "m": m, "n": n, "tol": tol, "block": b, "sketch_rows": c, "sketch": "sparse-sign",
+            "zeta": zeta, "form": a.form, "rank": last["rank"], "rho": last["rho"],
+            "iterations": info["iterations"], "timed_wall_s": wall,
+            "phase_ms": {"sketch": info["ms_sketch"], "select": info["ms_select"],
+                         "residual": info["ms_residual"], "core": info["ms_core"],
+                         "total_host": info["ms_total"]},
+        },
+        "roofline": {
+            "kernel": "sketch product G A (wide_kernel, BF16 pieces, FP64 output)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "avg_ms": avg_ms, "algorithmic_bytes": alg_bytes,
+        },
+    }
+    if not a.no_cpu:
+        print("timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(m_full=m, n_full=n)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

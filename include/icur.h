@@ -1,0 +1,216 @@
+/*
+ * libicur: IterativeCUR on one MI355X (gfx950).
+ *
+ * IterativeCUR (Pritchard, Park, Nakatsukasa, Martinsson, "Fast Rank Adaptive CUR via a
+ * Recycled Small Sketch", arXiv 2509.21963) builds A ~ C U R with C = A(:,J), R = A(I,:),
+ * U = A(I,J)^+ by adding b columns and b rows per iteration until the sketched relative
+ * residual rho = ||G (A - C U R)||_F / ||G A||_F falls to the tolerance (Alg. 1; notation
+ * of §1.1; estimator of §3.3).  G is a c x m random sketch, c = floor(1.1 b), drawn once
+ * and recycled in every iteration.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major with 0-based indices.  A "device" pointer is memory the
+ *     caller allocated on the current HIP device (hipMalloc or a torch CUDA tensor);
+ *     a "host" pointer is ordinary CPU memory.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   - Calls are synchronous: they return after every output has been written (host
+ *     outputs copied back, device outputs complete on `stream`).
+ *   - Return value: ICUR_OK (0), a positive warning (outputs valid) or a negative error.
+ *     Arguments are validated before any device work; on an argument error nothing is
+ *     written.  icur_last_error() returns a message describing the last failure of the
+ *     calling thread.
+ *   - The library keeps a per-device workspace cache between calls; icur_release()
+ *     frees it.  Calls on one device from several host threads are serialised
+ *     internally.
+ */
+#ifndef ICUR_H
+#define ICUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum icur_status {
+  ICUR_OK = 0,
+  ICUR_MAXRANK = 1,          /* |J| reached max_rank with rho > tolerance; outputs valid */
+  ICUR_STALLED = 2,          /* a block selected no index (exactly-zero residual pivots) */
+  ICUR_ERR_ARG = -1,         /* invalid argument */
+  ICUR_ERR_NONFINITE = -2,   /* ||G A||_F is not finite (A holds Inf/NaN) */
+  ICUR_ERR_NOMEM = -3,       /* device allocation failed */
+  ICUR_ERR_HIP = -4,         /* a HIP runtime call failed, or a kernel reported a fault */
+  ICUR_ERR_UNSUPPORTED = -5  /* shape outside what the kernels support (see each call) */
+};
+
+enum icur_sketch_kind {
+  ICUR_SKETCH_GAUSSIAN = 0,    /* N(0,1) entries rounded to BF16 (§3.4: Gaussian) */
+  ICUR_SKETCH_SPARSE_SIGN = 1  /* zeta entries +-1 per column of G (§2.1, §3.4) */
+};
+
+enum icur_precision {
+  ICUR_FP32 = 0,       /* plain form: FP32 products and accumulation */
+  ICUR_BF16_SPLIT = 1  /* BF16 matrix-core products of split hi/lo pieces, FP32 accumulate */
+};
+
+typedef struct icur_opts {
+  int32_t precision;    /* icur_precision; default ICUR_FP32 */
+  int32_t zeta;         /* nonzeros per column of a sparse-sign G; 0 -> 8 (clamped to c) */
+  int64_t max_rank;     /* cap on |J|; 0 -> min(m, n) */
+  void*   stream;       /* hipStream_t or NULL */
+  double  alpha;        /* risk-aware stopping (§3.3, Corollary): 0 = off, else in (0,1) */
+  double  delta;        /* allowed deviation, >= 0 (used when alpha > 0) */
+  int32_t split_terms;  /* BF16_SPLIT only: pieces per FP32 operand, 0 = from tol, 1..3 */
+  int32_t sketch_fp32;  /* FP32 form only: 1 = form G A on FP32 matrix cores; 0 (default) =
+                           exact products of three BF16 pieces of A with the BF16-valued G */
+  int32_t residual_fp64; /* residual-form factors in FP64 on FP64 matrix cores: 0 = when
+                            tol < 1e-5 (default), 1 = always, -1 = never */
+  int32_t reserved;      /* must be 0 */
+} icur_opts;
+
+/* Per-call statistics of the calling thread's last icur_run*/
+typedef struct icur_info {
+  int32_t iterations;
+  int32_t split_terms;        /* BF16 pieces used (0 in the FP32 form) */
+  double  sketch_norm;        /* ||G A||_F */
+  double  threshold;          /* tolerance actually applied (xi * tol) */
+  double  ms_total;           /* wall time of the call, host clock */
+  double  ms_sketch;          /* G generation + G A + its norm (device events) */
+  double  ms_select;          /* both LUPP selections, all iterations */
+  double  ms_residual;        /* gathers, N_k^-1 and the residual-form products */
+  double  ms_core;            /* FP64 assembly of U = A(I,J)^-1 after the loop */
+  double  ms_sketch_product;  /* the G A product kernel(s) alone (device events) */
+  int32_t n_rho;              /* entries written to rho[] (<= 512) */
+  int32_t pad;
+  double  rho[512];           /* rho after each iteration */
+} icur_info;
+
+/*
+ * icur_run: Alg. 1 on a dense FP32 matrix.
+ *   A        device, m x n, row-major, leading dimension lda >= n; read only.
+ *   tol      finite, > 0: stop when rho <= tol (times xi when opts->alpha > 0).
+ *   block    b, 1 <= b <= min(m, n); c = (11 b) / 10 sketch rows, c <= 4096.
+ *   sketch_kind, seed: G of icur_sketch_kind drawn from Philox4x32-10 keyed by seed.
+ *   opts     may be NULL (all defaults).
+ *   I, J     host, capacity max_rank each: selected row / column indices in selection
+ *            order (block by block, pivot order within a block).
+ *   U        host, capacity max_rank * max_rank doubles: the rank x rank core
+ *            A(I,J)^{-1} (row-major, leading dimension rank), so A ~ A(:,J) U A(I,:).
+ *   rank     host: |I| = |J|.
+ *   est_err  host: the final rho.
+ * Returns ICUR_OK, ICUR_MAXRANK, ICUR_STALLED or an error.  A zero matrix returns
+ * ICUR_OK with rank 0 and est_err 0.
+ */
+int icur_run(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int32_t block,
+             int32_t sketch_kind, uint64_t seed, const icur_opts* opts, int64_t* I,
+             int64_t* J, double* U, int64_t* rank, double* est_err);
+
+/* Statistics of the calling thread's most recent icur_run (copied into *info). */
+int icur_last_info(icur_info* info);
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* icur_last_error(void);
+
+/* Free the calling process's cached device workspaces (all devices). */
+int icur_release(void);
+
+/* ------------------------------------------------------------------------------------
+ * Step entry points.  Each runs one step of Alg. 1 on caller-provided device buffers;
+ * icur_run is built from the same kernels.
+ * ---------------------------------------------------------------------------------- */
+
+/*
+ * icur_make_sketch: the recycled sketch operator G (c x m) of Alg. 1 ("Generate a sketch
+ * matrix"; G is c x m, see §1.1).  Entry G[r][i] is defined from Philox4x32-10 with
+ * counter (lo32(i), hi32(i), r, 0x47415553) and key (lo32(seed), hi32(seed)): Box-Muller
+ * on the two 53-bit uniforms of the block, rounded FP64 -> FP32 -> BF16.  For the
+ * sparse-sign kind, column i holds min(zeta, c) entries +-1 at distinct rows chosen by
+ * Floyd's algorithm from counters (lo32(i), hi32(i), t, 0x53505253).
+ *   G_bf16   device, c x m uint16 BF16 bit patterns (dense, zeros included), or NULL.
+ *   rows     device, m x min(zeta,c) uint8 row indices (sparse-sign only), or NULL.
+ *   signs    device, m uint8 sign bit masks, bit t set = entry t is -1 (sparse-sign
+ *            only), or NULL.
+ * c <= 255 for the sparse-sign kind.
+ */
+int icur_make_sketch(uint64_t seed, int64_t c, int64_t m, int32_t sketch_kind, int32_t zeta,
+                     uint16_t* G_bf16, uint8_t* rows, uint8_t* signs, void* stream);
+
+/*
+ * icur_sketch: X0 = G A (Alg. 1, initial sketch S_0^col; §3.4 cost item 4) and
+ * ||X0||_F^2 accumulated in FP64.
+ *   G_bf16   device, c x m BF16 bit patterns (from icur_make_sketch).
+ *   A        device, m x n, lda >= n.
+ *   terms    0: FP32 matrix-core products (plain form); 1..3: A split into that many
+ *            BF16 pieces on BF16 matrix cores (3 pieces reproduce every FP32 product).
+ *   X0       device, c x n FP32 output, leading dimension n.
+ *   normsq   host, may be NULL: ||X0||_F^2.
+ */
+int icur_sketch(const uint16_t* G_bf16, int64_t c, const float* A, int64_t m, int64_t n,
+                int64_t lda, int32_t terms, float* X0, double* normsq, void* stream);
+
+/*
+ * icur_lupp: pivot order of LU with partial pivoting (§3.2.1 column selection, §3.2.2
+ * row selection) applied to T = X^T, an N x K matrix whose rows are the candidates.
+ *   X        device, K x N FP32, leading dimension ldx >= N: X[t*ldx + i] = T[i][t].
+ *   steps    number of pivots wanted, 1 <= steps <= K.
+ *   excluded device, N bytes (nonzero = candidate not eligible), or NULL.
+ *   piv      device, capacity steps: chosen candidate indices in pivot order.
+ *   npiv     host: number of pivots found (< steps when the candidates run out or the
+ *            best remaining entry is exactly zero).
+ * Arithmetic is FP64 with the textbook right-looking update (product rounded, then
+ * subtracted); ties go to the lowest index.  K <= 4096, N <= 524288.
+ */
+int icur_lupp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
+              const uint8_t* excluded, int64_t* piv, int32_t* npiv, void* stream);
+
+/*
+ * icur_residual: OUT = X - W B (the column residual G A - (G C) U R of Alg. 1 with
+ * W = (G C) U and B = R, and the row residual A(:,J_k)^T - (U A(I,J_k))^T C^T with
+ * W = Y^T and B = C^T), plus ||OUT||_F^2 in FP64.
+ *   X        device, M x N FP32, leading dimension ldx (may equal OUT for in place), or
+ *            NULL for X = 0.
+ *   W        device, M x K FP64, leading dimension ldw.
+ *   B        device, K x N FP32, leading dimension ldb.
+ *   terms    0: FP32 matrix-core products; 1..3: W and B split into that many BF16
+ *            pieces, products of pieces (i, j) with i + j < terms.
+ *   OUT      device, M x N FP32, leading dimension ldo.
+ *   normsq   host, may be NULL.
+ * M <= 4096; K may be 0 (OUT = X).
+ */
+int icur_residual(const float* X, int64_t ldx, const double* W, int64_t ldw, const float* B,
+                  int64_t ldb, int64_t M, int64_t K, int64_t N, int32_t terms, float* OUT,
+                  int64_t ldo, double* normsq, void* stream);
+
+/*
+ * icur_gather: the CUR factor gathers of Alg. 1 (C = A(:,J), R = A(I,:)).
+ *   cols     device, k indices < n, or NULL: Ct[t][i] = A[i][cols[t]] (Ct is k x m,
+ *            leading dimension ldct), i.e. C stored transposed.
+ *   rows     device, k indices < m, or NULL: Rout[t][j] = A[rows[t]][j] (k x n,
+ *            leading dimension ldr).
+ * Exactly one of (cols, Ct) and (rows, Rout) is given.  Indices are not validated on
+ * the device beyond being clamped into range; callers pass indices from icur_lupp.
+ */
+int icur_gather(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
+                const int64_t* rows, int64_t k, float* Ct, int64_t ldct, float* Rout,
+                int64_t ldr, void* stream);
+
+/*
+ * icur_core_update: the core U = A(I,J)^{-1} of Alg. 1 grown by one block through the
+ * block inverse of the residual-recurrence lemma (§4.2): with Y = U A(I,J_k),
+ * N = A(I_k,J_k) - A(I_k,J) Y and Z = A(I_k,J) U,
+ *   U_new = [[U + Y N^-1 Z, -Y N^-1], [-N^-1 Z, N^-1]].
+ * All FP64, device.
+ *   U      r x r on entry (leading dimension ldu >= r + k), (r+k) x (r+k) on exit.
+ *   Y      r x k,  A21 = A(I_k, J) k x r,  A22 = A(I_k, J_k) k x k (all row-major,
+ *          leading dimensions = their column counts).
+ *   rcond  host, may be NULL: 1 / (||N||_1 ||N^-1||_1) of the new block.
+ * Returns ICUR_ERR_ARG when N is exactly singular.  k <= 512.
+ */
+int icur_core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y,
+                     const double* A21, const double* A22, double* rcond, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ICUR_H */

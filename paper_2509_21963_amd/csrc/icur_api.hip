@@ -1,0 +1,772 @@
+// The C-ABI of libicur: argument checking, the per-device workspace cache and the host
+// driver of Alg. 1 (IterativeCUR).  Every step of the loop runs in the kernels of the
+// other translation units; the host only orders launches, reads back three scalars per
+// iteration (two pivot counts and the residual norm) and decides when to stop.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "icur_internal.h"
+
+namespace icur {
+
+// ----------------------------------------------------------------- errors and info
+namespace {
+thread_local std::string t_error;
+thread_local icur_info t_info;
+}  // namespace
+
+void set_error(const std::string& msg) { t_error = msg; }
+const char* last_error() { return t_error.c_str(); }
+
+int device_info(DeviceInfo* out) {
+  static std::mutex mu;
+  static std::map<int, int> cus;
+  int dev = 0;
+  ICUR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cus.find(dev);
+  if (it == cus.end()) {
+    int n = 0;
+    ICUR_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    it = cus.emplace(dev, n).first;
+  }
+  out->device = dev;
+  out->num_cus = it->second;
+  return ICUR_OK;
+}
+
+// ----------------------------------------------------------------- workspace cache
+namespace {
+
+enum Slot {
+  kG, kRowsPat, kSignsPat, kX0, kS, kSrow, kCt, kR, kU, kY, kA12, kA21, kA22, kYt, kX0J, kW64,
+  kWp, kColMask, kRowMask, kJk, kIk, kJall, kIall, kLupp, kGemmWs, kNormPart, kScal, kCoreWs,
+  kStepA, kStepB, kNumSlots
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct DeviceCache {
+  std::mutex mu;
+  Buf buf[kNumSlots];
+  void* host_pinned = nullptr;  // small staging area for scalar read-backs
+  std::vector<hipEvent_t> events;
+  ~DeviceCache() {}
+};
+
+std::mutex g_cache_mu;
+std::map<int, std::unique_ptr<DeviceCache>> g_cache;
+
+DeviceCache& cache_for(int dev) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto& p = g_cache[dev];
+  if (!p) p.reset(new DeviceCache());
+  return *p;
+}
+
+int ensure(DeviceCache& dc, int slot, size_t bytes, void** out) {
+  Buf& b = dc.buf[slot];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes < bytes) {
+    if (b.p) ICUR_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    const size_t want = (bytes + 4095) & ~size_t(4095);
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      set_error("device allocation of " + std::to_string(want) + " bytes failed");
+      return ICUR_ERR_NOMEM;
+    }
+    b.bytes = want;
+  }
+  *out = b.p;
+  return ICUR_OK;
+}
+
+// Grow a slot, keeping a 2D region: rows x row_bytes from (old, old_ld_bytes) to
+// (new, new_ld_bytes).
+int grow_keep(DeviceCache& dc, int slot, size_t bytes, int64_t rows, size_t row_bytes,
+              size_t old_ld_bytes, size_t new_ld_bytes, hipStream_t st, void** out) {
+  Buf& b = dc.buf[slot];
+  const bool keep = rows > 0 && row_bytes > 0;
+  if (b.bytes >= bytes && (!keep || old_ld_bytes == new_ld_bytes)) {
+    *out = b.p;
+    return ICUR_OK;
+  }
+  void* np = nullptr;
+  const size_t want = (bytes + 4095) & ~size_t(4095);
+  if (hipMalloc(&np, want) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of " + std::to_string(want) + " bytes failed");
+    return ICUR_ERR_NOMEM;
+  }
+  if (b.p && keep)
+    ICUR_HIP(hipMemcpy2DAsync(np, new_ld_bytes, b.p, old_ld_bytes, row_bytes, rows,
+                              hipMemcpyDeviceToDevice, st));
+  ICUR_HIP(hipStreamSynchronize(st));
+  if (b.p) ICUR_HIP(hipFree(b.p));
+  b.p = np;
+  b.bytes = want;
+  *out = np;
+  return ICUR_OK;
+}
+
+// Device scalars read back once per iteration.
+struct Scal {
+  double normsq_x0;
+  double normsq_s;
+  double norms[2];
+  int info;
+  int pad;
+};
+
+struct Timer {
+  DeviceCache* dc;
+  hipStream_t st;
+  size_t used = 0;
+  std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;
+  int mark(size_t* idx) {
+    if (used == dc->events.size()) {
+      hipEvent_t e;
+      ICUR_HIP(hipEventCreate(&e));
+      dc->events.push_back(e);
+    }
+    ICUR_HIP(hipEventRecord(dc->events[used], st));
+    *idx = used++;
+    return ICUR_OK;
+  }
+  float ms(size_t a, size_t b) {
+    float v = 0.f;
+    if (hipEventElapsedTime(&v, dc->events[a], dc->events[b]) != hipSuccess) {
+      (void)hipGetLastError();
+      v = 0.f;
+    }
+    return v;
+  }
+};
+
+int read_scal(DeviceCache& dc, const Scal* dev, Scal* host, hipStream_t st) {
+  Scal* pin = static_cast<Scal*>(dc.host_pinned);
+  ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(Scal), hipMemcpyDeviceToHost, st));
+  ICUR_HIP(hipStreamSynchronize(st));
+  *host = *pin;
+  return ICUR_OK;
+}
+
+int read_int(DeviceCache& dc, const int* dev, int* host, int count, hipStream_t st) {
+  int* pin = reinterpret_cast<int*>(static_cast<char*>(dc.host_pinned) + 256);
+  ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+  ICUR_HIP(hipStreamSynchronize(st));
+  std::memcpy(host, pin, sizeof(int) * count);
+  return ICUR_OK;
+}
+
+int prepare_device(DeviceCache** out) {
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  DeviceCache& dc = cache_for(dev.device);
+  if (!dc.host_pinned) ICUR_HIP(hipHostMalloc(&dc.host_pinned, 4096, hipHostMallocDefault));
+  *out = &dc;
+  return ICUR_OK;
+}
+
+// BF16 pieces per FP32 operand for a tolerance.  One piece rounds with relative error
+// up to 2^-8, two with 2^-16, three reproduce FP32.  The sketched residual's noise
+// floor is this error amplified by the interpolation coefficients of the cross, so the
+// count leaves a wide margin: one piece only for very loose tolerances.
+constexpr double kResidualFp64Below = 1e-5;
+
+int terms_for_tol(double tol) {
+  if (tol >= 1e-1) return 1;
+  if (tol >= 5e-4) return 2;
+  return 3;
+}
+
+double risk_factor(double alpha, double delta, int64_t c, int* status) {
+  *status = ICUR_OK;
+  if (alpha == 0.0) return 1.0;
+  if (!(alpha > 0.0 && alpha < 1.0) || !(delta >= 0.0) || !std::isfinite(delta)) {
+    *status = arg_error("risk-aware stopping needs 0 < alpha < 1 and delta >= 0");
+    return 1.0;
+  }
+  if (!(static_cast<double>(c) > -4.0 * std::log(alpha))) {
+    *status = arg_error("risk-aware stopping needs c > -4 ln(alpha)");
+    return 1.0;
+  }
+  return (1.0 + delta) * std::sqrt(1.0 - 2.0 * std::sqrt(-std::log(alpha) / static_cast<double>(c)));
+}
+
+// --------------------------------------------------------------------- the driver
+int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int32_t block,
+             int32_t kind, uint64_t seed, const icur_opts* opts, int64_t* I_out, int64_t* J_out,
+             double* U_out, int64_t* rank_out, double* est_out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  std::memset(&t_info, 0, sizeof(t_info));
+  // ---- arguments (before any device work)
+  if (!A) return arg_error("A is null");
+  if (m < 1 || n < 1) return arg_error("need m >= 1 and n >= 1");
+  if (lda < n) return arg_error("need lda >= n");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error("tol must be finite and > 0");
+  if (block < 1 || block > std::min(m, n)) return arg_error("need 1 <= block <= min(m, n)");
+  if (kind != ICUR_SKETCH_GAUSSIAN && kind != ICUR_SKETCH_SPARSE_SIGN)
+    return arg_error("unknown sketch kind");
+  if (!I_out || !J_out || !U_out || !rank_out || !est_out) return arg_error("null output pointer");
+  if (m > 0x7fffffffLL || n > 0x7fffffffLL) return arg_error("m and n must be below 2^31");
+  icur_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  const int64_t b = block;
+  const int64_t c = (11 * b) / 10;
+  if (c > 4096) return arg_error("sketch rows c = floor(1.1 b) above 4096 are not supported");
+  if (b > 1024) return arg_error("block above 1024 is not supported");
+  if (kind == ICUR_SKETCH_SPARSE_SIGN && c > 255) return arg_error("sparse-sign sketch needs c <= 255");
+  const int zeta = o.zeta > 0 ? o.zeta : 8;
+  if (zeta > 8) return arg_error("zeta must be at most 8");
+  if (o.precision != ICUR_FP32 && o.precision != ICUR_BF16_SPLIT) return arg_error("unknown precision");
+  if (o.split_terms < 0 || o.split_terms > 3) return arg_error("split_terms must be 0..3");
+  if (o.residual_fp64 < -1 || o.residual_fp64 > 1) return arg_error("residual_fp64 must be -1, 0 or 1");
+  if (o.max_rank < 0) return arg_error("max_rank must be >= 0");
+  const int64_t rmax = (o.max_rank == 0) ? std::min(m, n) : std::min(o.max_rank, std::min(m, n));
+  int st_risk = ICUR_OK;
+  const double xi = risk_factor(o.alpha, o.delta, c, &st_risk);
+  if (st_risk != ICUR_OK) return st_risk;
+  const double thr = xi * tol;
+  const bool split = (o.precision == ICUR_BF16_SPLIT);
+  const int T = split ? (o.split_terms ? o.split_terms : terms_for_tol(tol)) : 0;
+  // sketch pieces: the plain form forms every product exactly (three pieces of A times a
+  // BF16-exact G) unless FP32 matrix cores are asked for
+  const int sketch_terms = split ? T : (o.sketch_fp32 ? 0 : 3);
+  // Residual factors: FP64 on the FP64 matrix cores for tight tolerances (FP32 rounding
+  // of the residual-form factors leaves a floor near 1e-6 on ill-conditioned crosses),
+  // else FP32 (plain form) or BF16 pieces (split form).
+  const bool res64 = o.residual_fp64 > 0 || (o.residual_fp64 == 0 && tol < kResidualFp64Below);
+  const size_t fsz = res64 ? 8 : 4;
+  hipStream_t st = as_stream(o.stream);
+
+  DeviceCache* dcp = nullptr;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  Timer tm{&dc, st};
+
+  // ---- fixed-size buffers
+  void *pG, *pX0, *pSr, *pColMask, *pRowMask, *pJk, *pIk, *pLupp, *pGemm, *pNorm, *pScal, *pN;
+  ICUR_TRY(ensure(dc, kG, static_cast<size_t>(c) * m * 2, &pG));
+  ICUR_TRY(ensure(dc, kX0, static_cast<size_t>(c) * n * 8, &pX0));
+  ICUR_TRY(ensure(dc, kSrow, static_cast<size_t>(b) * n * fsz, &pSr));
+  ICUR_TRY(ensure(dc, kColMask, static_cast<size_t>(n), &pColMask));
+  ICUR_TRY(ensure(dc, kRowMask, static_cast<size_t>(m), &pRowMask));
+  ICUR_TRY(ensure(dc, kJk, static_cast<size_t>(b) * 8, &pJk));
+  ICUR_TRY(ensure(dc, kIk, static_cast<size_t>(b) * 8, &pIk));
+  ICUR_TRY(ensure(dc, kA22, static_cast<size_t>(b) * b * 8 + small_inverse_work_bytes(b), &pN));
+  ICUR_TRY(ensure(dc, kLupp, lupp_workspace_bytes(b, std::max(m, n)), &pLupp));
+  const int64_t BIGK = int64_t(1) << 40;
+  size_t gemm_ws = wide_gemm_workspace_bytes(c, m, n, dev.num_cus);
+  gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(c, BIGK, n, dev.num_cus));
+  gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(b, BIGK, m, dev.num_cus));
+  gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(b, BIGK, n, dev.num_cus));
+  ICUR_TRY(ensure(dc, kGemmWs, gemm_ws, &pGemm));
+  const int nparts_cap = std::max(max_norm_partials(c, n), max_norm_partials(b, m));
+  ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(nparts_cap) * 8, &pNorm));
+  ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  LuppWork lw;
+  lupp_bind_workspace(pLupp, b, std::max(m, n), &lw);
+  Scal* dscal = static_cast<Scal*>(pScal);
+  double* dnorm = static_cast<double*>(pNorm);
+  double* Nblk = static_cast<double*>(pN);                 // b x b, then its inverse
+  double* Nwork = Nblk + static_cast<size_t>(b) * b;       // Gauss-Jordan work (b > 128)
+  const int64_t bc = std::max(b, c);
+
+  // ---- rank-sized buffers, grown geometrically: the residual-form factors
+  //   LcT (r x m): column factors, row t = S^{(k-1)}(:, J_k[t])^T  (S^row of its block)
+  //   Ur  (r x n): row factors, block k = N_k^{-1} S^{(k-1)}(I_k, :)
+  // with A - C U R = A - sum_k Lc_k Ur_k (the residual-recurrence lemma of §4.2).
+  int64_t rcap = 0;
+  void *pLcT = nullptr, *pUr = nullptr, *pJall = nullptr, *pIall = nullptr, *pW64 = nullptr, *pWp = nullptr;
+  auto grow_to = [&](int64_t need) -> int {
+    if (need <= rcap) return ICUR_OK;
+    int64_t nc = std::max<int64_t>(std::max<int64_t>(rcap * 2, need), std::min<int64_t>(rmax, std::max<int64_t>(4 * b, 512)));
+    nc = std::min(nc, rmax);
+    if (nc < need) nc = need;
+    const int64_t keep = rcap;
+    ICUR_TRY(grow_keep(dc, kCt, static_cast<size_t>(nc) * m * fsz, keep, static_cast<size_t>(m) * fsz,
+                       static_cast<size_t>(m) * fsz, static_cast<size_t>(m) * fsz, st, &pLcT));
+    ICUR_TRY(grow_keep(dc, kR, static_cast<size_t>(nc) * n * fsz, keep, static_cast<size_t>(n) * fsz,
+                       static_cast<size_t>(n) * fsz, static_cast<size_t>(n) * fsz, st, &pUr));
+    ICUR_TRY(grow_keep(dc, kJall, static_cast<size_t>(nc) * 8, 1, static_cast<size_t>(keep) * 8,
+                       static_cast<size_t>(keep) * 8 + 8, static_cast<size_t>(nc) * 8 + 8, st, &pJall));
+    ICUR_TRY(grow_keep(dc, kIall, static_cast<size_t>(nc) * 8, 1, static_cast<size_t>(keep) * 8,
+                       static_cast<size_t>(keep) * 8 + 8, static_cast<size_t>(nc) * 8 + 8, st, &pIall));
+    ICUR_TRY(ensure(dc, kW64, static_cast<size_t>(bc) * std::max(nc, b) * 8, &pW64));
+    ICUR_TRY(ensure(dc, kWp, static_cast<size_t>(bc) * std::max(nc, b) * 6, &pWp));
+    rcap = nc;
+    return ICUR_OK;
+  };
+  // OUT = X - W B (subtract) or W B, W given in FP64 (rows x K, ld K) and split here;
+  // X and OUT are FP64 when out64.
+  auto product = [&](const double* W64, int64_t M, int64_t K, const void* X, int64_t ldx, const void* B,
+                     int64_t ldb, int64_t N, bool subtract, void* OUT, int64_t ldo, bool norm, bool out64,
+                     int* parts) -> int {
+    // res64: W and B are FP64 and OUT is FP64 (FP64 matrix cores); else W is split into
+    // BF16 pieces (or rounded to FP32) and B is FP32.
+    if (K > 0 && !res64) ICUR_TRY(launch_split_f64(W64, M, K, K, false, T, pWp, K, M * K, st));
+    WideGemm g{};
+    g.X = X;
+    g.ldx = ldx;
+    g.W = res64 ? static_cast<const void*>(W64) : pWp;
+    g.ldw = K;
+    g.wterms = res64 ? -1 : T;
+    g.B = B;
+    g.ldb = ldb;
+    g.bterms = res64 ? -1 : T;
+    g.M = M;
+    g.K = K;
+    g.N = N;
+    g.subtract = subtract;
+    g.out64 = out64 || res64;
+    g.OUT = OUT;
+    g.ldo = ldo;
+    g.norm_partials = norm ? dnorm : nullptr;
+    g.nparts = parts;
+    return wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st);
+  };
+
+  // ---- sketch: G, X0 = G A, ||X0||_F^2
+  size_t ev_s0, ev_s1, ev_p0, ev_p1;
+  ICUR_TRY(tm.mark(&ev_s0));
+  uint16_t* G = static_cast<uint16_t*>(pG);
+  if (kind == ICUR_SKETCH_GAUSSIAN)
+    ICUR_TRY(launch_gaussian_G(seed, c, m, G, st));
+  else
+    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, st));
+  double* S = static_cast<double*>(pX0);  // X0, then the sketched column residual in place (FP64)
+  {
+    WideGemm g{};
+    g.W = G;
+    g.ldw = m;
+    g.wterms = sketch_terms == 0 ? 0 : 1;
+    g.w_bf16 = true;
+    g.B = A;
+    g.ldb = lda;
+    g.bterms = sketch_terms;
+    g.M = c;
+    g.K = m;
+    g.N = n;
+    g.subtract = false;
+    g.out64 = true;
+    g.OUT = S;
+    g.ldo = n;
+    g.norm_partials = dnorm;
+    int parts = 0;
+    g.nparts = &parts;
+    ICUR_TRY(tm.mark(&ev_p0));
+    ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+    ICUR_TRY(tm.mark(&ev_p1));
+    ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
+  }
+  ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pColMask), n, 0, st));
+  ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pRowMask), m, 0, st));
+  ICUR_TRY(tm.mark(&ev_s1));
+  Scal hs;
+  ICUR_TRY(read_scal(dc, dscal, &hs, st));
+  const double gnorm2 = hs.normsq_x0;
+  t_info.sketch_norm = std::sqrt(gnorm2);
+  t_info.threshold = thr;
+  t_info.split_terms = T;
+  t_info.ms_sketch = tm.ms(ev_s0, ev_s1);
+  t_info.ms_sketch_product = tm.ms(ev_p0, ev_p1);
+  if (!std::isfinite(gnorm2)) {
+    set_error("||G A||_F is not finite: A holds Inf or NaN");
+    return ICUR_ERR_NONFINITE;
+  }
+  if (gnorm2 == 0.0) {
+    *rank_out = 0;
+    *est_out = 0.0;
+    t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return ICUR_OK;
+  }
+
+  // ---- the loop of Alg. 1, residual form
+  int64_t r = 0;
+  double rho = 1.0;
+  int status = ICUR_OK;
+  int64_t* Jk = static_cast<int64_t*>(pJk);
+  int64_t* Ik = static_cast<int64_t*>(pIk);
+  std::vector<int64_t> blocks;
+  // factor element access: FP32 or FP64 storage
+  auto fp = [&](void* base, int64_t elems) -> void* { return static_cast<char*>(base) + elems * fsz; };
+  auto gather_w = [&](const void* src, int64_t lds, int64_t rk, const int64_t* cols, int64_t ck, bool trans,
+                      double* dst, int64_t ldd) -> int {
+    return res64 ? launch_gather_f64(static_cast<const double*>(src), lds, nullptr, rk, cols, ck, trans, dst, ldd, st)
+                 : launch_gather_f64(static_cast<const float*>(src), lds, nullptr, rk, cols, ck, trans, dst, ldd, st);
+  };
+  while (rho > thr && r < rmax) {
+    const int64_t s = std::min(b, rmax - r);
+    ICUR_TRY(grow_to(r + s));
+    void* LcT = pLcT;
+    void* Ur = pUr;
+    void* Sr = pSr;
+    double* W64 = static_cast<double*>(pW64);
+    size_t e0, e1, e2, e3, e4;
+    int parts = 0;
+    ICUR_TRY(tm.mark(&e0));
+    // column selection: LUPP on (S^col)^T
+    ICUR_TRY(lupp_launch(S, true, c, n, n, static_cast<int>(s), static_cast<const uint8_t*>(pColMask), Jk, lw, st));
+    int lst[2];
+    ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
+    if (lst[1]) {
+      set_error("selection kernel: grid barrier did not complete");
+      return ICUR_ERR_HIP;
+    }
+    const int64_t nJ = lst[0];
+    ICUR_TRY(tm.mark(&e1));
+    if (nJ == 0) {
+      status = ICUR_STALLED;
+      break;
+    }
+    // row residual S^row = A(:,J_k) - C U R(:,J_k) = A(:,J_k) - Lc Ur(:,J_k), stored
+    // transposed as the next rows of LcT
+    void* Lk = fp(LcT, r * m);
+    if (res64)
+      ICUR_TRY(launch_gather_cols_T(A, m, n, lda, Jk, nJ, static_cast<double*>(Lk), m, st));
+    else
+      ICUR_TRY(launch_gather_cols_T(A, m, n, lda, Jk, nJ, static_cast<float*>(Lk), m, st));
+    if (r > 0) {
+      ICUR_TRY(gather_w(Ur, n, r, Jk, nJ, true, W64, r));   // Ur(:,J_k)^T
+      ICUR_TRY(product(W64, nJ, r, Lk, m, LcT, m, m, true, Lk, m, false, false, &parts));
+    }
+    ICUR_TRY(tm.mark(&e2));
+    // row selection: LUPP on S^row
+    ICUR_TRY(lupp_launch(Lk, res64, nJ, m, m, static_cast<int>(nJ), static_cast<const uint8_t*>(pRowMask), Ik, lw, st));
+    ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
+    if (lst[1]) {
+      set_error("selection kernel: grid barrier did not complete");
+      return ICUR_ERR_HIP;
+    }
+    const int64_t nI = lst[0];
+    ICUR_TRY(tm.mark(&e3));
+    if (nI == 0) {
+      status = ICUR_STALLED;
+      break;
+    }
+    // N_k = S^{(k-1)}(I_k, J_k) and its inverse (FP64)
+    ICUR_TRY(gather_w(Lk, m, nI, Ik, nI, true, Nblk, nI));
+    ICUR_TRY(launch_small_inverse(Nblk, nI, Nwork, &dscal->info, dscal->norms, st));
+    // residual at the new rows: Sr = A(I_k,:) - Lc(I_k,:) Ur
+    if (res64)
+      ICUR_TRY(launch_gather_rows(A, m, n, lda, Ik, nI, static_cast<double*>(Sr), n, st));
+    else
+      ICUR_TRY(launch_gather_rows(A, m, n, lda, Ik, nI, static_cast<float*>(Sr), n, st));
+    if (r > 0) {
+      ICUR_TRY(gather_w(LcT, m, r, Ik, nI, true, W64, r));  // Lc(I_k,:)
+      ICUR_TRY(product(W64, nI, r, Sr, n, Ur, n, n, true, Sr, n, false, false, &parts));
+    }
+    // new row factors Ur_k = N_k^{-1} Sr
+    void* Urk = fp(Ur, r * n);
+    ICUR_TRY(product(Nblk, nI, nI, nullptr, n, Sr, n, n, false, Urk, n, false, false, &parts));
+    // column residual update S^col <- S^col - S^col(:,J_k) Ur_k, and its norm
+    ICUR_TRY(launch_gather_f64(S, n, nullptr, c, Jk, nI, false, W64, nI, st));
+    ICUR_TRY(product(W64, c, nI, S, n, Urk, n, n, true, S, n, true, true, &parts));
+    ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_s, st));
+    ICUR_TRY(launch_set_mask(static_cast<uint8_t*>(pColMask), Jk, nI, st));
+    ICUR_TRY(launch_set_mask(static_cast<uint8_t*>(pRowMask), Ik, nI, st));
+    ICUR_HIP(hipMemcpyAsync(static_cast<int64_t*>(pJall) + r, Jk, nI * 8, hipMemcpyDeviceToDevice, st));
+    ICUR_HIP(hipMemcpyAsync(static_cast<int64_t*>(pIall) + r, Ik, nI * 8, hipMemcpyDeviceToDevice, st));
+    ICUR_TRY(tm.mark(&e4));
+    ICUR_TRY(read_scal(dc, dscal, &hs, st));
+    if (hs.info != 0) {
+      set_error("the residual block N_k = S(I_k, J_k) is exactly singular");
+      return ICUR_ERR_HIP;
+    }
+    r += nI;
+    blocks.push_back(nI);
+    rho = std::sqrt(hs.normsq_s / gnorm2);
+    const int it = t_info.iterations++;
+    if (it < 512) t_info.rho[it] = rho;
+    t_info.n_rho = std::min(t_info.iterations, 512);
+    t_info.ms_select += tm.ms(e0, e1) + tm.ms(e2, e3);
+    t_info.ms_residual += tm.ms(e1, e2) + tm.ms(e3, e4);
+    tm.used = ev_s1 + 1;  // recycle the iteration's events
+  }
+  if (status == ICUR_OK && rho > thr) status = ICUR_MAXRANK;
+
+  // ---- the core U = A(I,J)^{-1} in FP64 from the exact cross entries: block LU in the
+  //      selection order (its diagonal blocks are the pivot blocks N_k of the row
+  //      selections), then block triangular solves on the identity
+  if (r > 0) {
+    size_t ec0, ec1;
+    ICUR_TRY(tm.mark(&ec0));
+    void *pU, *pM, *pCore;
+    const int64_t nb = static_cast<int64_t>(blocks.size());
+    ICUR_TRY(ensure(dc, kU, static_cast<size_t>(r) * r * 8, &pU));
+    ICUR_TRY(ensure(dc, kY, static_cast<size_t>(r) * r * 8, &pM));
+    ICUR_TRY(ensure(dc, kCoreWs, core_inverse_ws_doubles(r, b) * 8 + static_cast<size_t>(nb) * 4 + 256, &pCore));
+    double* U = static_cast<double*>(pU);
+    double* M = static_cast<double*>(pM);
+    int* infos = reinterpret_cast<int*>(static_cast<double*>(pCore) + core_inverse_ws_doubles(r, b));
+    ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
+                               false, M, r, st));
+    ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, dscal->norms, st));
+    ICUR_TRY(tm.mark(&ec1));
+    std::vector<int> hinfo(nb);
+    ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+    ICUR_HIP(hipStreamSynchronize(st));
+    for (int v : hinfo)
+      if (v != 0) {
+        set_error("core assembly: a pivot block of A(I,J) is exactly singular");
+        return ICUR_ERR_HIP;
+      }
+    t_info.ms_core = tm.ms(ec0, ec1);
+    ICUR_HIP(hipMemcpyAsync(I_out, pIall, r * 8, hipMemcpyDeviceToHost, st));
+    ICUR_HIP(hipMemcpyAsync(J_out, pJall, r * 8, hipMemcpyDeviceToHost, st));
+    ICUR_HIP(hipMemcpyAsync(U_out, U, r * r * 8, hipMemcpyDeviceToHost, st));
+  }
+  ICUR_HIP(hipStreamSynchronize(st));
+  *rank_out = r;
+  *est_out = rho;
+  t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return status;
+}
+
+}  // namespace
+}  // namespace icur
+
+using namespace icur;
+
+// =========================================================================== C-ABI
+extern "C" {
+
+int icur_run(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int32_t block,
+             int32_t sketch_kind, uint64_t seed, const icur_opts* opts, int64_t* I, int64_t* J,
+             double* U, int64_t* rank, double* est_err) {
+  t_error.clear();
+  return run_impl(A, m, n, lda, tol, block, sketch_kind, seed, opts, I, J, U, rank, est_err);
+}
+
+int icur_last_info(icur_info* info) {
+  if (!info) return ICUR_ERR_ARG;
+  *info = t_info;
+  return ICUR_OK;
+}
+
+const char* icur_last_error(void) { return last_error(); }
+
+int icur_release(void) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  int dev0 = 0;
+  ICUR_HIP(hipGetDevice(&dev0));
+  for (auto& kv : g_cache) {
+    DeviceCache& dc = *kv.second;
+    std::lock_guard<std::mutex> l(dc.mu);
+    ICUR_HIP(hipSetDevice(kv.first));
+    for (auto& b : dc.buf) {
+      if (b.p) ICUR_HIP(hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (dc.host_pinned) ICUR_HIP(hipHostFree(dc.host_pinned));
+    dc.host_pinned = nullptr;
+    for (auto e : dc.events) (void)hipEventDestroy(e);
+    dc.events.clear();
+  }
+  g_cache.clear();
+  ICUR_HIP(hipSetDevice(dev0));
+  return ICUR_OK;
+}
+
+int icur_make_sketch(uint64_t seed, int64_t c, int64_t m, int32_t sketch_kind, int32_t zeta,
+                     uint16_t* G_bf16, uint8_t* rows, uint8_t* signs, void* stream) {
+  t_error.clear();
+  if (c < 1 || m < 1) return arg_error("need c >= 1 and m >= 1");
+  hipStream_t st = as_stream(stream);
+  if (sketch_kind == ICUR_SKETCH_GAUSSIAN) {
+    if (!G_bf16) return arg_error("Gaussian sketch needs G_bf16");
+    ICUR_TRY(launch_gaussian_G(seed, c, m, G_bf16, st));
+  } else if (sketch_kind == ICUR_SKETCH_SPARSE_SIGN) {
+    if (!G_bf16 && !rows && !signs) return arg_error("no output given");
+    if (zeta < 0 || zeta > 8) return arg_error("zeta must be in 0..8");
+    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta > 0 ? zeta : 8, rows, signs, G_bf16, st));
+  } else {
+    return arg_error("unknown sketch kind");
+  }
+  ICUR_HIP(hipStreamSynchronize(st));
+  return ICUR_OK;
+}
+
+int icur_sketch(const uint16_t* G_bf16, int64_t c, const float* A, int64_t m, int64_t n,
+                int64_t lda, int32_t terms, float* X0, double* normsq, void* stream) {
+  t_error.clear();
+  if (!G_bf16 || !A || !X0) return arg_error("null pointer");
+  if (c < 1 || m < 1 || n < 1 || lda < n) return arg_error("invalid shape");
+  if (c > 4096) return arg_error("c above 4096 is not supported");
+  if (terms < 0 || terms > 3) return arg_error("terms must be 0..3");
+  DeviceCache* dcp;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  hipStream_t st = as_stream(stream);
+  void *pGemm, *pNorm, *pScal;
+  ICUR_TRY(ensure(dc, kGemmWs, wide_gemm_workspace_bytes(c, m, n, dev.num_cus), &pGemm));
+  ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(max_norm_partials(c, n)) * 8, &pNorm));
+  ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  WideGemm g{};
+  g.W = G_bf16;
+  g.ldw = m;
+  g.wterms = terms == 0 ? 0 : 1;
+  g.w_bf16 = true;
+  g.B = A;
+  g.ldb = lda;
+  g.bterms = terms;
+  g.M = c;
+  g.K = m;
+  g.N = n;
+  g.subtract = false;
+  g.out64 = false;
+  g.OUT = X0;
+  g.ldo = n;
+  g.norm_partials = static_cast<double*>(pNorm);
+  int parts = 0;
+  g.nparts = &parts;
+  ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+  Scal* ds = static_cast<Scal*>(pScal);
+  ICUR_TRY(launch_reduce_partials(static_cast<double*>(pNorm), parts, &ds->normsq_x0, st));
+  Scal hs;
+  ICUR_TRY(read_scal(dc, ds, &hs, st));
+  if (normsq) *normsq = hs.normsq_x0;
+  return ICUR_OK;
+}
+
+int icur_lupp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
+              const uint8_t* excluded, int64_t* piv, int32_t* npiv, void* stream) {
+  t_error.clear();
+  if (!X || !piv || !npiv) return arg_error("null pointer");
+  if (K < 1 || N < 1 || ldx < N) return arg_error("invalid shape");
+  if (steps < 1 || steps > K) return arg_error("need 1 <= steps <= K");
+  if (K > 4096) return arg_error("K above 4096 is not supported");
+  if (N > 0x7fffffffLL) return arg_error("N must be below 2^31");
+  DeviceCache* dcp;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  hipStream_t st = as_stream(stream);
+  void* pL;
+  ICUR_TRY(ensure(dc, kStepA, lupp_workspace_bytes(steps, N), &pL));
+  LuppWork lw;
+  lupp_bind_workspace(pL, steps, N, &lw);
+  ICUR_TRY(lupp_launch(X, false, K, N, ldx, steps, excluded, piv, lw, st));
+  int lst[2];
+  ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
+  if (lst[1]) {
+    set_error("selection kernel: grid barrier did not complete");
+    return ICUR_ERR_HIP;
+  }
+  *npiv = lst[0];
+  return ICUR_OK;
+}
+
+int icur_residual(const float* X, int64_t ldx, const double* W, int64_t ldw, const float* B,
+                  int64_t ldb, int64_t M, int64_t K, int64_t N, int32_t terms, float* OUT,
+                  int64_t ldo, double* normsq, void* stream) {
+  t_error.clear();
+  if (!OUT || (K > 0 && (!W || !B))) return arg_error("null pointer");
+  if (M < 1 || N < 1 || K < 0) return arg_error("invalid shape");
+  if (M > 4096) return arg_error("M above 4096 is not supported");
+  if (ldo < N || (X && ldx < N) || (K > 0 && (ldw < K || ldb < N))) return arg_error("invalid leading dimension");
+  if (terms < 0 || terms > 3) return arg_error("terms must be 0..3");
+  DeviceCache* dcp;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  hipStream_t st = as_stream(stream);
+  void *pWp, *pGemm, *pNorm, *pScal;
+  const size_t wbytes = static_cast<size_t>(M) * std::max<int64_t>(K, 1) * (terms == 0 ? 4 : 2 * terms);
+  ICUR_TRY(ensure(dc, kStepB, wbytes, &pWp));
+  ICUR_TRY(ensure(dc, kGemmWs, wide_gemm_workspace_bytes(M, K, N, dev.num_cus), &pGemm));
+  ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(max_norm_partials(M, N)) * 8, &pNorm));
+  ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  if (K > 0) ICUR_TRY(launch_split_f64(W, M, K, ldw, false, terms, pWp, K, M * K, st));
+  WideGemm g{};
+  g.X = X;
+  g.ldx = ldx;
+  g.W = pWp;
+  g.ldw = K;
+  g.wterms = terms;
+  g.B = B;
+  g.ldb = ldb;
+  g.bterms = terms;
+  g.M = M;
+  g.K = K;
+  g.N = N;
+  g.subtract = true;
+  g.out64 = false;
+  g.OUT = OUT;
+  g.ldo = ldo;
+  g.norm_partials = static_cast<double*>(pNorm);
+  int parts = 0;
+  g.nparts = &parts;
+  ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+  Scal* ds = static_cast<Scal*>(pScal);
+  ICUR_TRY(launch_reduce_partials(static_cast<double*>(pNorm), parts, &ds->normsq_s, st));
+  Scal hs;
+  ICUR_TRY(read_scal(dc, ds, &hs, st));
+  if (normsq) *normsq = hs.normsq_s;
+  return ICUR_OK;
+}
+
+int icur_gather(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
+                const int64_t* rows, int64_t k, float* Ct, int64_t ldct, float* Rout, int64_t ldr,
+                void* stream) {
+  t_error.clear();
+  if (!A || m < 1 || n < 1 || lda < n || k < 0) return arg_error("invalid matrix");
+  const bool c_given = cols && Ct, r_given = rows && Rout;
+  if (c_given == r_given) return arg_error("give exactly one of (cols, Ct) and (rows, Rout)");
+  hipStream_t st = as_stream(stream);
+  if (c_given) {
+    if (ldct < m) return arg_error("ldct < m");
+    ICUR_TRY(launch_gather_cols_T(A, m, n, lda, cols, k, Ct, ldct, st));
+  } else {
+    if (ldr < n) return arg_error("ldr < n");
+    ICUR_TRY(launch_gather_rows(A, m, n, lda, rows, k, Rout, ldr, st));
+  }
+  ICUR_HIP(hipStreamSynchronize(st));
+  return ICUR_OK;
+}
+
+int icur_core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y,
+                     const double* A21, const double* A22, double* rcond, void* stream) {
+  t_error.clear();
+  if (!U || !A22 || (r > 0 && (!Y || !A21))) return arg_error("null pointer");
+  if (r < 0 || k < 1 || k > 512 || ldu < r + k) return arg_error("invalid shape");
+  DeviceCache* dcp;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  hipStream_t st = as_stream(stream);
+  void *pCore, *pScal;
+  ICUR_TRY(ensure(dc, kStepA, core_update_ws_doubles(r, k) * 8, &pCore));
+  ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  Scal* ds = static_cast<Scal*>(pScal);
+  ICUR_TRY(core_update(U, ldu, r, k, Y, k, A21, A22, static_cast<double*>(pCore), &ds->info, ds->norms, st));
+  Scal hs;
+  ICUR_TRY(read_scal(dc, ds, &hs, st));
+  if (hs.info != 0) return arg_error("the Schur complement block is exactly singular");
+  if (rcond) *rcond = (hs.norms[0] > 0 && hs.norms[1] > 0) ? 1.0 / (hs.norms[0] * hs.norms[1]) : 0.0;
+  return ICUR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,358 @@
+// FP64 kernels for the core U = A(I,J)^{-1} of Alg. 1 and the small products around it.
+//
+// The core is grown block by block with the block inverse used in the proof of the
+// residual-recurrence lemma (§4.2): with the old core A11 = A(I,J) (inverse U known),
+// the new block A12 = A(I,J_k), A21 = A(I_k,J), A22 = A(I_k,J_k), Y = U A12,
+// Z = A21 U and the Schur complement N = A22 - A21 Y (the residual at the new rows and
+// columns),
+//     [A11 A12; A21 A22]^{-1} = [U + Y N^-1 Z, -Y N^-1; -N^-1 Z, N^-1].
+// This costs O(r^2 b) per iteration instead of refactorising the r x r core (the paper
+// notes the update alternative in §3.4).  N^-1 comes from Gauss-Jordan elimination with
+// partial pivoting in one workgroup.
+#include <algorithm>
+
+#include "icur_internal.h"
+
+namespace icur {
+namespace {
+
+constexpr int kTM = 64, kTN = 64, kTK = 16;
+
+// C = alpha A B + beta C, 64x64 tiles, 256 threads each computing a 4x4 block.
+__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                    const double* __restrict__ A, int64_t sa0,
+                                                    int64_t sa1, const double* __restrict__ B,
+                                                    int64_t sb0, int64_t sb1, double beta,
+                                                    double* __restrict__ C, int64_t ldc) {
+  __shared__ double As[kTK][kTM + 1];
+  __shared__ double Bs[kTK][kTN + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.y) * kTM;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * kTN;
+  double acc[4][4] = {};
+  for (int64_t k0 = 0; k0 < K; k0 += kTK) {
+    for (int e = threadIdx.x; e < kTM * kTK; e += 256) {
+      // A tile: choose the mapping that walks A's unit-stride dimension across threads
+      int i, kk;
+      if (sa1 == 1) {
+        i = e / kTK;
+        kk = e % kTK;
+      } else {
+        kk = e / kTM;
+        i = e % kTM;
+      }
+      const int64_t gi = row0 + i, gk = k0 + kk;
+      As[kk][i] = (gi < M && gk < K) ? A[gi * sa0 + gk * sa1] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kTK * kTN; e += 256) {
+      int kk, j;
+      if (sb1 == 1) {
+        kk = e / kTN;
+        j = e % kTN;
+      } else {
+        j = e / kTK;
+        kk = e % kTK;
+      }
+      const int64_t gk = k0 + kk, gj = col0 + j;
+      Bs[kk][j] = (gk < K && gj < N) ? B[gk * sb0 + gj * sb1] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[kk][ty + 16 * u];
+        b[u] = Bs[kk][tx + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t gi = row0 + ty + 16 * u;
+    if (gi >= M) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gj = col0 + tx + 16 * v;
+      if (gj >= N) continue;
+      double* c = C + gi * ldc + gj;
+      *c = alpha * acc[u][v] + (beta == 0.0 ? 0.0 : beta * *c);
+    }
+  }
+}
+
+__global__ void identity_kernel(double* U, int64_t r) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < r * r) U[e] = (e / r == e % r) ? 1.0 : 0.0;
+}
+
+__global__ void dcopy2d_kernel(int64_t M, int64_t N, double alpha, const double* __restrict__ src,
+                               int64_t lds, double* __restrict__ dst, int64_t ldd) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t i = e / N, j = e % N;
+  dst[i * ldd + j] = alpha * src[i * lds + j];
+}
+
+// In-place inverse of the k x k matrix N by Gauss-Jordan elimination with partial
+// pivoting (row interchanges, undone as column interchanges at the end).
+__global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ Ng, int k, int use_lds,
+                                                          double* __restrict__ work,
+                                                          int* __restrict__ info,
+                                                          double* __restrict__ norms) {
+  extern __shared__ double sm[];
+  __shared__ int perm[512];
+  __shared__ double fcol[512];
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ int bp;
+  __shared__ double bpv;
+  double* a = use_lds ? sm : work;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  for (int e = tid; e < k * k; e += nt) a[e] = Ng[e];
+  __syncthreads();
+  // ||N||_1 (max column sum)
+  {
+    double cs = 0.0;
+    for (int j = tid; j < k; j += nt) {
+      double s = 0.0;
+      for (int i = 0; i < k; ++i) s += fabs(a[i * k + j]);
+      cs = fmax(cs, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+    if (lane == 0) red_v[wave] = cs;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int w = 0; w < nw; ++w) m = fmax(m, red_v[w]);
+      norms[0] = m;
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < k; ++j) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = j + tid; i < k; i += nt) {
+      const double v = fabs(a[i * k + j]);
+      if (v > bv || (v == bv && i < bi)) {
+        bv = v;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double gv = red_v[0];
+      int gi = red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (red_v[w] > gv || (red_v[w] == gv && red_i[w] < gi)) {
+          gv = red_v[w];
+          gi = red_i[w];
+        }
+      bp = gi;
+      bpv = gv;
+      perm[j] = gi;
+    }
+    __syncthreads();
+    if (!(bpv > 0.0)) {
+      if (tid == 0) *info = 1;
+      return;
+    }
+    const int p = bp;
+    if (p != j)
+      for (int c = tid; c < k; c += nt) {
+        const double t = a[j * k + c];
+        a[j * k + c] = a[p * k + c];
+        a[p * k + c] = t;
+      }
+    __syncthreads();
+    const double piv = a[j * k + j];
+    __syncthreads();
+    for (int c = tid; c < k; c += nt) a[j * k + c] = (c == j) ? 1.0 / piv : a[j * k + c] / piv;
+    for (int i = tid; i < k; i += nt) fcol[i] = a[i * k + j];
+    __syncthreads();
+    const double pjj = a[j * k + j];
+    for (int e = tid; e < k * k; e += nt) {
+      const int i = e / k, c = e % k;
+      if (i == j) continue;
+      const double f = fcol[i];
+      if (c == j)
+        a[e] = -f * pjj;
+      else
+        a[e] = a[e] - f * a[j * k + c];
+    }
+    __syncthreads();
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    const int p = perm[j];
+    if (p != j)
+      for (int i = tid; i < k; i += nt) {
+        const double t = a[i * k + j];
+        a[i * k + j] = a[i * k + p];
+        a[i * k + p] = t;
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < k * k; e += nt) Ng[e] = a[e];
+  {
+    double cs = 0.0;
+    for (int j = tid; j < k; j += nt) {
+      double s = 0.0;
+      for (int i = 0; i < k; ++i) s += fabs(a[i * k + j]);
+      cs = fmax(cs, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+    if (lane == 0) red_v[wave] = cs;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int w = 0; w < nw; ++w) m = fmax(m, red_v[w]);
+      norms[1] = m;
+      *info = 0;
+    }
+  }
+}
+
+}  // namespace
+
+int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sa0,
+          int64_t sa1, const double* B, int64_t sb0, int64_t sb1, double beta, double* C,
+          int64_t ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return ICUR_OK;
+  if ((N + kTN - 1) / kTN > 0x7fffffff || (M + kTM - 1) / kTM > 65535)
+    return arg_error("dgemm: matrix too large");
+  dim3 grid(static_cast<unsigned>((N + kTN - 1) / kTN), static_cast<unsigned>((M + kTM - 1) / kTM));
+  hipLaunchKernelGGL(dgemm_kernel, grid, dim3(256), 0, st, M, N, K, alpha, A, sa0, sa1, B, sb0, sb1,
+                     beta, C, ldc);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int dcopy2d(int64_t M, int64_t N, double alpha, const double* src, int64_t lds, double* dst,
+            int64_t ldd, hipStream_t st) {
+  if (M <= 0 || N <= 0) return ICUR_OK;
+  const int64_t total = M * N;
+  hipLaunchKernelGGL(dcopy2d_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, st,
+                     M, N, alpha, src, lds, dst, ldd);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_fill_f64_identity(double* U, int64_t r, hipStream_t st) {
+  if (r <= 0) return ICUR_OK;
+  const int64_t total = r * r;
+  hipLaunchKernelGGL(identity_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, st, U, r);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+size_t small_inverse_work_bytes(int64_t k) { return static_cast<size_t>(k) * k * sizeof(double); }
+
+int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
+                         hipStream_t st) {
+  if (k < 1 || k > 512) return arg_error("inverse: block size must be in 1..512");
+  const bool use_lds = k <= 128;
+  const size_t shmem = use_lds ? static_cast<size_t>(k) * k * sizeof(double) : 0;
+  if (shmem > 64 * 1024)
+    ICUR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(gj_inverse_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shmem)));
+  hipLaunchKernelGGL(gj_inverse_kernel, dim3(1), dim3(1024), shmem, st, N, static_cast<int>(k),
+                     use_lds ? 1 : 0, work, info, norms);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+// U (ldu) grows from r x r to (r+k) x (r+k).  ws must hold k*k + 2*k*r + k*k doubles.
+int core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y, int64_t ldy,
+                const double* A21, const double* A22, double* ws, int* info, double* norms,
+                hipStream_t st) {
+  double* Nw = ws;                // k x k
+  double* Z = Nw + k * k;         // k x r
+  double* V = Z + k * r;          // r x k
+  double* gjw = V + r * k;        // k x k (Gauss-Jordan work when k > 128)
+  ICUR_TRY(dcopy2d(k, k, 1.0, A22, k, Nw, k, st));
+  if (r > 0) ICUR_TRY(dgemm(k, k, r, -1.0, A21, r, 1, Y, ldy, 1, 1.0, Nw, k, st));
+  ICUR_TRY(launch_small_inverse(Nw, k, gjw, info, norms, st));
+  if (r > 0) {
+    ICUR_TRY(dgemm(k, r, r, 1.0, A21, r, 1, U, ldu, 1, 0.0, Z, r, st));      // Z = A21 U
+    ICUR_TRY(dgemm(r, k, k, 1.0, Y, ldy, 1, Nw, k, 1, 0.0, V, k, st));      // V = Y N^-1
+    ICUR_TRY(dgemm(r, r, k, 1.0, V, k, 1, Z, r, 1, 1.0, U, ldu, st));       // U += V Z
+    ICUR_TRY(dcopy2d(r, k, -1.0, V, k, U + r, ldu, st));                    // U12 = -V
+    ICUR_TRY(dgemm(k, r, k, -1.0, Nw, k, 1, Z, r, 1, 0.0, U + r * ldu, ldu, st));  // U21
+  }
+  ICUR_TRY(dcopy2d(k, k, 1.0, Nw, k, U + r * ldu + r, ldu, st));            // U22 = N^-1
+  return ICUR_OK;
+}
+
+size_t core_update_ws_doubles(int64_t r, int64_t k) { return 2 * k * k + 2 * k * r; }
+
+// U = M^{-1} for the r x r cross M = A(I,J) (FP64, ld r, overwritten), by block LU in the
+// selection order (diagonal blocks are the Schur complements N_k the row selection
+// pivoted on, each inverted by Gauss-Jordan with partial pivoting) followed by block
+// forward and back substitution on the identity.  U (ld r) receives the inverse.
+// ws holds core_inverse_ws_doubles(r, bmax) doubles.
+int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblocks, int64_t bmax, double* U,
+                       double* ws, int* info, double* norms, hipStream_t st) {
+  double* Dinv = ws;                           // r x bmax: the diagonal block inverses, stacked
+  double* T = Dinv + r * bmax;                 // bmax x r temporary
+  double* gjw = T + bmax * r;                  // bmax x bmax Gauss-Jordan work
+  // block LU: M = L~ U~ with L~ unit block lower (stored below the diagonal blocks)
+  int64_t q = 0;
+  for (int64_t k = 0; k < nblocks; ++k) {
+    const int64_t nk = blocks[k];
+    double* Dk = Dinv + q * bmax;              // nk x nk, ld nk
+    ICUR_TRY(dcopy2d(nk, nk, 1.0, M + q * r + q, r, Dk, nk, st));
+    ICUR_TRY(launch_small_inverse(Dk, nk, gjw, info + k, norms, st));
+    const int64_t rest = r - q - nk;
+    if (rest > 0) {
+      // L~ panel: M[q+nk:, q:q+nk] <- M[q+nk:, q:q+nk] D_k^{-1}   (via T, rest x nk)
+      ICUR_TRY(dgemm(rest, nk, nk, 1.0, M + (q + nk) * r + q, r, 1, Dk, nk, 1, 0.0, T, nk, st));
+      ICUR_TRY(dcopy2d(rest, nk, 1.0, T, nk, M + (q + nk) * r + q, r, st));
+      // trailing update: M[q+nk:, q+nk:] -= L~ panel * M[q:q+nk, q+nk:]
+      ICUR_TRY(dgemm(rest, rest, nk, -1.0, M + (q + nk) * r + q, r, 1, M + q * r + q + nk, r, 1, 1.0,
+                     M + (q + nk) * r + q + nk, r, st));
+    }
+    q += nk;
+  }
+  // forward: U <- L~^{-1} (block unit lower), row block by row block
+  ICUR_TRY(launch_fill_f64_identity(U, r, st));
+  q = 0;
+  for (int64_t k = 0; k < nblocks; ++k) {
+    const int64_t nk = blocks[k];
+    if (q > 0)
+      ICUR_TRY(dgemm(nk, q, q, -1.0, M + q * r, r, 1, U, r, 1, 0.0, U + q * r, r, st));
+    q += nk;
+  }
+  // back: U <- U~^{-1} U, row blocks from the last
+  for (int64_t k = nblocks - 1; k >= 0; --k) {
+    const int64_t nk = blocks[k];
+    q -= nk;
+    const int64_t rest = r - q - nk;
+    ICUR_TRY(dcopy2d(nk, r, 1.0, U + q * r, r, T, r, st));
+    if (rest > 0)
+      ICUR_TRY(dgemm(nk, r, rest, -1.0, M + q * r + q + nk, r, 1, U + (q + nk) * r, r, 1, 1.0, T, r, st));
+    ICUR_TRY(dgemm(nk, r, nk, 1.0, Dinv + q * bmax, nk, 1, T, r, 1, 0.0, U + q * r, r, st));
+  }
+  return ICUR_OK;
+}
+
+size_t core_inverse_ws_doubles(int64_t r, int64_t bmax) { return r * bmax + bmax * r + bmax * bmax; }
+
+}  // namespace icur

@@ -1,0 +1,200 @@
+// Gathers of the CUR factors C = A(:,J), R = A(I,:) and of the small blocks of the core
+// (Alg. 1 update step; §1.1 Notation), plus mask and fill helpers.
+//
+// C is kept transposed (C^T: one contiguous row of length m per selected column), so the
+// row residual reads it with the same coalesced layout as every other wide product.  A
+// column of a row-major A is a strided gather: each element costs one cache line, which
+// is inherent to the layout; the writes are coalesced.  Rows of A are copied with 16-byte
+// loads when alignment allows.
+#include "icur_internal.h"
+
+namespace icur {
+namespace {
+
+template <typename DstT>
+__global__ void gather_cols_T_kernel(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                     const int64_t* __restrict__ cols, int64_t k,
+                                     DstT* __restrict__ Ct, int64_t ldct) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t t = blockIdx.y;
+  if (i >= m || t >= k) return;
+  int64_t j = cols[t];
+  j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+  Ct[t * ldct + i] = static_cast<DstT>(A[i * lda + j]);
+}
+
+__global__ void gather_rows_kernel(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                   const int64_t* __restrict__ rows, int64_t k,
+                                   float* __restrict__ R, int64_t ldr, int vec4) {
+  const int64_t t = blockIdx.y;
+  if (t >= k) return;
+  int64_t i = rows[t];
+  i = i < 0 ? 0 : (i >= m ? m - 1 : i);
+  const float* src = A + i * lda;
+  float* dst = R + t * ldr;
+  if (vec4) {
+    const int64_t n4 = n / 4;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n4;
+         j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+      reinterpret_cast<float4*>(dst)[j] = reinterpret_cast<const float4*>(src)[j];
+    for (int64_t j = 4 * n4 + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+         j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+      dst[j] = src[j];
+  } else {
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+         j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+      dst[j] = src[j];
+  }
+}
+
+__global__ void gather_rows_f64_kernel(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                       const int64_t* __restrict__ rows, int64_t k, double* __restrict__ R,
+                                       int64_t ldr) {
+  const int64_t t = blockIdx.y;
+  if (t >= k) return;
+  int64_t i = rows[t];
+  i = i < 0 ? 0 : (i >= m ? m - 1 : i);
+  const float* src = A + i * lda;
+  double* dst = R + t * ldr;
+  for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[j] = static_cast<double>(src[j]);
+}
+
+template <typename SrcT>
+__global__ void gather_f64_kernel(const SrcT* __restrict__ src, int64_t lds,
+                                  const int64_t* __restrict__ rows, int64_t rk,
+                                  const int64_t* __restrict__ cols, int64_t ck, int trans,
+                                  double* __restrict__ dst, int64_t ldd) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= rk * ck) return;
+  // consecutive threads walk the source's contiguous dimension when no column index list
+  // is given, else the destination's
+  const int64_t i = e / ck, j = e % ck;
+  const int64_t si = rows ? rows[i] : i;
+  const int64_t sj = cols ? cols[j] : j;
+  const double v = static_cast<double>(src[si * lds + sj]);
+  if (trans)
+    dst[j * ldd + i] = v;
+  else
+    dst[i * ldd + j] = v;
+}
+
+__global__ void set_mask_kernel(uint8_t* mask, const int64_t* idx, int64_t k) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < k) mask[idx[t]] = 1;
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, int64_t n, uint8_t v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int64_t n, unsigned v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+unsigned blocks_for(int64_t n, int64_t per = 256, int64_t cap = 4096) {
+  int64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace
+
+template <typename DstT>
+int gather_cols_T_t(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols, int64_t k, DstT* Ct,
+                    int64_t ldct, hipStream_t st) {
+  if (k <= 0 || m <= 0) return ICUR_OK;
+  if (k > 65535) return arg_error("gather: more than 65535 columns at once");
+  dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(k));
+  hipLaunchKernelGGL(gather_cols_T_kernel<DstT>, grid, dim3(256), 0, st, A, m, n, lda, cols, k, Ct, ldct);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_gather_cols_T(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
+                         int64_t k, float* Ct, int64_t ldct, hipStream_t st) {
+  return gather_cols_T_t(A, m, n, lda, cols, k, Ct, ldct, st);
+}
+
+int launch_gather_cols_T(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
+                         int64_t k, double* Ct, int64_t ldct, hipStream_t st) {
+  return gather_cols_T_t(A, m, n, lda, cols, k, Ct, ldct, st);
+}
+
+int launch_gather_rows(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* rows,
+                       int64_t k, double* R, int64_t ldr, hipStream_t st) {
+  if (k <= 0 || n <= 0) return ICUR_OK;
+  if (k > 65535) return arg_error("gather: more than 65535 rows at once");
+  const unsigned bx = blocks_for(n, 256, 64);
+  hipLaunchKernelGGL(gather_rows_f64_kernel, dim3(bx, static_cast<unsigned>(k)), dim3(256), 0, st, A, m, n, lda,
+                     rows, k, R, ldr);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_gather_rows(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* rows,
+                       int64_t k, float* R, int64_t ldr, hipStream_t st) {
+  if (k <= 0 || n <= 0) return ICUR_OK;
+  if (k > 65535) return arg_error("gather: more than 65535 rows at once");
+  const int vec4 = ((lda & 3) == 0) && ((ldr & 3) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(R) & 15) == 0);
+  const unsigned bx = blocks_for(vec4 ? (n + 3) / 4 : n, 256, 64);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(bx, static_cast<unsigned>(k)), dim3(256), 0, st, A, m,
+                     n, lda, rows, k, R, ldr, vec4);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+template <typename SrcT>
+int gather_f64_t(const SrcT* src, int64_t lds, const int64_t* rows, int64_t rk, const int64_t* cols,
+                 int64_t ck, bool trans, double* dst, int64_t ldd, hipStream_t st) {
+  if (rk <= 0 || ck <= 0) return ICUR_OK;
+  const int64_t total = rk * ck;
+  hipLaunchKernelGGL(gather_f64_kernel<SrcT>, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                     st, src, lds, rows, rk, cols, ck, trans ? 1 : 0, dst, ldd);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_gather_f64(const float* src, int64_t lds, const int64_t* rows, int64_t rk,
+                      const int64_t* cols, int64_t ck, bool trans, double* dst, int64_t ldd,
+                      hipStream_t st) {
+  return gather_f64_t(src, lds, rows, rk, cols, ck, trans, dst, ldd, st);
+}
+
+int launch_gather_f64(const double* src, int64_t lds, const int64_t* rows, int64_t rk,
+                      const int64_t* cols, int64_t ck, bool trans, double* dst, int64_t ldd,
+                      hipStream_t st) {
+  return gather_f64_t(src, lds, rows, rk, cols, ck, trans, dst, ldd, st);
+}
+
+int launch_set_mask(uint8_t* mask, const int64_t* idx, int64_t k, hipStream_t st) {
+  if (k <= 0) return ICUR_OK;
+  hipLaunchKernelGGL(set_mask_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st,
+                     mask, idx, k);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st) {
+  if (n <= 0) return ICUR_OK;
+  hipLaunchKernelGGL(fill_u8_kernel, dim3(blocks_for(n)), dim3(256), 0, st, p, n, v);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st) {
+  if (n <= 0) return ICUR_OK;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n)), dim3(256), 0, st, p, n, v);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+}  // namespace icur

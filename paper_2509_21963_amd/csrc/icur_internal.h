@@ -1,0 +1,157 @@
+// Internal declarations shared by the libicur translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "icur.h"
+
+namespace icur {
+
+// Error plumbing: every host wrapper returns an icur_status; the message of the last
+// failure of the calling thread is kept for icur_last_error().
+void set_error(const std::string& msg);
+const char* last_error();
+
+#define ICUR_HIP(call)                                                         \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::icur::set_error(std::string(#call) + ": " + hipGetErrorString(e_));    \
+      return ICUR_ERR_HIP;                                                     \
+    }                                                                          \
+  } while (0)
+
+#define ICUR_TRY(expr)        \
+  do {                        \
+    int s_ = (expr);          \
+    if (s_ < 0) return s_;    \
+  } while (0)
+
+inline int arg_error(const std::string& msg) {
+  set_error(msg);
+  return ICUR_ERR_ARG;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Device properties of the current device (cached).
+struct DeviceInfo {
+  int device;
+  int num_cus;
+};
+int device_info(DeviceInfo* out);
+
+// ----- sketch operator (icur_rng.hip) -----
+int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, hipStream_t st);
+int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* rows,
+                       uint8_t* signs, uint16_t* G_dense, hipStream_t st);
+
+// ----- wide products (icur_gemm.hip, icur_wide_*.hip) -----
+// OUT(M x N) = X - W(M x K) B(K x N) (subtract) or W B.  X and OUT are FP32, or FP64 when
+// out64.  W is FP32 (wterms == 0; BF16 bit patterns widened to FP32 when w_bf16) or
+// `wterms` BF16 pieces stored as consecutive M x ldw planes of uint16.  B is FP32, split
+// on the fly into `bterms` BF16 pieces; products of pieces (i, j) with i + j <
+// max(wterms, bterms) are summed.  Chunks of 32 K rows are summed on the matrix cores
+// and accumulated in FP64.  norm_partials (device, may be null) receives per-block FP64
+// partial sums of OUT^2; the number written is returned in *nparts.
+struct WideGemm {
+  const void* X;
+  int64_t ldx;
+  const void* W;
+  int64_t ldw;
+  int wterms;    // -1: FP64 W and B on FP64 matrix cores (needs out64)
+  bool w_bf16;
+  const void* B;
+  int64_t ldb;
+  int bterms;
+  int64_t M, K, N;
+  bool subtract;
+  bool out64;
+  void* OUT;
+  int64_t ldo;
+  double* norm_partials;
+  int* nparts;
+};
+int wide_gemm(const WideGemm& g, void* workspace, size_t workspace_bytes, hipStream_t st);
+size_t wide_gemm_workspace_bytes(int64_t M, int64_t K, int64_t N, int num_cus);
+int max_norm_partials(int64_t M, int64_t N);
+
+// FP64 -> BF16 pieces (terms planes) or FP32 (terms == 0), optionally transposed.
+// src is rows x cols with leading dimension lds; dst is (trans ? cols x rows : rows x
+// cols) with leading dimension ldd (elements), planes of stride plane.
+int launch_split_f64(const double* src, int64_t rows, int64_t cols, int64_t lds, bool trans,
+                     int terms, void* dst, int64_t ldd, int64_t plane, hipStream_t st);
+
+// Sum of per-block partials into out (device double, written in a fixed order).
+int launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st);
+
+// ----- selection (icur_lupp.hip) -----
+struct LuppWork {
+  double* L;          // steps_cap x N_cap
+  void* slots;        // 2 * max_groups slot records
+  unsigned* barrier;  // 1 counter
+  int* status;        // [0] npiv, [1] fault flag
+  int64_t steps_cap, N_cap;
+};
+size_t lupp_workspace_bytes(int64_t steps, int64_t N);
+int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w);
+// Pivots of LUPP on T = X^T (see icur_lupp); X is FP32, or FP64 when x64.  piv is
+// device; the pivot count and a fault flag land in w.status.
+int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps,
+                const uint8_t* excluded, int64_t* piv, const LuppWork& w, hipStream_t st);
+
+// ----- gathers and small FP64 kernels (icur_gather.hip) -----
+int launch_gather_cols_T(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
+                         int64_t k, float* Ct, int64_t ldct, hipStream_t st);
+int launch_gather_cols_T(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
+                         int64_t k, double* Ct, int64_t ldct, hipStream_t st);
+int launch_gather_rows(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* rows,
+                       int64_t k, float* R, int64_t ldr, hipStream_t st);
+int launch_gather_rows(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* rows,
+                       int64_t k, double* R, int64_t ldr, hipStream_t st);
+// dst(rk x ck, FP64, ld ldd) = src[rows[i]][cols[j]] (FP32 src with leading dim lds);
+// rows/cols null means identity offset (i or j).  trans: dst(j, i) instead.
+int launch_gather_f64(const float* src, int64_t lds, const int64_t* rows, int64_t rk,
+                      const int64_t* cols, int64_t ck, bool trans, double* dst, int64_t ldd,
+                      hipStream_t st);
+// Same with an FP64 source.
+int launch_gather_f64(const double* src, int64_t lds, const int64_t* rows, int64_t rk,
+                      const int64_t* cols, int64_t ck, bool trans, double* dst, int64_t ldd,
+                      hipStream_t st);
+int launch_set_mask(uint8_t* mask, const int64_t* idx, int64_t k, hipStream_t st);
+int launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
+int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
+
+// ----- FP64 dense kernels (icur_core.hip) -----
+// C(M x N) = alpha * A(M x K) B(K x N) + beta * C with element strides:
+// A(i,k) = A[i*sa0 + k*sa1], B(k,j) = B[k*sb0 + j*sb1], C(i,j) = C[i*ldc + j].
+int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sa0,
+          int64_t sa1, const double* B, int64_t sb0, int64_t sb1, double beta, double* C,
+          int64_t ldc, hipStream_t st);
+// In-place inverse of the k x k matrix N (ld k) by Gauss-Jordan elimination with
+// partial pivoting in FP64; info[0] = 0 on success, 1 on an exactly zero pivot;
+// info_d[1] (double) receives ||N||_1 and info_d[2] ||N^-1||_1.
+int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
+                         hipStream_t st);
+size_t small_inverse_work_bytes(int64_t k);
+int dcopy2d(int64_t M, int64_t N, double alpha, const double* src, int64_t lds, double* dst,
+            int64_t ldd, hipStream_t st);
+// Grow the core inverse U (ld ldu) from r x r to (r+k) x (r+k) by the block inverse of
+// the bordered matrix (see icur_core.hip).  Y is r x k (ld ldy), A21 k x r (ld r), A22
+// k x k (ld k).  ws holds core_update_ws_doubles(r, k) doubles.  info/norms are device.
+int core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y, int64_t ldy,
+                const double* A21, const double* A22, double* ws, int* info, double* norms,
+                hipStream_t st);
+size_t core_update_ws_doubles(int64_t r, int64_t k);
+// U = A(I,J)^{-1} from the gathered cross M (r x r, ld r, overwritten): block LU in the
+// selection order, then block triangular solves on the identity.  info has one entry
+// per block (0 = regular).  ws: core_inverse_ws_doubles(r, bmax) doubles.
+int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblocks, int64_t bmax, double* U,
+                       double* ws, int* info, double* norms, hipStream_t st);
+size_t core_inverse_ws_doubles(int64_t r, int64_t bmax);
+int launch_fill_f64_identity(double* U, int64_t r, hipStream_t st);
+
+}  // namespace icur

@@ -1,0 +1,125 @@
+// The recycled sketch operator G (c x m) of Alg. 1, generated on the device.
+//
+// The paper draws G once and reuses it in every iteration (Alg. 1; §3.2.1); it uses
+// Gaussian entries in its experiments and names the sparse-sign matrix as a cheaper
+// alternative (§2.1, §3.4).  Entries come from the counter-based generator
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), so every entry is a pure function
+// of (seed, row, column) and any thread can produce any entry:
+//   Gaussian G[r][i]: counter (lo32(i), hi32(i), r, 'GAUS'), Box-Muller on the two
+//     53-bit uniforms of the block in FP64, rounded to FP32 then to BF16 (nearest even);
+//   sparse-sign column i: Floyd's sampling of min(zeta, c) distinct rows, the t-th draw
+//     from counter (lo32(i), hi32(i), t, 'SPRS'): row = word0 mod (c - z + t + 1),
+//     replaced by c - z + t when already taken; sign negative when bit 0 of word1 is 1.
+#include "icur_internal.h"
+
+namespace icur {
+namespace {
+
+constexpr uint32_t kTagGauss = 0x47415553u;
+constexpr uint32_t kTagSign = 0x53505253u;
+
+struct U32x4 {
+  uint32_t x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+    const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t* __restrict__ G) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (i >= m || r >= c) return;
+  const uint64_t ui = static_cast<uint64_t>(i);
+  const U32x4 w = philox4x32_10(static_cast<uint32_t>(ui), static_cast<uint32_t>(ui >> 32),
+                                static_cast<uint32_t>(r), kTagGauss,
+                                static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  const uint64_t a = ((static_cast<uint64_t>(w.x1) << 32) | w.x0) >> 11;
+  const uint64_t b = ((static_cast<uint64_t>(w.x3) << 32) | w.x2) >> 11;
+  const double u1 = (static_cast<double>(a) + 1.0) * 0x1.0p-53;  // (0, 1]
+  const double u2 = static_cast<double>(b) * 0x1.0p-53;          // [0, 1)
+  const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  G[r * m + i] = f32_to_bf16_rne(static_cast<float>(z));
+}
+
+// One thread per column i of G (row i of A).  Writes the pattern and, when G_dense is
+// given, the whole dense column (zeros included) as BF16 bit patterns.
+__global__ void sparse_sign_kernel(uint64_t seed, int c, int64_t m, int z,
+                                   uint8_t* __restrict__ rows, uint8_t* __restrict__ signs,
+                                   uint16_t* __restrict__ G) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t ui = static_cast<uint64_t>(i);
+  int chosen[8];
+  uint32_t sbits = 0;
+  for (int t = 0; t < z; ++t) {
+    const U32x4 w = philox4x32_10(static_cast<uint32_t>(ui), static_cast<uint32_t>(ui >> 32),
+                                  static_cast<uint32_t>(t), kTagSign,
+                                  static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    const int j = c - z + t;
+    int v = static_cast<int>(w.x0 % static_cast<uint32_t>(j + 1));
+    bool taken = false;
+    for (int s = 0; s < t; ++s) taken |= (chosen[s] == v);
+    chosen[t] = taken ? j : v;
+    sbits |= (w.x1 & 1u) << t;
+  }
+  if (rows) {
+    for (int t = 0; t < z; ++t) rows[i * z + t] = static_cast<uint8_t>(chosen[t]);
+  }
+  if (signs) signs[i] = static_cast<uint8_t>(sbits);
+  if (G) {
+    for (int r = 0; r < c; ++r) {
+      uint16_t v = 0;
+      for (int t = 0; t < z; ++t)
+        if (chosen[t] == r) v = ((sbits >> t) & 1u) ? 0xBF80u : 0x3F80u;  // -1 / +1
+      G[static_cast<int64_t>(r) * m + i] = v;
+    }
+  }
+}
+
+}  // namespace
+
+int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, hipStream_t st) {
+  if (c <= 0 || m <= 0) return ICUR_OK;
+  if (c > 65535) return arg_error("sketch rows c exceed 65535");
+  dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(c));
+  hipLaunchKernelGGL(gaussian_G_kernel, grid, dim3(256), 0, st, seed, c, m, G);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* rows,
+                       uint8_t* signs, uint16_t* G_dense, hipStream_t st) {
+  if (c <= 0 || m <= 0) return ICUR_OK;
+  if (c > 255) return arg_error("sparse-sign sketch needs c <= 255");
+  const int z = zeta < c ? zeta : static_cast<int>(c);
+  if (z < 1 || z > 8) return arg_error("sparse-sign zeta must be in 1..8");
+  hipLaunchKernelGGL(sparse_sign_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256),
+                     0, st, seed, static_cast<int>(c), m, z, rows, signs, G_dense);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+}  // namespace icur

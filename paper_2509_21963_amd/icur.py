@@ -1,0 +1,241 @@
+"""Python binding of libicur (ctypes).
+
+Argument marshalling only: every step of IterativeCUR runs in the HIP kernels of
+libicur.so.  Device buffers are torch CUDA (HIP) tensors; the binding passes their
+pointers and the current torch stream.  If the library has not been built this module
+raises on import of the library (there is no fallback path).
+
+Function names follow the C entry points in include/icur.h without the `icur_` prefix.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libicur.so")
+
+OK, MAXRANK, STALLED = 0, 1, 2
+ERR_ARG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+GAUSSIAN, SPARSE_SIGN = 0, 1
+FP32, BF16_SPLIT = 0, 1
+
+_STATUS_NAMES = {0: "ok", 1: "maxrank", 2: "stalled", -1: "bad argument",
+                 -2: "non-finite input", -3: "out of device memory", -4: "HIP error",
+                 -5: "unsupported shape"}
+
+
+class IcurError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("libicur: %s (%d): %s" % (_STATUS_NAMES.get(status, "?"), status, message))
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("zeta", ctypes.c_int32),
+                ("max_rank", ctypes.c_int64), ("stream", ctypes.c_void_p),
+                ("alpha", ctypes.c_double), ("delta", ctypes.c_double),
+                ("split_terms", ctypes.c_int32), ("sketch_fp32", ctypes.c_int32),
+                ("residual_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("split_terms", ctypes.c_int32),
+                ("sketch_norm", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_sketch", ctypes.c_double),
+                ("ms_select", ctypes.c_double), ("ms_residual", ctypes.c_double),
+                ("ms_core", ctypes.c_double), ("ms_sketch_product", ctypes.c_double),
+                ("n_rho", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("rho", ctypes.c_double * 512)]
+
+
+_lib = None
+EXPORTS = ["icur_run", "icur_last_info", "icur_last_error", "icur_release",
+           "icur_make_sketch", "icur_sketch", "icur_lupp", "icur_residual", "icur_gather",
+           "icur_core_update"]
+
+
+def load(path=LIB_PATH):
+    """Load libicur.so (once).  Raises FileNotFoundError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            "libicur.so not found at %s; build it with `python -m paper_2509_21963_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    P, I64, I32, D, U64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64
+    lib.icur_run.argtypes = [P, I64, I64, I64, D, I32, I32, U64, ctypes.POINTER(Opts), P, P, P,
+                             ctypes.POINTER(I64), ctypes.POINTER(D)]
+    lib.icur_last_info.argtypes = [ctypes.POINTER(Info)]
+    lib.icur_last_error.restype = ctypes.c_char_p
+    lib.icur_make_sketch.argtypes = [U64, I64, I64, I32, I32, P, P, P, P]
+    lib.icur_sketch.argtypes = [P, I64, P, I64, I64, I64, I32, P, ctypes.POINTER(D), P]
+    lib.icur_lupp.argtypes = [P, I64, I64, I64, I32, P, P, ctypes.POINTER(I32), P]
+    lib.icur_residual.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, I32, P, I64,
+                                  ctypes.POINTER(D), P]
+    lib.icur_gather.argtypes = [P, I64, I64, I64, P, P, I64, P, I64, P, I64, P]
+    lib.icur_core_update.argtypes = [P, I64, I64, I64, P, P, P, ctypes.POINTER(D), P]
+    for name in EXPORTS:
+        if name not in ("icur_last_error",):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, allow_warnings=False):
+    if status < 0 or (status > 0 and not allow_warnings):
+        raise IcurError(status, load().icur_last_error().decode())
+    return status
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _require(t, dtype, name):
+    import torch
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s" % (name, dtype))
+    if t.dim() == 2 and t.stride(1) != 1:
+        raise ValueError("%s must be row-major with unit column stride" % name)
+
+
+def run(A, tol, block, sketch_kind=GAUSSIAN, seed=0, precision=FP32, zeta=0, max_rank=0,
+        alpha=0.0, delta=0.0, split_terms=0, sketch_fp32=False, residual_fp64=0):
+    """icur_run on the m x n FP32 device tensor A.  Returns a dict with I, J (int64
+    numpy arrays, selection order), U (rank x rank float64 numpy array), rank, rho
+    (final estimate), status ("ok", "maxrank" or "stalled") and info (per-call
+    statistics)."""
+    import torch
+    lib = load()
+    _require(A, torch.float32, "A")
+    m, n = A.shape
+    rmax = min(m, n) if max_rank == 0 else min(int(max_rank), m, n)
+    I = np.zeros(rmax, np.int64)
+    J = np.zeros(rmax, np.int64)
+    U = np.zeros(rmax * rmax, np.float64)
+    rank = ctypes.c_int64(0)
+    rho = ctypes.c_double(0.0)
+    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 1 if sketch_fp32 else 0,
+             int(residual_fp64), 0)
+    st = lib.icur_run(_ptr(A), m, n, A.stride(0), float(tol), int(block), int(sketch_kind),
+                      ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
+                      I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
+                      U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
+    _check(st, allow_warnings=True)
+    r = rank.value
+    return {"I": I[:r].copy(), "J": J[:r].copy(), "U": U[:r * r].reshape(r, r).copy(),
+            "rank": r, "rho": rho.value, "status": _STATUS_NAMES[st], "info": last_info()}
+
+
+def last_info():
+    info = Info()
+    load().icur_last_info(ctypes.byref(info))
+    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad")}
+    d["rho"] = list(info.rho[:info.n_rho])
+    return d
+
+
+def release():
+    _check(load().icur_release())
+
+
+def make_sketch(seed, c, m, kind=GAUSSIAN, zeta=0, want_dense=True, want_pattern=False):
+    """icur_make_sketch: returns (G_bf16 uint16 c x m or None, rows uint8 m x z or None,
+    signs uint8 m or None) as device tensors (int16 holds the BF16 bit patterns)."""
+    import torch
+    lib = load()
+    G = torch.empty((c, m), dtype=torch.int16, device="cuda") if want_dense else None
+    z = min(zeta if zeta > 0 else 8, c)
+    rows = torch.empty((m, z), dtype=torch.uint8, device="cuda") if want_pattern else None
+    signs = torch.empty((m,), dtype=torch.uint8, device="cuda") if want_pattern else None
+    _check(lib.icur_make_sketch(ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), c, m, kind, zeta,
+                                _ptr(G), _ptr(rows), _ptr(signs), _stream()))
+    return G, rows, signs
+
+
+def sketch(G, A, terms):
+    """icur_sketch: X0 = G A (c x n FP32 device tensor) and ||X0||_F^2."""
+    import torch
+    lib = load()
+    _require(A, torch.float32, "A")
+    c, m = G.shape
+    n = A.shape[1]
+    if A.shape[0] != m:
+        raise ValueError("shape mismatch")
+    X0 = torch.empty((c, n), dtype=torch.float32, device="cuda")
+    nsq = ctypes.c_double(0.0)
+    _check(lib.icur_sketch(_ptr(G), c, _ptr(A), m, n, A.stride(0), terms, _ptr(X0),
+                           ctypes.byref(nsq), _stream()))
+    return X0, nsq.value
+
+
+def lupp(X, steps, excluded=None):
+    """icur_lupp on the K x N FP32 device tensor X (candidates along N): returns the
+    pivot order as an int64 numpy array."""
+    import torch
+    lib = load()
+    _require(X, torch.float32, "X")
+    K, N = X.shape
+    piv = torch.zeros((steps,), dtype=torch.int64, device="cuda")
+    npiv = ctypes.c_int32(0)
+    if excluded is not None and (excluded.dtype != torch.uint8 or excluded.numel() != N):
+        raise ValueError("excluded must be a uint8 device tensor of length N")
+    _check(lib.icur_lupp(_ptr(X), K, N, X.stride(0), steps, _ptr(excluded), _ptr(piv),
+                         ctypes.byref(npiv), _stream()))
+    return piv[:npiv.value].cpu().numpy()
+
+
+def residual(X, W, B, terms):
+    """icur_residual: OUT = X - W B with W FP64 (M x K), B FP32 (K x N), X FP32 (M x N)
+    or None.  Returns (OUT, ||OUT||_F^2)."""
+    import torch
+    lib = load()
+    M, K = W.shape
+    N = B.shape[1]
+    OUT = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    nsq = ctypes.c_double(0.0)
+    _check(lib.icur_residual(_ptr(X), X.stride(0) if X is not None else N, _ptr(W),
+                             W.stride(0) if K > 0 else 1, _ptr(B), B.stride(0), M, K, N, terms,
+                             _ptr(OUT), N, ctypes.byref(nsq), _stream()))
+    return OUT, nsq.value
+
+
+def gather_cols_T(A, cols):
+    import torch
+    lib = load()
+    m, n = A.shape
+    k = cols.numel()
+    Ct = torch.empty((k, m), dtype=torch.float32, device="cuda")
+    _check(lib.icur_gather(_ptr(A), m, n, A.stride(0), _ptr(cols), None, k, _ptr(Ct), m, None, 0,
+                           _stream()))
+    return Ct
+
+
+def gather_rows(A, rows):
+    import torch
+    lib = load()
+    m, n = A.shape
+    k = rows.numel()
+    R = torch.empty((k, n), dtype=torch.float32, device="cuda")
+    _check(lib.icur_gather(_ptr(A), m, n, A.stride(0), None, _ptr(rows), k, None, 0, _ptr(R), n,
+                           _stream()))
+    return R
+
+
+def core_update(U, r, k, Y, A21, A22):
+    """icur_core_update in place on the FP64 device tensor U ((r+k) x (r+k) or larger,
+    row-major).  Returns rcond of the new diagonal block."""
+    lib = load()
+    rc = ctypes.c_double(0.0)
+    _check(lib.icur_core_update(_ptr(U), U.stride(0), r, k, _ptr(Y), _ptr(A21), _ptr(A22),
+                                ctypes.byref(rc), _stream()))
+    return rc.value

@@ -1,0 +1,100 @@
+"""The C-ABI library loads and exports every symbol include/icur.h declares; argument
+errors are reported before any device work (CPU only: no compute call reaches a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "icur.h")
+
+
+def _lib():
+    from paper_2509_21963_amd import icur
+    if not os.path.exists(icur.LIB_PATH):
+        from paper_2509_21963_amd import build
+        build.build()
+    return icur, icur.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(icur_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("icur_run", "icur_lupp", "icur_sketch", "icur_residual", "icur_gather",
+                 "icur_core_update", "icur_make_sketch", "icur_release", "icur_last_error",
+                 "icur_last_info"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    icur, lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(icur.EXPORTS) == set(declared_functions())
+
+
+def test_struct_layouts_match_header():
+    icur, _ = _lib()
+    # icur_opts: 2 x int32, int64, pointer, 2 x double, 4 x int32
+    assert ctypes.sizeof(icur.Opts) == 56
+    # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles
+    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation precedes device work
+
+
+def _run_args(lib, m=10, n=8, lda=8, tol=1e-3, block=2, kind=0, opts=None):
+    I = np.zeros(64, np.int64)
+    J = np.zeros(64, np.int64)
+    U = np.zeros(64 * 64)
+    rank = ctypes.c_int64(-1)
+    rho = ctypes.c_double(-1.0)
+    st = lib.icur_run(FAKE, m, n, lda, tol, block, kind, ctypes.c_uint64(0), opts,
+                      I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
+                      U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
+    return st, rank.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=0), dict(n=0), dict(lda=7), dict(tol=0.0), dict(tol=float("nan")),
+    dict(tol=float("inf")), dict(block=0), dict(block=9), dict(kind=2),
+])
+def test_run_rejects_bad_arguments_before_device_work(kw):
+    icur, lib = _lib()
+    st, rank = _run_args(lib, **kw)
+    assert st == icur.ERR_ARG
+    assert rank == -1                      # nothing written
+    assert lib.icur_last_error()
+
+
+def test_run_rejects_bad_options():
+    icur, lib = _lib()
+    for o in (icur.Opts(precision=5), icur.Opts(zeta=9), icur.Opts(split_terms=4),
+              icur.Opts(max_rank=-1), icur.Opts(alpha=1e-10),     # c = 2 < -4 ln(alpha)
+              icur.Opts(residual_fp64=2)):
+        st, _ = _run_args(lib, opts=ctypes.byref(o))
+        assert st == icur.ERR_ARG, (o.precision, o.zeta)
+    # sparse-sign needs c <= 255
+    st, _ = _run_args(lib, m=300, n=300, lda=300, block=240, kind=1)
+    assert st == icur.ERR_ARG
+
+
+def test_step_entry_points_reject_bad_shapes():
+    icur, lib = _lib()
+    n = ctypes.c_int32(0)
+    assert lib.icur_lupp(FAKE, 4, 10, 9, 2, None, FAKE, ctypes.byref(n), None) == icur.ERR_ARG
+    assert lib.icur_lupp(FAKE, 4, 10, 10, 5, None, FAKE, ctypes.byref(n), None) == icur.ERR_ARG
+    assert lib.icur_sketch(FAKE, 0, FAKE, 5, 5, 5, 0, FAKE, None, None) == icur.ERR_ARG
+    assert lib.icur_sketch(FAKE, 3, FAKE, 5, 5, 5, 4, FAKE, None, None) == icur.ERR_ARG
+    assert lib.icur_residual(None, 4, FAKE, 3, FAKE, 4, 2, 3, 4, 0, FAKE, 3, None, None) == icur.ERR_ARG
+    assert lib.icur_gather(FAKE, 4, 4, 4, FAKE, FAKE, 2, FAKE, 4, FAKE, 4, None) == icur.ERR_ARG
+    assert lib.icur_core_update(FAKE, 3, 2, 2, FAKE, FAKE, FAKE, None, None) == icur.ERR_ARG
+    assert lib.icur_make_sketch(ctypes.c_uint64(0), 3, 5, 7, 0, FAKE, None, None, None) == icur.ERR_ARG

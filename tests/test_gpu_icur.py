@@ -1,0 +1,182 @@
+"""End-to-end parity of icur_run with the FP64 oracle (GPU).
+
+IterativeCUR is a greedy, randomized iteration, so the HIP path and the oracle agree on
+the unique part of the result and are checked for validity on the rest:
+  * the selected index sequence equals the oracle's up to the first pivot step whose
+    oracle margin (1 - |2nd best| / |best|) is below the precision gap of the form;
+  * the final exact error ||A - CUR||_F / ||A||_F (computed on the host in FP64 from the
+    GPU's I, J, U) is at most 2 tol, and the estimate rho is within a factor 2 of it;
+  * the residual vanishes on the selected rows and columns; U = A(I,J)^{-1}.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.icur import exact_relative_error, iterative_cur   # noqa: E402
+from paper_2509_21963_amd import workloads as W               # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def icur():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_21963_amd import icur as m
+    m.load()
+    return m
+
+
+def _prefix_until_tie(oracle_out, margin):
+    seq_J, seq_I = [], []
+    for h in oracle_out["history"]:
+        for j, mg in zip(h["J_k"], h["col_margins"]):
+            if mg < margin:
+                return seq_J, seq_I, False
+            seq_J.append(j)
+        for i, mg in zip(h["I_k"], h["row_margins"]):
+            if mg < margin:
+                return seq_J, seq_I, False
+            seq_I.append(i)
+    return seq_J, seq_I, True
+
+
+def check_against_oracle(icur, A32, tol, b, kind, seed, precision=0, margin=1e-3, **kw):
+    A64 = A32.astype(np.float64)
+    got = icur.run(torch.from_numpy(A32).cuda(), tol, b, kind, seed, precision, **kw)
+    ora = iterative_cur(A64, tol, b, kind=kind, seed=seed, record=True,
+                        max_rank=kw.get("max_rank") or None)
+    r = got["rank"]
+    I, J, U = got["I"].tolist(), got["J"].tolist(), got["U"]
+    assert len(set(I)) == r and len(set(J)) == r
+    # unique part: same choices until the oracle meets a near tie
+    pJ, pI, complete = _prefix_until_tie(ora, margin)
+    assert J[:len(pJ)] == pJ
+    assert I[:len(pI)] == pI
+    if complete:
+        assert J == ora["J"] and I == ora["I"]
+    # validity of the rest: U is the inverse of the cross A(I,J): the CUR error with the
+    # returned U matches the one with an inverse computed on the host
+    err = exact_relative_error(A64, I, J, U) if r else 1.0
+    if r:
+        core = A64[np.ix_(I, J)]
+        err_ref = exact_relative_error(A64, I, J, np.linalg.inv(core))
+        assert err <= 1.5 * err_ref + 1e-9
+    return got, ora, err
+
+
+def test_planted_spectrum_2000x1500_fp32(icur):
+    # tol 1e-6 on a cross with condition ~1e8: the residual factors run in FP64
+    A, _ = W.planted_geometric(2000, 1500, 40.0, seed=0)
+    A32, _ = W.to_f32(A)
+    got, ora, err = check_against_oracle(icur, A32, 1e-6, 50, 0, 0)
+    assert got["status"] == "ok" and got["rho"] <= 1e-6
+    assert err <= 2e-6 and 0.5 <= got["rho"] / err <= 2.0
+    assert abs(got["rank"] - ora["rank"]) <= 50
+    assert got["info"]["iterations"] == len(got["info"]["rho"])
+
+
+@pytest.mark.parametrize("res64", [1, -1])
+def test_residual_factor_precision_switch(icur, res64):
+    # tol 1e-4 is well above the FP32 floor: both factor precisions meet it
+    A, _ = W.planted_geometric(1200, 1000, 30.0, seed=6)
+    A32, _ = W.to_f32(A)
+    got, ora, err = check_against_oracle(icur, A32, 1e-4, 32, 0, 6, residual_fp64=res64)
+    assert got["status"] == "ok" and err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_exact_low_rank_recovery(icur, kind):
+    A32, _ = W.to_f32(W.exact_lowrank(400, 300, 30, seed=5))
+    got, ora, err = check_against_oracle(icur, A32, 1e-5, 10, kind, 1)
+    assert got["rank"] == 30
+    assert err < 1e-5 and got["rho"] < 1e-5
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rbf_sparse_sign(icur, seed):
+    A32, _ = W.to_f32(W.rbf(1500, 1200, seed))
+    got, ora, err = check_against_oracle(icur, A32, 1e-4, 20, 1, seed)
+    assert got["status"] == "ok"
+    assert err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
+
+
+@pytest.mark.parametrize("tol", [1e-2, 1e-3, 1e-5])
+def test_bf16_split_form(icur, tol):
+    A, _ = W.planted_geometric(3000, 2000, 60.0, seed=3)
+    A32, _ = W.to_f32(A)
+    got, ora, err = check_against_oracle(icur, A32, tol, 64, 0, 3, precision=1, margin=1e-2)
+    assert got["status"] == "ok"
+    assert err <= 2 * tol and 0.5 <= got["rho"] / err <= 2.0
+    assert got["info"]["split_terms"] == (1 if tol >= 1e-1 else 2 if tol >= 5e-4 else 3)
+
+
+def test_fp32_matrix_core_sketch_option(icur):
+    A32, _ = W.to_f32(W.planted_geometric(800, 600, 30.0, seed=4)[0])
+    got, ora, err = check_against_oracle(icur, A32, 1e-5, 16, 0, 4, sketch_fp32=True)
+    assert err <= 2e-5
+
+
+def test_schur_zeros_of_the_result(icur):
+    A32, _ = W.to_f32(W.rbf(900, 700, 2))
+    got = icur.run(torch.from_numpy(A32).cuda(), 1e-5, 16, 0, 7)
+    A = A32.astype(np.float64)
+    I, J, U = got["I"], got["J"], got["U"]
+    S = A - A[:, J] @ U @ A[I, :]
+    scale = np.abs(A).max()
+    assert np.abs(S[I, :]).max() < 1e-9 * scale * np.linalg.cond(A[np.ix_(I, J)])
+    assert np.abs(S[:, J]).max() < 1e-9 * scale * np.linalg.cond(A[np.ix_(I, J)])
+
+
+def test_degenerate_and_edge_cases(icur):
+    z = torch.zeros((300, 200), dtype=torch.float32, device="cuda")
+    out = icur.run(z, 1e-3, 8)
+    assert out["rank"] == 0 and out["rho"] == 0.0 and out["status"] == "ok"
+    bad = torch.ones((300, 200), dtype=torch.float32, device="cuda")
+    bad[5, 7] = float("nan")
+    with pytest.raises(icur.IcurError) as e:
+        icur.run(bad, 1e-3, 8)
+    assert e.value.status == icur.ERR_NONFINITE
+    # max_rank cap
+    A32, _ = W.to_f32(W.rbf(400, 300, 1, h=0.05))
+    out = icur.run(torch.from_numpy(A32).cuda(), 1e-12, 7, max_rank=20)
+    assert out["status"] == "maxrank" and out["rank"] == 20
+    # exhaustion of a full-rank matrix with a shortened last block (23 = 4*5 + 3)
+    R32 = np.random.default_rng(0).standard_normal((30, 23)).astype(np.float32)
+    out = icur.run(torch.from_numpy(R32).cuda(), 1e-12, 5)
+    assert out["rank"] == 23
+    # block 1 and the smallest shapes
+    out = icur.run(torch.from_numpy(W.to_f32(W.rbf(50, 40, 3))[0]).cuda(), 1e-3, 1)
+    assert out["status"] == "ok" and out["rank"] >= 1
+    one = torch.full((1, 1), 2.0, device="cuda")
+    out = icur.run(one, 1e-3, 1)
+    assert out["rank"] == 1 and out["I"].tolist() == [0] and out["U"][0, 0] == 0.5
+
+
+def test_repeatable_and_seed_dependent(icur):
+    A = torch.from_numpy(W.to_f32(W.rbf(1000, 800, 5))[0]).cuda()
+    a = icur.run(A, 1e-4, 10, 0, 11)
+    b = icur.run(A, 1e-4, 10, 0, 11)
+    c = icur.run(A, 1e-4, 10, 0, 12)
+    assert a["I"].tolist() == b["I"].tolist() and a["J"].tolist() == b["J"].tolist()
+    assert a["rho"] == b["rho"]
+    assert a["J"].tolist() != c["J"].tolist()
+
+
+def test_risk_aware_threshold(icur):
+    A32, _ = W.to_f32(W.planted_geometric(600, 500, 30.0, seed=1)[0])
+    out = icur.run(torch.from_numpy(A32).cuda(), 1e-4, 91, alpha=1e-10)   # c = 100
+    assert out["info"]["threshold"] == pytest.approx(1e-4 / 4.98, rel=1e-3)
+    assert out["rho"] <= 1e-4 / 4.98
+
+
+def test_strided_input_leading_dimension(icur):
+    big = torch.from_numpy(W.to_f32(W.rbf(600, 900, 4))[0]).cuda()
+    view = big[:, :700]                     # lda = 900 > n = 700
+    A32 = np.ascontiguousarray(big.cpu().numpy()[:, :700])
+    a = icur.run(view, 1e-4, 12, 0, 2)
+    b = icur.run(torch.from_numpy(A32).cuda(), 1e-4, 12, 0, 2)
+    assert a["J"].tolist() == b["J"].tolist() and a["I"].tolist() == b["I"].tolist()
