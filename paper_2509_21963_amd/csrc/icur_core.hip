@@ -100,7 +100,9 @@ __global__ void dcopy2d_kernel(int64_t M, int64_t N, double alpha, const double*
 }
 
 // In-place inverse of the k x k matrix N by Gauss-Jordan elimination with partial
-// pivoting (row interchanges, undone as column interchanges at the end).
+// pivoting (row interchanges, undone as column interchanges at the end).  One workgroup
+// of 1024 threads: thread t owns column t % k of the rows t / k, t / k + g, ... (g row
+// groups), so every elimination sweep is coalesced in LDS and needs no division.
 __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ Ng, int k, int use_lds,
                                                           double* __restrict__ work,
                                                           int* __restrict__ info,
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
   extern __shared__ double sm[];
   __shared__ int perm[512];
   __shared__ double fcol[512];
+  __shared__ double prow[512];
   __shared__ double red_v[16];
   __shared__ int red_i[16];
   __shared__ int bp;
@@ -115,15 +118,17 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
   double* a = use_lds ? sm : work;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int ng = nt / k;                      // row groups (>= 2 for k <= 512)
+  const int col = tid % k, grp = tid / k;     // this thread's column and row group
+  const bool active = grp < ng;
   for (int e = tid; e < k * k; e += nt) a[e] = Ng[e];
   __syncthreads();
-  // ||N||_1 (max column sum)
-  {
+  auto colnorm_max = [&](int slot) {
     double cs = 0.0;
-    for (int j = tid; j < k; j += nt) {
+    if (tid < k) {
       double s = 0.0;
-      for (int i = 0; i < k; ++i) s += fabs(a[i * k + j]);
-      cs = fmax(cs, s);
+      for (int i = 0; i < k; ++i) s += fabs(a[i * k + tid]);
+      cs = s;
     }
     for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
     if (lane == 0) red_v[wave] = cs;
@@ -131,11 +136,13 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
     if (tid == 0) {
       double m = 0.0;
       for (int w = 0; w < nw; ++w) m = fmax(m, red_v[w]);
-      norms[0] = m;
+      norms[slot] = m;
     }
     __syncthreads();
-  }
+  };
+  colnorm_max(0);
   for (int j = 0; j < k; ++j) {
+    // pivot: largest |a[i][j]| over rows i >= j, lowest index on ties
     double bv = -1.0;
     int bi = 0x7fffffff;
     for (int i = j + tid; i < k; i += nt) {
@@ -176,27 +183,36 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
       return;
     }
     const int p = bp;
-    if (p != j)
-      for (int c = tid; c < k; c += nt) {
-        const double t = a[j * k + c];
-        a[j * k + c] = a[p * k + c];
-        a[p * k + c] = t;
+    // swap rows j and p, then scale the pivot row; keep column j and the pivot row
+    if (tid < k) {
+      double rj = a[j * k + tid], rp = a[p * k + tid];
+      if (p != j) {
+        a[j * k + tid] = rp;
+        a[p * k + tid] = rj;
+        rj = rp;
       }
+      prow[tid] = rj;
+    }
     __syncthreads();
-    const double piv = a[j * k + j];
+    const double pinv = 1.0 / prow[j];
+    if (tid < k) {
+      fcol[tid] = (tid == j) ? 0.0 : a[tid * k + j];
+      const double v = (tid == j) ? pinv : prow[tid] * pinv;
+      a[j * k + tid] = v;
+    }
     __syncthreads();
-    for (int c = tid; c < k; c += nt) a[j * k + c] = (c == j) ? 1.0 / piv : a[j * k + c] / piv;
-    for (int i = tid; i < k; i += nt) fcol[i] = a[i * k + j];
+    if (tid < k) prow[tid] = a[j * k + tid];
     __syncthreads();
-    const double pjj = a[j * k + j];
-    for (int e = tid; e < k * k; e += nt) {
-      const int i = e / k, c = e % k;
-      if (i == j) continue;
-      const double f = fcol[i];
-      if (c == j)
-        a[e] = -f * pjj;
-      else
-        a[e] = a[e] - f * a[j * k + c];
+    // eliminate column j from every other row
+    if (active) {
+      const double pc = prow[col];
+      const bool isj = (col == j);
+      for (int i = grp; i < k; i += ng) {
+        if (i == j) continue;
+        const double f = fcol[i];
+        double* e = a + i * k + col;
+        *e = isj ? -f * pc : *e - f * pc;
+      }
     }
     __syncthreads();
   }
@@ -211,23 +227,8 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
     __syncthreads();
   }
   for (int e = tid; e < k * k; e += nt) Ng[e] = a[e];
-  {
-    double cs = 0.0;
-    for (int j = tid; j < k; j += nt) {
-      double s = 0.0;
-      for (int i = 0; i < k; ++i) s += fabs(a[i * k + j]);
-      cs = fmax(cs, s);
-    }
-    for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
-    if (lane == 0) red_v[wave] = cs;
-    __syncthreads();
-    if (tid == 0) {
-      double m = 0.0;
-      for (int w = 0; w < nw; ++w) m = fmax(m, red_v[w]);
-      norms[1] = m;
-      *info = 0;
-    }
-  }
+  colnorm_max(1);
+  if (tid == 0) *info = 0;
 }
 
 }  // namespace

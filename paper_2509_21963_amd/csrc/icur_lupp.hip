@@ -69,16 +69,17 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
 
-// Returns false when the barrier could not complete (fault); all threads agree.
+// Returns false when the barrier could not complete (fault); all threads agree.  The
+// arrival is a release add and the wait an acquire, both at device scope, so the slot
+// writes before the barrier are visible to every workgroup after it.
 __device__ bool grid_barrier(unsigned* bar, unsigned target, int* fault, int* flag_lds) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(bar, 1u);
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
       if ((++spins & 255u) == 0 &&
           __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         ok = 0;
@@ -90,7 +91,7 @@ __device__ bool grid_barrier(unsigned* bar, unsigned target, int* fault, int* fl
         break;
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *flag_lds = ok;
   }
   __syncthreads();
@@ -372,7 +373,10 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   if (steps > w.steps_cap || N > w.N_cap) return arg_error("lupp: workspace too small");
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
+  // Rows per thread: the grid barrier's cost grows with the number of workgroups, so
+  // pack up to 8 candidate rows per thread and aim for about 16 workgroups.
   int R = 1;
+  while (R < 8 && static_cast<int64_t>(R) * kLT * 16 < N) R *= 2;
   while (R <= 8 && static_cast<int64_t>(R) * kLT * dev.num_cus < N) R *= 2;
   if (R > 8) {
     set_error("lupp: N exceeds the candidates one grid can hold in registers");
