@@ -90,10 +90,13 @@ int launch_reduce_partials(const double* partials, int n, double* out, hipStream
 
 // ----- selection (icur_lupp.hip) -----
 struct LuppWork {
-  double* L;          // steps_cap x N_cap
+  double* L;          // steps_cap x N_cap multipliers
+  double* P;          // 16 x N_cap: the current panel
+  double* U;          // steps_cap x steps_cap: extended pivot rows
+  uint8_t* chosen;    // N_cap flags
   void* slots;        // 2 * max_groups slot records
-  unsigned* barrier;  // 1 counter
-  int* status;        // [0] npiv, [1] fault flag
+  unsigned* ctl;      // barrier counter and status words, cleared by every call
+  int* status;        // [0] npiv, [1] fault flag, [2] ended early (inside ctl)
   int64_t steps_cap, N_cap;
 };
 size_t lupp_workspace_bytes(int64_t steps, int64_t N);

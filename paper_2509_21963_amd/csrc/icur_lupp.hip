@@ -9,16 +9,27 @@
 // rounded operations as the unblocked algorithm, so the pivots equal those of a plain
 // FP64 LUPP on the same input, ties going to the lowest index.
 //
-// Schedule.  One persistent cooperative grid (<= one workgroup per CU).  Candidate rows
-// are spread over the grid, R rows per thread, and the current 16-column panel of each
-// row lives in registers.  Each pivot step is
-//   local argmax (wave shuffle + LDS)  ->  publish (|value|, index, panel row) into a
-//   per-workgroup slot  ->  one grid barrier  ->  every workgroup reduces the slots
-//   itself, reads the winner's panel row and applies the rank-one update.
-// At a panel boundary each workgroup rebuilds the previous pivots' rows restricted to the
-// new panel (a right-looking triangular recurrence in LDS, same operation order) and
-// applies all previous updates to its own rows, reading the stored multipliers.
+// Schedule, per panel of 16 pivot columns [t0, t0 + 16):
+//   prep kernel (all CUs)  every live candidate row gets the panel's 16 entries with all
+//       t0 previous updates applied (left-looking, multipliers read from L), written to
+//       the panel buffer P.  The pivot rows of the previous panel are first extended to
+//       every later column (a 16-row triangular recurrence per column, kept in U), so
+//       that the previous pivot rows restricted to this panel are available in LDS.
+//   panel kernel (one persistent grid, <= one workgroup per CU)  the 16 pivot steps on
+//       P held in registers, R rows per thread:
+//         local argmax (DPP within waves, LDS across them)  ->  the owner publishes
+//         (|value|, index, panel row) into its workgroup's slot and arrives at the grid
+//         barrier (release)  ->  every workgroup reads all slots and reduces them
+//         itself  ->  rank-one update.  One grid-wide exchange per step.
+//       The multipliers replace the consumed panel entries in registers and are
+//       written to L once, at the end of the panel.
+// The panel grid is an ordinary dispatch (a cooperative launch costs about 10 us more
+// per panel): at most one workgroup per CU, each within one CU's resources, so every
+// workgroup is resident once dispatched, and work of other streams only delays that.
+// Every wait is bounded; a wait that runs out sets a fault flag that ends the call
+// with an error instead of a hang.
 #include <algorithm>
+#include <climits>
 #include <utility>
 
 #include "icur_internal.h"
@@ -29,28 +40,47 @@ namespace icur {
 namespace {
 
 constexpr int kPW = 16;          // panel width
-constexpr int kLT = 256;         // threads per workgroup
-constexpr int kMaxSteps = 1024;  // LDS holds the previous pivot rows of one panel
+constexpr int kPT = 256;         // threads per workgroup of the prep kernel (= 16 x 16)
+constexpr int kMaxSteps = 1024;  // LDS of the prep kernel holds t0 x 16 pivot-row entries
+constexpr int kMaxGroups = 256;  // panel-kernel workgroups (one per CU at most)
 constexpr unsigned kSpinLimit = 1u << 22;
+constexpr size_t kCtlBytes = 256;  // barrier counter (word 0), status words (from byte 128)
 
 struct Slot {
-  double val;  // |best entry| of the workgroup, -1 if it has no eligible candidate
+  double val;  // |best entry| of the workgroup, 0 if it has no candidate with a nonzero entry
   long long idx;
   double row[kPW];
 };
 
-struct Args {
-  const void* X;  // FP32 or FP64 (InT)
+// Device view of the workspace.
+struct Work {
+  double* L;        // steps x N: row t holds the multipliers of step t
+  double* P;        // kPW x N: the current panel with all previous updates applied
+  double* U;        // steps x steps: row k = pivot row of step k at the columns after its panel
+  uint8_t* chosen;  // N: 1 once the candidate has been chosen as a pivot
+  Slot* slots;      // 2 x kMaxGroups, by step parity
+  unsigned* bar;    // grid barrier counter: G arrivals per step
+  int* status;      // [0] pivots found, [1] fault flag, [2] ended early
+  int64_t* piv;     // steps
+};
+
+struct PrepArgs {
+  const void* X;
   int64_t ldx;
-  int K;
   int N;
   int steps;
+  int t0;
+  int ncand;  // workgroups that prepare candidate rows; the rest extend pivot rows
   const uint8_t* excl;
-  double* L;  // steps x N multipliers
-  Slot* slots;  // 2 x gridDim.x
-  unsigned* bar;
-  int* status;  // [0] pivots found, [1] fault flag
-  int64_t* piv;
+  Work w;
+};
+
+struct PanelArgs {
+  int N;
+  int steps;
+  int t0;
+  const uint8_t* excl;
+  Work w;
 };
 
 // Calls f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>): the
@@ -69,297 +99,425 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
 
-// Returns false when the barrier could not complete (fault); all threads agree.  The
-// arrival is a release add and the wait an acquire, both at device scope, so the slot
-// writes before the barrier are visible to every workgroup after it.
-__device__ bool grid_barrier(unsigned* bar, unsigned target, int* fault, int* flag_lds) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 255u) == 0 &&
-          __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        ok = 0;
-        break;
-      }
-      if (spins > kSpinLimit) {
-        atomicExch(fault, 1);
-        ok = 0;
-        break;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *flag_lds = ok;
-  }
-  __syncthreads();
-  return *flag_lds != 0;
+// ---------------------------------------------------------------------------------
+// prep kernel
+// ---------------------------------------------------------------------------------
+// Multipliers of candidate `row` at steps k0 .. k0+15 (coalesced across threads).
+__device__ __forceinline__ void load_l16(const double* L, int N, int k0, int64_t row, double* out) {
+#pragma unroll
+  for (int u = 0; u < kPW; ++u) out[u] = L[static_cast<int64_t>(k0 + u) * N + row];
 }
 
-template <int R, typename InT>
-__global__ __launch_bounds__(kLT, 1) void lupp_kernel(const Args a) {
-  const InT* Xin = static_cast<const InT*>(a.X);
-  extern __shared__ double dyn[];
-  double* Upan = dyn;                                               // steps x kPW
-  int* pivs = reinterpret_cast<int*>(dyn + static_cast<size_t>(a.steps) * kPW);  // steps
-  __shared__ double red_v[kLT / 64];
-  __shared__ int red_i[kLT / 64];
-  __shared__ int red_w[kLT / 64];
-  __shared__ double u_sh[kPW];
-  __shared__ int bcast_i;
-  __shared__ int bcast_w;
-  __shared__ double bcast_v;
+template <typename InT>
+__global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
+  if (a.w.status[1] != 0 || a.w.status[2] != 0) return;  // fault, or no pivots left
+  const InT* X = static_cast<const InT*>(a.X);
+  extern __shared__ double Upan[];  // t0 x kPW: pivot rows 0..t0-1 at 16 columns
+  const int tid = threadIdx.x;
+  const int N = a.N, t0 = a.t0, steps = a.steps;
+  const bool cand = static_cast<int>(blockIdx.x) < a.ncand;
+  const int col0 = cand ? t0 : t0 + kPW * (static_cast<int>(blockIdx.x) - a.ncand + 1);
+
+  if (t0 > 0) {
+    const int nb = t0 - kPW;  // the previous panel's pivots are steps nb .. t0-1
+    // (1) older pivot rows at these columns, extended by earlier launches
+    for (int e = tid; e < nb * kPW; e += kPT) {
+      const int k = e / kPW, jj = e % kPW;
+      const int col = col0 + jj;
+      Upan[e] = col < steps ? a.w.U[static_cast<int64_t>(k) * steps + col] : 0.0;
+    }
+    __syncthreads();
+    // (2) the previous panel's pivot rows at these columns.  Thread (jj, q) owns column
+    // col0 + jj of the pivot row of step nb + q; the 16 rows of one column sit in one
+    // wave, so the recurrence among them runs on shuffles without block barriers.
+    const int jj = tid >> 4, q = tid & 15;
+    const int lane = tid & 63;
+    const int col = col0 + jj;
+    const int64_t p = a.w.piv[nb + q];
+    double acc = 0.0;
+    if (col < steps) {
+      acc = static_cast<double>(X[static_cast<int64_t>(col) * a.ldx + p]);
+      // nb is a multiple of 16: multipliers are fetched 16 steps ahead of their use
+      double lc[kPW], ln[kPW];
+      if (nb > 0) load_l16(a.w.L, N, 0, p, lc);
+      for (int kb = 0; kb < nb; kb += kPW) {
+        if (kb + kPW < nb) load_l16(a.w.L, N, kb + kPW, p, ln);
+#pragma unroll
+        for (int u = 0; u < kPW; ++u) {
+          const double prod = lc[u] * Upan[(kb + u) * kPW + jj];
+          acc = acc - prod;
+        }
+#pragma unroll
+        for (int u = 0; u < kPW; ++u) lc[u] = ln[u];
+      }
+    }
+    double lq[kPW - 1];
+#pragma unroll
+    for (int qq = 0; qq < kPW - 1; ++qq)
+      lq[qq] = (qq < q && col < steps) ? a.w.L[static_cast<int64_t>(nb + qq) * N + p] : 0.0;
+#pragma unroll
+    for (int qq = 0; qq < kPW - 1; ++qq) {
+      const double u = __shfl(acc, (lane & 48) | qq, 64);  // row nb + qq, final by now
+      if (q > qq) {
+        const double prod = lq[qq] * u;
+        acc = acc - prod;
+      }
+    }
+    Upan[(nb + q) * kPW + jj] = acc;
+    if (!cand && col < steps) a.w.U[static_cast<int64_t>(nb + q) * steps + col] = acc;
+    __syncthreads();
+  }
+  if (!cand) return;
+
+  // (3) candidate rows: the panel entries with all t0 previous updates, in step order
+  const int i = static_cast<int>(blockIdx.x) * kPT + tid;
+  if (i >= N) return;
+  if (t0 == 0) a.w.chosen[i] = 0;
+  if ((a.excl && a.excl[i]) || (t0 > 0 && a.w.chosen[i])) return;
+  const int pw = min(kPW, steps - t0);
+  double x[kPW];
+#pragma unroll
+  for (int jj = 0; jj < kPW; ++jj)
+    x[jj] = jj < pw ? static_cast<double>(X[static_cast<int64_t>(t0 + jj) * a.ldx + i]) : 0.0;
+  // t0 is a multiple of 16: multipliers are fetched 16 steps ahead of their use
+  double lc[kPW], ln[kPW];
+  if (t0 > 0) load_l16(a.w.L, N, 0, i, lc);
+  for (int kb = 0; kb < t0; kb += kPW) {
+    if (kb + kPW < t0) load_l16(a.w.L, N, kb + kPW, i, ln);
+#pragma unroll
+    for (int u = 0; u < kPW; ++u) {
+      const double* up = Upan + (kb + u) * kPW;
+#pragma unroll
+      for (int jj = 0; jj < kPW; ++jj) {
+        const double prod = lc[u] * up[jj];
+        x[jj] = x[jj] - prod;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPW; ++u) lc[u] = ln[u];
+  }
+#pragma unroll
+  for (int jj = 0; jj < kPW; ++jj) a.w.P[static_cast<int64_t>(jj) * N + i] = x[jj];
+}
+
+// ---------------------------------------------------------------------------------
+// panel kernel
+// ---------------------------------------------------------------------------------
+
+// Argmax keys: the bit pattern of |value|, which orders non-negative doubles like their
+// values; key 0 stands for "no candidate with a nonzero value".
+__device__ __forceinline__ unsigned long long cand_key(double v) {
+  return v > 0.0 ? static_cast<unsigned long long>(__double_as_longlong(v)) : 0ull;
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(x & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(x >> 32), CTRL, 0xF, 0xF, false);
+  return (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo);
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int lane) {
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(x & 0xffffffffull), lane));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(x >> 32), lane));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// Wave-wide argmax (every lane of the wave must be active): the largest key, the lowest
+// index among the lanes holding it and that lane's tag w.  The maximum is taken with DPP
+// moves inside each row of 16 lanes (quad permutations, then row rotations by 4 and 8)
+// and across the four rows with lane reads; the winning lane comes from a ballot.
+__device__ __forceinline__ void wave_argmax(unsigned long long k, int i, int w, unsigned long long* wk,
+                                            int* wi, int* ww) {
+  unsigned long long m = k, o;
+  o = dpp_u64<0xB1>(m);   // quad_perm [1,0,3,2]
+  m = o > m ? o : m;
+  o = dpp_u64<0x4E>(m);   // quad_perm [2,3,0,1]
+  m = o > m ? o : m;
+  o = dpp_u64<0x124>(m);  // row_ror 4
+  m = o > m ? o : m;
+  o = dpp_u64<0x128>(m);  // row_ror 8
+  m = o > m ? o : m;
+  unsigned long long best = readlane_u64(m, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    const unsigned long long r = readlane_u64(m, 16 * row);
+    best = r > best ? r : best;
+  }
+  *wk = best;
+  *wi = INT_MAX;
+  *ww = -1;
+  if (best == 0ull) return;
+  unsigned long long lanes = __ballot(k == best);
+  int lane = __builtin_ctzll(lanes);
+  int bi = __builtin_amdgcn_readlane(i, lane);
+  int bw = __builtin_amdgcn_readlane(w, lane);
+  lanes &= lanes - 1;
+  while (lanes) {  // equal keys in several lanes (rare): lowest index
+    lane = __builtin_ctzll(lanes);
+    const int i2 = __builtin_amdgcn_readlane(i, lane);
+    if (i2 < bi) {
+      bi = i2;
+      bw = __builtin_amdgcn_readlane(w, lane);
+    }
+    lanes &= lanes - 1;
+  }
+  *wi = bi;
+  *ww = bw;
+}
+
+struct Red {
+  unsigned long long k;
+  int i, w;
+};
+
+// Workgroup-wide argmax over (key, index, tag), ties to the lowest index; every thread gets
+// the result.  red holds LT / 64 entries; one __syncthreads.
+template <int LT>
+__device__ __forceinline__ void block_argmax(unsigned long long k, int i, int w, Red* red,
+                                             unsigned long long* gk, int* gi, int* gw) {
+  unsigned long long wk;
+  int wi, ww;
+  wave_argmax(k, i, w, &wk, &wi, &ww);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = Red{wk, wi, ww};
+  __syncthreads();
+  Red b = red[0];
+#pragma unroll
+  for (int q = 1; q < LT / 64; ++q) {
+    const Red c = red[q];
+    if (c.k > b.k || (c.k == b.k && c.i < b.i)) b = c;
+  }
+  *gk = b.k;
+  *gi = b.i;
+  *gw = b.w;
+}
+
+template <int R, int LT>
+__global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
+  static_assert(LT >= kMaxGroups, "one thread per slot in the slot reduction");
+  // two sets of reduction scratch: the workgroup argmax (a) and the slot reduction (d)
+  // of one step use different sets, so neither needs an extra barrier before reuse
+  __shared__ Red red[2][LT / 64];
+  __shared__ double rows_sh[kMaxGroups * kPW];  // published panel rows of all workgroups
+  __shared__ long long piv_sh[kPW];
   __shared__ int flag;
 
+  // A previous panel ended the factorization (or faulted): every workgroup reads the
+  // same values, so the whole grid leaves together.
+  if (a.w.status[1] != 0 || a.w.status[2] != 0) return;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
   const int G = gridDim.x;
-  const int N = a.N;
+  const int N = a.N, t0 = a.t0;
+  const int pw = min(kPW, a.steps - t0);
 
   int rowid[R];
   unsigned alive = 0;  // bit r: row r is a valid, eligible, not yet chosen candidate
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    rowid[r] = (static_cast<int>(blockIdx.x) * R + r) * kLT + tid;
-    if (rowid[r] < N && !(a.excl && a.excl[rowid[r]])) alive |= 1u << r;
+    rowid[r] = (static_cast<int>(blockIdx.x) * R + r) * LT + tid;
+    if (rowid[r] < N && !(a.excl && a.excl[rowid[r]]) && !a.w.chosen[rowid[r]]) alive |= 1u << r;
   }
+  const unsigned alive0 = alive;
+  unsigned cstep = 0;  // 4 bits per row: the panel step at which row r became a pivot
   double x[R][kPW];
-  unsigned epoch = 0;
-  int found = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool live = (alive >> r) & 1u;
+#pragma unroll
+    for (int jj = 0; jj < kPW; ++jj)
+      x[r][jj] = (live && jj < pw) ? a.w.P[static_cast<int64_t>(jj) * N + rowid[r]] : 0.0;
+  }
+  int found = t0;
   bool stop = false;
 
-  for (int t0 = 0; t0 < a.steps && !stop; t0 += kPW) {
-    const int pw = min(kPW, a.steps - t0);
-    // (1) previous pivot rows restricted to this panel, rebuilt in LDS with the same
-    //     sequence of rounded updates they received in the unblocked algorithm.
-    if (t0 > 0) {
-      for (int e = tid; e < t0 * kPW; e += kLT) {
-        const int k = e / kPW, jj = e % kPW;
-        Upan[e] = (jj < pw) ? static_cast<double>(Xin[static_cast<int64_t>(t0 + jj) * a.ldx + pivs[k]]) : 0.0;
-      }
-      __syncthreads();
-      for (int kp = 0; kp + 1 < t0; ++kp) {
-        const int rows_left = t0 - kp - 1;
-        for (int e = tid; e < rows_left * pw; e += kLT) {
-          const int k = kp + 1 + e / pw, jj = e % pw;
-          const double l = a.L[static_cast<int64_t>(kp) * N + pivs[k]];
-          const double prod = l * Upan[kp * kPW + jj];
-          Upan[k * kPW + jj] = Upan[k * kPW + jj] - prod;
-        }
-        __syncthreads();
-      }
-    }
-    // (2) own rows: load the panel and apply all previous updates in step order.
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const bool live = (alive >> r) & 1u;
-#pragma unroll
-      for (int jj = 0; jj < kPW; ++jj)
-        x[r][jj] = (live && jj < pw) ? static_cast<double>(Xin[static_cast<int64_t>(t0 + jj) * a.ldx + rowid[r]]) : 0.0;
-    }
-    for (int kp = 0; kp < t0; ++kp) {
-      double u[kPW];
-#pragma unroll
-      for (int jj = 0; jj < kPW; ++jj) u[jj] = Upan[kp * kPW + jj];
+  static_for<kPW>([&](auto ttc) {
+    constexpr int tt = decltype(ttc)::value;
+    if (!stop && tt < pw) {
+      const int t = t0 + tt;
+      // (a) local argmax, then the workgroup's best
+      double bv = -1.0;
+      int bi = INT_MAX;
+      int br = -1;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const bool live = (alive >> r) & 1u;
-        const double l = live ? a.L[static_cast<int64_t>(kp) * N + rowid[r]] : 0.0;
-#pragma unroll
-        for (int jj = 0; jj < kPW; ++jj) {
-          const double prod = l * u[jj];
-          x[r][jj] = x[r][jj] - prod;
+        const double v = fabs(x[r][tt]);
+        if (((alive >> r) & 1u) && better(v, rowid[r], bv, bi)) {
+          bv = v;
+          bi = rowid[r];
+          br = r;
         }
       }
-    }
-    // (3) the pivot steps of this panel (every register index is static).
-    static_for<kPW>([&](auto ttc) {
-      constexpr int tt = decltype(ttc)::value;
-      if (!stop && tt < pw) {
-        const int t = t0 + tt;
-        // (a) local argmax
-        double bv = -1.0;
-        int bi = 0x7fffffff;
-        int br = -1;
+      unsigned long long gk;
+      int gi, gw;
+      block_argmax<LT>(cand_key(bv), bi, 0, red[0], &gk, &gi, &gw);
+      // (b) the owner (or thread 0 when the workgroup has no candidate) publishes the
+      // slot and arrives at the grid barrier; the release orders its slot stores.
+      Slot* slot = a.w.slots + (t & 1) * kMaxGroups + blockIdx.x;
+      const bool owner = gk != 0ull && br >= 0 && bi == gi;
+      if (owner) {
+        // select row br with bit masks (a read x[br] with a run-time index would force x
+        // into scratch memory); entries before tt are no longer needed
+        unsigned long long pub[kPW];
+#pragma unroll
+        for (int jj = tt; jj < kPW; ++jj) pub[jj] = 0ull;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double v = fabs(x[r][tt]);
-          if (((alive >> r) & 1u) && better(v, rowid[r], bv, bi)) {
-            bv = v;
-            bi = rowid[r];
-            br = r;
+          const unsigned long long mask = (r == br) ? ~0ull : 0ull;
+#pragma unroll
+          for (int jj = tt; jj < kPW; ++jj)
+            pub[jj] |= static_cast<unsigned long long>(__double_as_longlong(x[r][jj])) & mask;
+        }
+#pragma unroll
+        for (int jj = tt; jj < kPW; ++jj) slot->row[jj] = __longlong_as_double(static_cast<long long>(pub[jj]));
+        slot->val = __longlong_as_double(static_cast<long long>(gk));
+        slot->idx = gi;
+      } else if (gk == 0ull && tid == 0) {
+        slot->val = 0.0;
+        slot->idx = INT_MAX;
+      }
+      if (owner || (gk == 0ull && tid == 0))
+        __hip_atomic_fetch_add(a.w.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      // (c) wait for every workgroup's arrival (thread 0 polls, bounded)
+      if (tid == 0) {
+        const unsigned target = static_cast<unsigned>(t + 1) * static_cast<unsigned>(G);
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(a.w.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          __builtin_amdgcn_s_sleep(1);
+          if ((++spins & 255u) == 0 &&
+              __hip_atomic_load(a.w.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = 0;
+            break;
+          }
+          if (spins > kSpinLimit) {
+            atomicExch(a.w.status + 1, 1);
+            ok = 0;
+            break;
           }
         }
-        double wv = bv;
-        int wi = bi;
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(wv, off, 64);
-          const int oi = __shfl_xor(wi, off, 64);
-          if (better(ov, oi, wv, wi)) {
-            wv = ov;
-            wi = oi;
-          }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        flag = ok;
+      }
+      __syncthreads();
+      if (!flag) {
+        stop = true;
+      } else {
+        // (d) read every slot (header and row in one round trip) and reduce
+        const Slot* sl = a.w.slots + (t & 1) * kMaxGroups;
+        for (int e = tid; e < G * kPW; e += LT)
+          rows_sh[e] = __hip_atomic_load(&sl[e / kPW].row[e % kPW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long ck = 0ull;
+        int ci = INT_MAX, cw = -1;
+        if (tid < G) {
+          ck = cand_key(__hip_atomic_load(&sl[tid].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          ci = static_cast<int>(__hip_atomic_load(&sl[tid].idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          cw = tid;
         }
-        if (lane == 0) {
-          red_v[wave] = wv;
-          red_i[wave] = wi;
-        }
-        __syncthreads();
-        if (tid == 0) {
-          double gv = red_v[0];
-          int gi = red_i[0];
-          for (int w = 1; w < kLT / 64; ++w)
-            if (better(red_v[w], red_i[w], gv, gi)) {
-              gv = red_v[w];
-              gi = red_i[w];
-            }
-          bcast_v = gv;
-          bcast_i = gi;
-        }
-        __syncthreads();
-        // (b) publish: the owner writes its panel row, thread 0 the header.
-        Slot* slot = a.slots + (t & 1) * G + blockIdx.x;
-        if (bcast_v >= 0.0 && br >= 0 && bi == bcast_i) {
-          // select row br with bit masks (an indexed read x[br] would force x into memory)
-          unsigned long long pub[kPW];
+        block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);  // its barrier also publishes rows_sh
+        if (gk == 0ull) stop = true;  // none left, or an exact zero column
+      }
+      if (!stop) {
+        if (tid == 0) piv_sh[tt] = gi;
+        found = t + 1;
+        const int p = gi;
+        // (e) rank-one update of the remaining panel columns; the multiplier replaces
+        // the consumed entry x[r][tt]
+        const double* u = rows_sh + gw * kPW;
+        const double upiv = u[tt];
+        double uu[kPW];
 #pragma unroll
-          for (int jj = 0; jj < kPW; ++jj) pub[jj] = 0ull;
+        for (int jj = tt + 1; jj < kPW; ++jj) uu[jj] = u[jj];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const unsigned long long mask = (r == br) ? ~0ull : 0ull;
+        for (int r = 0; r < R; ++r) {
+          if (((alive >> r) & 1u) && rowid[r] == p) {
+            alive &= ~(1u << r);
+            cstep |= static_cast<unsigned>(tt) << (4 * r);
+          }
+          // Unconditional (no register selects): on a row that is not live the update
+          // only touches entries that are never read again (its multipliers before the
+          // step it was chosen at stay as they are; rows that never were live hold 0).
+          const double l = x[r][tt] / upiv;
+          x[r][tt] = l;
 #pragma unroll
-            for (int jj = 0; jj < kPW; ++jj)
-              pub[jj] |= static_cast<unsigned long long>(__double_as_longlong(x[r][jj])) & mask;
-          }
-#pragma unroll
-          for (int jj = 0; jj < kPW; ++jj) slot->row[jj] = __longlong_as_double(static_cast<long long>(pub[jj]));
-          __threadfence();
-        }
-        __syncthreads();
-        if (tid == 0) {
-          slot->val = bcast_v;
-          slot->idx = bcast_i;
-        }
-        // (c) one grid barrier per pivot step
-        ++epoch;
-        if (!grid_barrier(a.bar, epoch * static_cast<unsigned>(G), a.status + 1, &flag)) stop = true;
-        if (!stop) {
-          // (d) every workgroup reduces the published candidates itself
-          double cv = -1.0;
-          int ci = 0x7fffffff, cw = -1;
-          for (int w = tid; w < G; w += kLT) {
-            const Slot* s = a.slots + (t & 1) * G + w;
-            const double v = __hip_atomic_load(&s->val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int i = static_cast<int>(__hip_atomic_load(&s->idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (v >= 0.0 && better(v, i, cv, ci)) {
-              cv = v;
-              ci = i;
-              cw = w;
-            }
-          }
-          for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(cv, off, 64);
-            const int oi = __shfl_xor(ci, off, 64);
-            const int ow = __shfl_xor(cw, off, 64);
-            if (ow >= 0 && (cw < 0 || better(ov, oi, cv, ci))) {
-              cv = ov;
-              ci = oi;
-              cw = ow;
-            }
-          }
-          if (lane == 0) {
-            red_v[wave] = cv;
-            red_i[wave] = ci;
-            red_w[wave] = cw;
-          }
-          __syncthreads();
-          if (tid == 0) {
-            double gv = -1.0;
-            int gi = 0x7fffffff, gw = -1;
-            for (int w = 0; w < kLT / 64; ++w)
-              if (red_w[w] >= 0 && (gw < 0 || better(red_v[w], red_i[w], gv, gi))) {
-                gv = red_v[w];
-                gi = red_i[w];
-                gw = red_w[w];
-              }
-            bcast_v = gv;
-            bcast_i = gi;
-            bcast_w = gw;
-          }
-          __syncthreads();
-          if (bcast_w < 0 || !(bcast_v > 0.0)) stop = true;  // none left, or exact zero
-        }
-        if (!stop) {
-          if (tid < kPW) {
-            const Slot* s = a.slots + (t & 1) * G + bcast_w;
-            u_sh[tid] = __hip_atomic_load(&s->row[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-          if (tid == 0) {
-            pivs[t] = bcast_i;
-            if (blockIdx.x == 0) a.piv[t] = bcast_i;
-          }
-          __syncthreads();
-          found = t + 1;
-          const int p = bcast_i;
-          // (e) rank-one update of the remaining panel columns; store the multipliers
-          const double upiv = u_sh[tt];
-          double u[kPW];
-#pragma unroll
-          for (int jj = tt + 1; jj < kPW; ++jj) u[jj] = u_sh[jj];
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (((alive >> r) & 1u) && rowid[r] == p) alive &= ~(1u << r);
-            if ((alive >> r) & 1u) {
-              const double l = x[r][tt] / upiv;
-              a.L[static_cast<int64_t>(t) * N + rowid[r]] = l;
-#pragma unroll
-              for (int jj = tt + 1; jj < kPW; ++jj) {
-                const double prod = l * u[jj];
-                x[r][jj] = x[r][jj] - prod;
-              }
-            }
+          for (int jj = tt + 1; jj < kPW; ++jj) {
+            const double prod = l * uu[jj];
+            x[r][jj] = x[r][jj] - prod;
           }
         }
       }
-    });
+      // rows_sh, flag and red[1] are rewritten by the next step only after the barrier
+      // inside its first block_argmax, which every thread reaches after finishing this
+      // update; red[0] only after the barrier of (c)
+    }
+  });
+
+  // multipliers of this panel: every step for live rows, the steps before their own
+  // for the rows chosen as pivots here
+  const int done = found - t0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if ((alive0 >> r) & 1u) {
+      const bool piv_row = !((alive >> r) & 1u);
+      const int nl = piv_row ? static_cast<int>((cstep >> (4 * r)) & 15u) : done;
+#pragma unroll
+      for (int jj = 0; jj < kPW; ++jj)
+        if (jj < nl) a.w.L[static_cast<int64_t>(t0 + jj) * N + rowid[r]] = x[r][jj];
+      if (piv_row) a.w.chosen[rowid[r]] = 1;
+    }
+  }
+  if (blockIdx.x == 0) {
     __syncthreads();
-  }
-  if (blockIdx.x == 0 && tid == 0) a.status[0] = found;
-}
-
-using LuppFn = void (*)(const Args);
-
-template <typename InT>
-LuppFn pick_t(int R) {
-  switch (R) {
-    case 1: return lupp_kernel<1, InT>;
-    case 2: return lupp_kernel<2, InT>;
-    case 4: return lupp_kernel<4, InT>;
-    case 8: return lupp_kernel<8, InT>;
-    default: return nullptr;
+    if (tid < done) a.w.piv[t0 + tid] = piv_sh[tid];
+    if (tid == 0) {
+      a.w.status[0] = found;
+      if (stop) a.w.status[2] = 1;
+    }
   }
 }
+
+using PanelFn = void (*)(const PanelArgs);
+
+// Candidate rows per workgroup = R * LT: 256, 512, 1024, then 2048 (four rows per thread
+// on 512 threads, two waves per SIMD, which keeps each wave within 256 registers).
+struct PanelShape {
+  int R, LT;
+  PanelFn fn;
+};
+constexpr int kShapes = 4;
+const PanelShape kShape[kShapes] = {{1, 256, lupp_panel<1, 256>},
+                                    {2, 256, lupp_panel<2, 256>},
+                                    {4, 256, lupp_panel<4, 256>},
+                                    {4, 512, lupp_panel<4, 512>}};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
 size_t lupp_workspace_bytes(int64_t steps, int64_t N) {
-  const size_t L = static_cast<size_t>(steps) * N * sizeof(double);
-  const size_t slots = 2 * 1024 * sizeof(Slot);
-  return ((L + 255) & ~size_t(255)) + ((slots + 255) & ~size_t(255)) + 256 + 256;
+  return align256(static_cast<size_t>(steps) * N * sizeof(double)) +      // L
+         align256(static_cast<size_t>(kPW) * N * sizeof(double)) +        // P
+         align256(static_cast<size_t>(steps) * steps * sizeof(double)) +  // U
+         align256(static_cast<size_t>(N)) +                               // chosen
+         align256(2 * kMaxGroups * sizeof(Slot)) +                        // slots
+         kCtlBytes;                                                       // barrier, status
 }
 
 int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w) {
   char* p = static_cast<char*>(base);
-  const size_t L = static_cast<size_t>(steps) * N * sizeof(double);
   w->L = reinterpret_cast<double*>(p);
-  p += (L + 255) & ~size_t(255);
+  p += align256(static_cast<size_t>(steps) * N * sizeof(double));
+  w->P = reinterpret_cast<double*>(p);
+  p += align256(static_cast<size_t>(kPW) * N * sizeof(double));
+  w->U = reinterpret_cast<double*>(p);
+  p += align256(static_cast<size_t>(steps) * steps * sizeof(double));
+  w->chosen = reinterpret_cast<uint8_t*>(p);
+  p += align256(static_cast<size_t>(N));
   w->slots = p;
-  p += (2 * 1024 * sizeof(Slot) + 255) & ~size_t(255);
-  w->barrier = reinterpret_cast<unsigned*>(p);
-  p += 256;
-  w->status = reinterpret_cast<int*>(p);
+  p += align256(2 * kMaxGroups * sizeof(Slot));
+  // control words, cleared by every call: the barrier counter, then (in another cache
+  // line) the status words
+  w->ctl = reinterpret_cast<unsigned*>(p);
+  w->status = reinterpret_cast<int*>(p + 128);
   w->steps_cap = steps;
   w->N_cap = N;
   return ICUR_OK;
@@ -370,41 +528,63 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   if (steps < 1 || steps > K) return arg_error("lupp: need 1 <= steps <= K");
   if (steps > kMaxSteps) return arg_error("lupp: steps above 1024 are not supported");
   if (N < 1 || ldx < N) return arg_error("lupp: need N >= 1 and ldx >= N");
+  if (N > INT_MAX) return arg_error("lupp: N must be below 2^31");
   if (steps > w.steps_cap || N > w.N_cap) return arg_error("lupp: workspace too small");
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
-  // Rows per thread: the grid barrier's cost grows with the number of workgroups, so
-  // pack up to 8 candidate rows per thread and aim for about 16 workgroups.
-  int R = 1;
-  while (R < 8 && static_cast<int64_t>(R) * kLT * 16 < N) R *= 2;
-  while (R <= 8 && static_cast<int64_t>(R) * kLT * dev.num_cus < N) R *= 2;
-  if (R > 8) {
+  // Rows per workgroup: the per-step exchange costs more with more workgroups, so
+  // pack more candidates per workgroup and aim for about 16 of them.
+  const int max_groups = std::min(dev.num_cus, kMaxGroups);
+  int sh = 0;
+  while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * 16 < N) ++sh;
+  const int64_t per_group = static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT;
+  if (per_group * max_groups < N) {
     set_error("lupp: N exceeds the candidates one grid can hold in registers");
     return ICUR_ERR_UNSUPPORTED;
   }
-  const int groups = static_cast<int>((N + static_cast<int64_t>(R) * kLT - 1) / (static_cast<int64_t>(R) * kLT));
-  ICUR_TRY(launch_fill_u32(w.barrier, 1, 0u, st));
-  ICUR_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(w.status), 2, 0u, st));
-  Args a;
-  a.X = X;
-  a.ldx = ldx;
-  a.K = static_cast<int>(K);
-  a.N = static_cast<int>(N);
-  a.steps = steps;
-  a.excl = excluded;
-  a.L = w.L;
-  a.slots = static_cast<Slot*>(w.slots);
-  a.bar = w.barrier;
-  a.status = w.status;
-  a.piv = piv;
-  void* params[] = {&a};
-  const size_t shmem = static_cast<size_t>(steps) * kPW * sizeof(double) + static_cast<size_t>(steps) * sizeof(int);
-  LuppFn fn = x64 ? pick_t<double>(R) : pick_t<float>(R);
-  if (shmem > 64 * 1024) ICUR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       static_cast<int>(shmem)));
-  ICUR_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(groups), dim3(kLT),
-                                      params, static_cast<unsigned>(shmem), st));
+  const int groups = static_cast<int>((N + per_group - 1) / per_group);
+  ICUR_TRY(launch_fill_u32(w.ctl, kCtlBytes / sizeof(unsigned), 0u, st));  // barrier and status
+
+  Work wk;
+  wk.L = w.L;
+  wk.P = w.P;
+  wk.U = w.U;
+  wk.chosen = w.chosen;
+  wk.slots = static_cast<Slot*>(w.slots);
+  wk.bar = w.ctl;
+  wk.status = w.status;
+  wk.piv = piv;
+
+  PrepArgs pa;
+  pa.X = X;
+  pa.ldx = ldx;
+  pa.N = static_cast<int>(N);
+  pa.steps = steps;
+  pa.ncand = static_cast<int>((N + kPT - 1) / kPT);
+  pa.excl = excluded;
+  pa.w = wk;
+  PanelArgs qa;
+  qa.N = static_cast<int>(N);
+  qa.steps = steps;
+  qa.excl = excluded;
+  qa.w = wk;
+
+  const void* prep = x64 ? reinterpret_cast<const void*>(lupp_prep<double>)
+                         : reinterpret_cast<const void*>(lupp_prep<float>);
+  const size_t max_lds = static_cast<size_t>(steps) * kPW * sizeof(double);
+  if (max_lds > 64 * 1024)
+    ICUR_HIP(hipFuncSetAttribute(prep, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(max_lds)));
+  const void* panel = reinterpret_cast<const void*>(kShape[sh].fn);
+  for (int t0 = 0; t0 < steps; t0 += kPW) {
+    pa.t0 = t0;
+    qa.t0 = t0;
+    const int extra = t0 > 0 ? std::max(0, (steps - t0 + kPW - 1) / kPW - 1) : 0;
+    const size_t lds = static_cast<size_t>(t0) * kPW * sizeof(double);
+    void* pparams[] = {&pa};
+    ICUR_HIP(hipLaunchKernel(prep, dim3(pa.ncand + extra), dim3(kPT), pparams, lds, st));
+    void* qparams[] = {&qa};
+    ICUR_HIP(hipLaunchKernel(panel, dim3(groups), dim3(kShape[sh].LT), qparams, 0, st));
+  }
   return ICUR_OK;
 }
 

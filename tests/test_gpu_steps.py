@@ -112,11 +112,14 @@ LUPP_CASES = [
     (33, 300, 33, 0.1, 1),        # ragged last panel
     (16, 257, 16, 0.0, 2),        # one panel, ragged groups
     (1, 40, 1, 0.0, 3),
-    (110, 40000, 100, 0.01, 4),   # column selection at the RBF config's shape
-    (64, 70000, 64, 0.0, 5),      # two rows per thread
-    (70, 200000, 64, 0.001, 6),   # four rows per thread
-    (20, 300000, 20, 0.0, 7),     # eight rows per thread
-    (130, 5000, 128, 0.2, 8),     # 8+ panels
+    (110, 40000, 100, 0.01, 4),   # column selection at the 40000-column RBF shape
+    (40, 6000, 40, 0.0, 9),       # two rows per thread
+    (48, 12000, 48, 0.05, 10),    # four rows per thread, 256 threads
+    (64, 70000, 64, 0.0, 5),      # four rows per thread, 512 threads
+    (70, 200000, 64, 0.001, 6),
+    (20, 300000, 20, 0.0, 7),
+    (130, 5000, 128, 0.2, 8),     # 8 panels
+    (600, 2000, 600, 0.0, 11),    # pivot rows of 37 panels: more than 64 KB of LDS
 ]
 
 
@@ -150,6 +153,12 @@ def test_lupp_degenerate_inputs(icur):
     got = icur.lupp(dev(Y), 5, dev(excl)).tolist()
     assert got == lupp_pivots(Y.astype(np.float64).T, 5, exclude=np.nonzero(excl)[0].tolist())
     assert len(got) == 2
+    # the Schur complement becomes exactly zero in the middle of the second panel: the
+    # selection ends there, in every workgroup at once
+    Z = np.zeros((40, 20000), np.float32)
+    Z[:21] = np.random.default_rng(2).standard_normal((21, 20000))
+    got = icur.lupp(dev(Z), 40).tolist()
+    assert got == lupp_pivots(Z.astype(np.float64).T, 40) and len(got) == 21
 
 
 def test_lupp_repeatable(icur):
