@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("icur_wide_kernel.h", "icur_gemm.hip", "icur_wide_f64.hip"):
+    for f in ("icur_sketch.hip", "icur_wide_kernel.h"):
         with open(os.path.join(ROOT, "paper_2509_21963_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -157,7 +157,7 @@ def main():
                          "total_host": info["ms_total"]},
         },
         "roofline": {
-            "kernel": "sketch product G A (wide_kernel, BF16 pieces, FP64 output)",
+            "kernel": "sketch product G A (sketch_kernel: 3 BF16 pieces of A on bf16 MFMA, FP64 output)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "avg_ms": avg_ms, "algorithmic_bytes": alg_bytes,

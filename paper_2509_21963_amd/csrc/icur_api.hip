@@ -184,6 +184,11 @@ int prepare_device(DeviceCache** out) {
 // floor is this error amplified by the interpolation coefficients of the cross, so the
 // count leaves a wide margin: one piece only for very loose tolerances.
 constexpr double kResidualFp64Below = 1e-5;
+// Sketch accumulation: FP32 sums over 128 rows of A give X0 a relative noise near
+// sqrt(128) 2^-24; the column residual subtracts X0(:,J) times interpolation coefficients
+// whose norm reaches tens on ill-conditioned crosses, which puts a floor near 1e-5 under
+// rho.  Below this tolerance the sums are widened to FP64 after every 32 rows.
+constexpr double kSketchChunkFlushBelow = 1e-4;
 
 int terms_for_tol(double tol) {
   if (tol >= 1e-1) return 1;
@@ -262,7 +267,8 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
 
   // ---- fixed-size buffers
   void *pG, *pX0, *pSr, *pColMask, *pRowMask, *pJk, *pIk, *pLupp, *pGemm, *pNorm, *pScal, *pN;
-  ICUR_TRY(ensure(dc, kG, static_cast<size_t>(c) * m * 2, &pG));
+  const int64_t ldg = (m + 7) / 8 * 8;  // 16-byte aligned rows of G for the sketch kernel
+  ICUR_TRY(ensure(dc, kG, static_cast<size_t>(c) * ldg * 2, &pG));
   ICUR_TRY(ensure(dc, kX0, static_cast<size_t>(c) * n * 8, &pX0));
   ICUR_TRY(ensure(dc, kSrow, static_cast<size_t>(b) * n * fsz, &pSr));
   ICUR_TRY(ensure(dc, kColMask, static_cast<size_t>(n), &pColMask));
@@ -276,8 +282,10 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
   gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(c, BIGK, n, dev.num_cus));
   gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(b, BIGK, m, dev.num_cus));
   gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(b, BIGK, n, dev.num_cus));
+  gemm_ws = std::max(gemm_ws, sketch_workspace_bytes(c, m, n, dev.num_cus));
   ICUR_TRY(ensure(dc, kGemmWs, gemm_ws, &pGemm));
-  const int nparts_cap = std::max(max_norm_partials(c, n), max_norm_partials(b, m));
+  const int nparts_cap =
+      std::max(std::max(max_norm_partials(c, n), max_norm_partials(b, m)), sketch_max_norm_partials(c, n));
   ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(nparts_cap) * 8, &pNorm));
   ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
   LuppWork lw;
@@ -347,14 +355,21 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
   ICUR_TRY(tm.mark(&ev_s0));
   uint16_t* G = static_cast<uint16_t*>(pG);
   if (kind == ICUR_SKETCH_GAUSSIAN)
-    ICUR_TRY(launch_gaussian_G(seed, c, m, G, st));
+    ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
   else
-    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, st));
+    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, ldg, st));
   double* S = static_cast<double*>(pX0);  // X0, then the sketched column residual in place (FP64)
   {
+    int parts = 0;
+    ICUR_TRY(tm.mark(&ev_p0));
+    int sk = ICUR_ERR_UNSUPPORTED;
+    if (sketch_terms > 0)
+      sk = sketch_product(G, ldg, c, A, m, n, lda, sketch_terms, tol < kSketchChunkFlushBelow, S, n, dnorm,
+                          &parts, pGemm, dc.buf[kGemmWs].bytes, st);
+    if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
     WideGemm g{};
     g.W = G;
-    g.ldw = m;
+    g.ldw = ldg;
     g.wterms = sketch_terms == 0 ? 0 : 1;
     g.w_bf16 = true;
     g.B = A;
@@ -368,10 +383,8 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
     g.OUT = S;
     g.ldo = n;
     g.norm_partials = dnorm;
-    int parts = 0;
     g.nparts = &parts;
-    ICUR_TRY(tm.mark(&ev_p0));
-    ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+    if (sk == ICUR_ERR_UNSUPPORTED) ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
     ICUR_TRY(tm.mark(&ev_p1));
     ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
   }
@@ -592,11 +605,11 @@ int icur_make_sketch(uint64_t seed, int64_t c, int64_t m, int32_t sketch_kind, i
   hipStream_t st = as_stream(stream);
   if (sketch_kind == ICUR_SKETCH_GAUSSIAN) {
     if (!G_bf16) return arg_error("Gaussian sketch needs G_bf16");
-    ICUR_TRY(launch_gaussian_G(seed, c, m, G_bf16, st));
+    ICUR_TRY(launch_gaussian_G(seed, c, m, G_bf16, m, st));
   } else if (sketch_kind == ICUR_SKETCH_SPARSE_SIGN) {
     if (!G_bf16 && !rows && !signs) return arg_error("no output given");
     if (zeta < 0 || zeta > 8) return arg_error("zeta must be in 0..8");
-    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta > 0 ? zeta : 8, rows, signs, G_bf16, st));
+    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta > 0 ? zeta : 8, rows, signs, G_bf16, m, st));
   } else {
     return arg_error("unknown sketch kind");
   }
@@ -618,10 +631,26 @@ int icur_sketch(const uint16_t* G_bf16, int64_t c, const float* A, int64_t m, in
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
   hipStream_t st = as_stream(stream);
-  void *pGemm, *pNorm, *pScal;
-  ICUR_TRY(ensure(dc, kGemmWs, wide_gemm_workspace_bytes(c, m, n, dev.num_cus), &pGemm));
-  ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(max_norm_partials(c, n)) * 8, &pNorm));
+  void *pGemm, *pNorm, *pScal, *p64;
+  ICUR_TRY(ensure(dc, kGemmWs,
+                  std::max(wide_gemm_workspace_bytes(c, m, n, dev.num_cus), sketch_workspace_bytes(c, m, n, dev.num_cus)),
+                  &pGemm));
+  ICUR_TRY(ensure(dc, kNormPart,
+                  static_cast<size_t>(std::max(max_norm_partials(c, n), sketch_max_norm_partials(c, n))) * 8, &pNorm));
   ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  int parts = 0;
+  // the sketch kernel (FP64 result, then FP32 and its norm), as in icur_run; other
+  // shapes and terms 0 take the general product
+  int sk = ICUR_ERR_UNSUPPORTED;
+  if (terms > 0) {
+    ICUR_TRY(ensure(dc, kStepA, static_cast<size_t>(c) * n * 8, &p64));
+    sk = sketch_product(G_bf16, m, c, A, m, n, lda, terms, false, static_cast<double*>(p64), n, nullptr, nullptr,
+                        pGemm, dc.buf[kGemmWs].bytes, st);
+    if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
+    if (sk == ICUR_OK)
+      ICUR_TRY(convert_f64_f32_norm(static_cast<const double*>(p64), c, n, X0, n, static_cast<double*>(pNorm), &parts,
+                                    st));
+  }
   WideGemm g{};
   g.W = G_bf16;
   g.ldw = m;
@@ -638,9 +667,8 @@ int icur_sketch(const uint16_t* G_bf16, int64_t c, const float* A, int64_t m, in
   g.OUT = X0;
   g.ldo = n;
   g.norm_partials = static_cast<double*>(pNorm);
-  int parts = 0;
   g.nparts = &parts;
-  ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+  if (sk == ICUR_ERR_UNSUPPORTED) ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
   Scal* ds = static_cast<Scal*>(pScal);
   ICUR_TRY(launch_reduce_partials(static_cast<double*>(pNorm), parts, &ds->normsq_x0, st));
   Scal hs;

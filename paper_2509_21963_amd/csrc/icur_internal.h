@@ -45,9 +45,10 @@ struct DeviceInfo {
 int device_info(DeviceInfo* out);
 
 // ----- sketch operator (icur_rng.hip) -----
-int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, hipStream_t st);
+// G is c x m BF16 bit patterns, row-major with leading dimension ldg >= m.
+int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t ldg, hipStream_t st);
 int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* rows,
-                       uint8_t* signs, uint16_t* G_dense, hipStream_t st);
+                       uint8_t* signs, uint16_t* G_dense, int64_t ldg, hipStream_t st);
 
 // ----- wide products (icur_gemm.hip, icur_wide_*.hip) -----
 // OUT(M x N) = X - W(M x K) B(K x N) (subtract) or W B.  X and OUT are FP32, or FP64 when
@@ -76,6 +77,24 @@ struct WideGemm {
   int* nparts;
 };
 int wide_gemm(const WideGemm& g, void* workspace, size_t workspace_bytes, hipStream_t st);
+
+// ----- the sketch product (icur_sketch.hip) -----
+// X0 (c x n, FP64, ld ldx) = G A with G the c x m BF16 sketch (leading dimension ldg, a
+// multiple of 8, 16-byte aligned) and A the m x n FP32 input, each element of A split into
+// `terms` (1..3) BF16 pieces; FP32 sums over 128-row blocks are accumulated in FP64
+// (over 32-row chunks when precise, which needs terms 3); per-block FP64 partial sums of
+// X0^2 land in norm_partials (count in *nparts).  Returns ICUR_ERR_UNSUPPORTED for
+// shapes outside its fast path (misaligned A or G, terms 0, very long rows); the caller
+// then uses wide_gemm.
+int sketch_product(const uint16_t* G, int64_t ldg, int64_t c, const float* A, int64_t m, int64_t n,
+                   int64_t lda, int terms, bool precise, double* X0, int64_t ldx, double* norm_partials,
+                   int* nparts, void* workspace, size_t workspace_bytes, hipStream_t st);
+size_t sketch_workspace_bytes(int64_t c, int64_t m, int64_t n, int num_cus);
+// dst (FP32, ld ldd) = src (FP64 M x N, ld N), with per-block partial sums of dst^2
+// (at most 1024 blocks; count in *nparts).
+int convert_f64_f32_norm(const double* src, int64_t M, int64_t N, float* dst, int64_t ldd, double* norm_partials,
+                         int* nparts, hipStream_t st);
+int sketch_max_norm_partials(int64_t c, int64_t n);
 size_t wide_gemm_workspace_bytes(int64_t M, int64_t K, int64_t N, int num_cus);
 int max_norm_partials(int64_t M, int64_t N);
 

@@ -48,7 +48,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-__global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t* __restrict__ G) {
+__global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t* __restrict__ G, int64_t ldg) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t r = blockIdx.y;
   if (i >= m || r >= c) return;
@@ -61,14 +61,14 @@ __global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t*
   const double u1 = (static_cast<double>(a) + 1.0) * 0x1.0p-53;  // (0, 1]
   const double u2 = static_cast<double>(b) * 0x1.0p-53;          // [0, 1)
   const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  G[r * m + i] = f32_to_bf16_rne(static_cast<float>(z));
+  G[r * ldg + i] = f32_to_bf16_rne(static_cast<float>(z));
 }
 
 // One thread per column i of G (row i of A).  Writes the pattern and, when G_dense is
 // given, the whole dense column (zeros included) as BF16 bit patterns.
 __global__ void sparse_sign_kernel(uint64_t seed, int c, int64_t m, int z,
                                    uint8_t* __restrict__ rows, uint8_t* __restrict__ signs,
-                                   uint16_t* __restrict__ G) {
+                                   uint16_t* __restrict__ G, int64_t ldg) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
   const uint64_t ui = static_cast<uint64_t>(i);
@@ -94,30 +94,32 @@ __global__ void sparse_sign_kernel(uint64_t seed, int c, int64_t m, int z,
       uint16_t v = 0;
       for (int t = 0; t < z; ++t)
         if (chosen[t] == r) v = ((sbits >> t) & 1u) ? 0xBF80u : 0x3F80u;  // -1 / +1
-      G[static_cast<int64_t>(r) * m + i] = v;
+      G[static_cast<int64_t>(r) * ldg + i] = v;
     }
   }
 }
 
 }  // namespace
 
-int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, hipStream_t st) {
+int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t ldg, hipStream_t st) {
   if (c <= 0 || m <= 0) return ICUR_OK;
+  if (ldg < m) return arg_error("sketch: need ldg >= m");
   if (c > 65535) return arg_error("sketch rows c exceed 65535");
   dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(c));
-  hipLaunchKernelGGL(gaussian_G_kernel, grid, dim3(256), 0, st, seed, c, m, G);
+  hipLaunchKernelGGL(gaussian_G_kernel, grid, dim3(256), 0, st, seed, c, m, G, ldg);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }
 
 int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* rows,
-                       uint8_t* signs, uint16_t* G_dense, hipStream_t st) {
+                       uint8_t* signs, uint16_t* G_dense, int64_t ldg, hipStream_t st) {
   if (c <= 0 || m <= 0) return ICUR_OK;
+  if (G_dense && ldg < m) return arg_error("sketch: need ldg >= m");
   if (c > 255) return arg_error("sparse-sign sketch needs c <= 255");
   const int z = zeta < c ? zeta : static_cast<int>(c);
   if (z < 1 || z > 8) return arg_error("sparse-sign zeta must be in 1..8");
   hipLaunchKernelGGL(sparse_sign_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256),
-                     0, st, seed, static_cast<int>(c), m, z, rows, signs, G_dense);
+                     0, st, seed, static_cast<int>(c), m, z, rows, signs, G_dense, ldg);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }
