@@ -105,6 +105,25 @@ int icur_run(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
              int32_t sketch_kind, uint64_t seed, const icur_opts* opts, int64_t* I,
              int64_t* J, double* U, int64_t* rank, double* est_err);
 
+/*
+ * icur_run_csr: Alg. 1 on a sparse m x n matrix in CSR form (the paper's sparse test
+ * matrices, §5; sparse inputs are where the cost of the sketch matters, §3.4).
+ *   rowptr   device, m + 1 int64: row i holds entries rowptr[i] .. rowptr[i+1]-1,
+ *            rowptr[0] = 0, rowptr[m] = nnz.
+ *   colind   device, nnz int32: column indices, strictly increasing within each row.
+ *   vals     device, nnz FP32.
+ *   nnz      0 <= nnz < 2^31.
+ * The other arguments and the outputs are those of icur_run (opts->sketch_fp32 does not
+ * apply: the sparse sketch accumulates in FP64).  The CSR arrays are checked on the
+ * device first; a non-canonical matrix returns ICUR_ERR_ARG before any other work.  The
+ * call builds a column-compressed copy (8 bytes per entry plus n + 1 offsets) in the
+ * cached workspace.  Needs c = floor(1.1 b) <= 256.
+ */
+int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals, int64_t m,
+                 int64_t n, int64_t nnz, double tol, int32_t block, int32_t sketch_kind,
+                 uint64_t seed, const icur_opts* opts, int64_t* I, int64_t* J, double* U,
+                 int64_t* rank, double* est_err);
+
 /* Statistics of the calling thread's most recent icur_run (copied into *info). */
 int icur_last_info(icur_info* info);
 

@@ -46,7 +46,7 @@ namespace {
 enum Slot {
   kG, kRowsPat, kSignsPat, kX0, kS, kSrow, kCt, kR, kU, kY, kA12, kA21, kA22, kYt, kX0J, kW64,
   kWp, kColMask, kRowMask, kJk, kIk, kJall, kIall, kLupp, kGemmWs, kNormPart, kScal, kCoreWs,
-  kStepA, kStepB, kNumSlots
+  kStepA, kStepB, kCsc, kNumSlots
 };
 
 struct Buf {
@@ -134,16 +134,22 @@ struct Timer {
   hipStream_t st;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;
-  int mark(size_t* idx) {
+  // An event slot that the caller records itself (or that mark() records now).
+  int reserve(size_t* idx) {
     if (used == dc->events.size()) {
       hipEvent_t e;
       ICUR_HIP(hipEventCreate(&e));
       dc->events.push_back(e);
     }
-    ICUR_HIP(hipEventRecord(dc->events[used], st));
     *idx = used++;
     return ICUR_OK;
   }
+  int mark(size_t* idx) {
+    ICUR_TRY(reserve(idx));
+    ICUR_HIP(hipEventRecord(dc->events[*idx], st));
+    return ICUR_OK;
+  }
+  hipEvent_t event(size_t idx) const { return dc->events[idx]; }
   float ms(size_t a, size_t b) {
     float v = 0.f;
     if (hipEventElapsedTime(&v, dc->events[a], dc->events[b]) != hipSuccess) {
@@ -189,6 +195,12 @@ constexpr double kResidualFp64Below = 1e-5;
 // whose norm reaches tens on ill-conditioned crosses, which puts a floor near 1e-5 under
 // rho.  Below this tolerance the sums are widened to FP64 after every 32 rows.
 constexpr double kSketchChunkFlushBelow = 1e-4;
+// Row selection ends at a pivot below this fraction of its first pivot: the Schur
+// complement is then rounding noise of the factors' precision (a block straddling the
+// exact rank of A), and inverting that noise in N_k would wreck the residual recurrence.
+// What is dropped is at most this fraction of the block's largest residual entry.
+constexpr double kRowCutFp64 = 0x1.0p-40;
+constexpr double kRowCutFp32 = 0x1.0p-16;
 
 int terms_for_tol(double tol) {
   if (tol >= 1e-1) return 1;
@@ -211,15 +223,25 @@ double risk_factor(double alpha, double delta, int64_t c, int* status) {
 }
 
 // --------------------------------------------------------------------- the driver
-int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int32_t block,
-             int32_t kind, uint64_t seed, const icur_opts* opts, int64_t* I_out, int64_t* J_out,
-             double* U_out, int64_t* rank_out, double* est_out) {
-  const auto t_start = std::chrono::steady_clock::now();
-  std::memset(&t_info, 0, sizeof(t_info));
+// The matrix the loop reads: dense FP32 (A, lda), or CSR with its CSC copy.  Only the
+// sketch and the three gathers (columns A(:,J_k), rows A(I_k,:), the cross A(I,J))
+// depend on it; every other step works on dense gathered operands.
+struct Source {
+  const float* A = nullptr;
+  int64_t lda = 0;
+  const CsrMatrix* csr = nullptr;  // checked and copied to CSC by run_impl
+};
+
+int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block, int32_t kind, uint64_t seed,
+             const icur_opts* opts, int64_t* I_out, int64_t* J_out, double* U_out, int64_t* rank_out,
+             double* est_out, std::chrono::steady_clock::time_point t_start) {
+  const float* A = src.A;
+  const int64_t lda = src.lda;
+  const bool sparse = (src.csr != nullptr);
   // ---- arguments (before any device work)
-  if (!A) return arg_error("A is null");
+  if (!A && !sparse) return arg_error("A is null");
   if (m < 1 || n < 1) return arg_error("need m >= 1 and n >= 1");
-  if (lda < n) return arg_error("need lda >= n");
+  if (!sparse && lda < n) return arg_error("need lda >= n");
   if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error("tol must be finite and > 0");
   if (block < 1 || block > std::min(m, n)) return arg_error("need 1 <= block <= min(m, n)");
   if (kind != ICUR_SKETCH_GAUSSIAN && kind != ICUR_SKETCH_SPARSE_SIGN)
@@ -234,6 +256,7 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
   if (c > 4096) return arg_error("sketch rows c = floor(1.1 b) above 4096 are not supported");
   if (b > 1024) return arg_error("block above 1024 is not supported");
   if (kind == ICUR_SKETCH_SPARSE_SIGN && c > 255) return arg_error("sparse-sign sketch needs c <= 255");
+  if (sparse && c > 256) return arg_error("the CSR sketch needs c = floor(1.1 b) <= 256");
   const int zeta = o.zeta > 0 ? o.zeta : 8;
   if (zeta > 8) return arg_error("zeta must be at most 8");
   if (o.precision != ICUR_FP32 && o.precision != ICUR_BF16_SPLIT) return arg_error("unknown precision");
@@ -264,11 +287,27 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
   Timer tm{&dc, st};
+  CscCopy csc{};
+  if (sparse) {
+    // a canonical CSR is required: rowptr from 0 to nnz, columns in range, sorted and
+    // unique within each row (checked on the device before anything else)
+    const CsrMatrix& S0 = *src.csr;
+    void* pc;
+    ICUR_TRY(ensure(dc, kCsc, csc_workspace_bytes(S0.nnz, S0.n) + 256, &pc));
+    unsigned* flag = reinterpret_cast<unsigned*>(static_cast<char*>(pc) + csc_workspace_bytes(S0.nnz, S0.n));
+    ICUR_TRY(csr_validate(S0, flag, st));
+    int hflag = 0;
+    ICUR_TRY(read_int(dc, reinterpret_cast<const int*>(flag), &hflag, 1, st));
+    if (hflag & 1) return arg_error("CSR: rowptr must start at 0, end at nnz and not decrease");
+    if (hflag & 2) return arg_error("CSR: column index out of range [0, n)");
+    if (hflag & 4) return arg_error("CSR: column indices must be strictly increasing within each row");
+    ICUR_TRY(csc_build(S0, &csc, pc, csc_workspace_bytes(S0.nnz, S0.n), st));
+  }
 
   // ---- fixed-size buffers
   void *pG, *pX0, *pSr, *pColMask, *pRowMask, *pJk, *pIk, *pLupp, *pGemm, *pNorm, *pScal, *pN;
   const int64_t ldg = (m + 7) / 8 * 8;  // 16-byte aligned rows of G for the sketch kernel
-  ICUR_TRY(ensure(dc, kG, static_cast<size_t>(c) * ldg * 2, &pG));
+  ICUR_TRY(ensure(dc, kG, sparse ? csr_sketch_aux_bytes(m, c) : static_cast<size_t>(c) * ldg * 2, &pG));
   ICUR_TRY(ensure(dc, kX0, static_cast<size_t>(c) * n * 8, &pX0));
   ICUR_TRY(ensure(dc, kSrow, static_cast<size_t>(b) * n * fsz, &pSr));
   ICUR_TRY(ensure(dc, kColMask, static_cast<size_t>(n), &pColMask));
@@ -284,8 +323,9 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
   gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(b, BIGK, n, dev.num_cus));
   gemm_ws = std::max(gemm_ws, sketch_workspace_bytes(c, m, n, dev.num_cus));
   ICUR_TRY(ensure(dc, kGemmWs, gemm_ws, &pGemm));
-  const int nparts_cap =
-      std::max(std::max(max_norm_partials(c, n), max_norm_partials(b, m)), sketch_max_norm_partials(c, n));
+  const int nparts_cap = std::max(std::max(std::max(max_norm_partials(c, n), max_norm_partials(b, m)),
+                                           sketch_max_norm_partials(c, n)),
+                                  csr_max_norm_partials(n));
   ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(nparts_cap) * 8, &pNorm));
   ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
   LuppWork lw;
@@ -354,19 +394,30 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
   size_t ev_s0, ev_s1, ev_p0, ev_p1;
   ICUR_TRY(tm.mark(&ev_s0));
   uint16_t* G = static_cast<uint16_t*>(pG);
-  if (kind == ICUR_SKETCH_GAUSSIAN)
-    ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
-  else
-    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, ldg, st));
   double* S = static_cast<double*>(pX0);  // X0, then the sketched column residual in place (FP64)
-  {
+  if (sparse) {
+    // G is drawn inside (as row masks or transposed Gaussian values); X0 from the CSC copy
     int parts = 0;
     ICUR_TRY(tm.mark(&ev_p0));
+    ICUR_TRY(csr_sketch(csc, m, n, c, kind, seed, zeta, S, n, dnorm, &parts, pG, st));
+    ICUR_TRY(tm.mark(&ev_p1));
+    ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
+  } else {
+    if (kind == ICUR_SKETCH_GAUSSIAN)
+      ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
+    else
+      ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, ldg, st));
+    int parts = 0;
+    // ev_p0 / ev_p1 bracket the sketch kernel itself (the first 160-row slice of G when
+    // c > 160), not its split-K reduce; the general product is bracketed whole
+    ICUR_TRY(tm.reserve(&ev_p0));
+    ICUR_TRY(tm.reserve(&ev_p1));
     int sk = ICUR_ERR_UNSUPPORTED;
     if (sketch_terms > 0)
       sk = sketch_product(G, ldg, c, A, m, n, lda, sketch_terms, tol < kSketchChunkFlushBelow, S, n, dnorm,
-                          &parts, pGemm, dc.buf[kGemmWs].bytes, st);
+                          &parts, pGemm, dc.buf[kGemmWs].bytes, st, tm.event(ev_p0), tm.event(ev_p1));
     if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
+    if (sk == ICUR_ERR_UNSUPPORTED) ICUR_HIP(hipEventRecord(tm.event(ev_p0), st));
     WideGemm g{};
     g.W = G;
     g.ldw = ldg;
@@ -384,8 +435,10 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
     g.ldo = n;
     g.norm_partials = dnorm;
     g.nparts = &parts;
-    if (sk == ICUR_ERR_UNSUPPORTED) ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
-    ICUR_TRY(tm.mark(&ev_p1));
+    if (sk == ICUR_ERR_UNSUPPORTED) {
+      ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+      ICUR_HIP(hipEventRecord(tm.event(ev_p1), st));
+    }
     ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
   }
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pColMask), n, 0, st));
@@ -451,17 +504,24 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
     // row residual S^row = A(:,J_k) - C U R(:,J_k) = A(:,J_k) - Lc Ur(:,J_k), stored
     // transposed as the next rows of LcT
     void* Lk = fp(LcT, r * m);
-    if (res64)
+    if (sparse) {
+      if (res64)
+        ICUR_TRY(csc_gather_cols_T(csc, m, Jk, nJ, static_cast<double*>(Lk), m, st));
+      else
+        ICUR_TRY(csc_gather_cols_T(csc, m, Jk, nJ, static_cast<float*>(Lk), m, st));
+    } else if (res64) {
       ICUR_TRY(launch_gather_cols_T(A, m, n, lda, Jk, nJ, static_cast<double*>(Lk), m, st));
-    else
+    } else {
       ICUR_TRY(launch_gather_cols_T(A, m, n, lda, Jk, nJ, static_cast<float*>(Lk), m, st));
+    }
     if (r > 0) {
       ICUR_TRY(gather_w(Ur, n, r, Jk, nJ, true, W64, r));   // Ur(:,J_k)^T
       ICUR_TRY(product(W64, nJ, r, Lk, m, LcT, m, m, true, Lk, m, false, false, &parts));
     }
     ICUR_TRY(tm.mark(&e2));
     // row selection: LUPP on S^row
-    ICUR_TRY(lupp_launch(Lk, res64, nJ, m, m, static_cast<int>(nJ), static_cast<const uint8_t*>(pRowMask), Ik, lw, st));
+    ICUR_TRY(lupp_launch(Lk, res64, nJ, m, m, static_cast<int>(nJ), static_cast<const uint8_t*>(pRowMask), Ik, lw, st,
+                         res64 ? kRowCutFp64 : kRowCutFp32));
     ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
     if (lst[1]) {
       set_error("selection kernel: grid barrier did not complete");
@@ -477,10 +537,16 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
     ICUR_TRY(gather_w(Lk, m, nI, Ik, nI, true, Nblk, nI));
     ICUR_TRY(launch_small_inverse(Nblk, nI, Nwork, &dscal->info, dscal->norms, st));
     // residual at the new rows: Sr = A(I_k,:) - Lc(I_k,:) Ur
-    if (res64)
+    if (sparse) {
+      if (res64)
+        ICUR_TRY(csr_gather_rows(*src.csr, Ik, nI, static_cast<double*>(Sr), n, st));
+      else
+        ICUR_TRY(csr_gather_rows(*src.csr, Ik, nI, static_cast<float*>(Sr), n, st));
+    } else if (res64) {
       ICUR_TRY(launch_gather_rows(A, m, n, lda, Ik, nI, static_cast<double*>(Sr), n, st));
-    else
+    } else {
       ICUR_TRY(launch_gather_rows(A, m, n, lda, Ik, nI, static_cast<float*>(Sr), n, st));
+    }
     if (r > 0) {
       ICUR_TRY(gather_w(LcT, m, r, Ik, nI, true, W64, r));  // Lc(I_k,:)
       ICUR_TRY(product(W64, nI, r, Sr, n, Ur, n, n, true, Sr, n, false, false, &parts));
@@ -528,8 +594,12 @@ int run_impl(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int3
     double* U = static_cast<double*>(pU);
     double* M = static_cast<double*>(pM);
     int* infos = reinterpret_cast<int*>(static_cast<double*>(pCore) + core_inverse_ws_doubles(r, b));
-    ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
-                               false, M, r, st));
+    if (sparse)
+      ICUR_TRY(csr_gather_cross(*src.csr, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
+                                M, r, st));
+    else
+      ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
+                                 false, M, r, st));
     ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, dscal->norms, st));
     ICUR_TRY(tm.mark(&ec1));
     std::vector<int> hinfo(nb);
@@ -563,8 +633,27 @@ extern "C" {
 int icur_run(const float* A, int64_t m, int64_t n, int64_t lda, double tol, int32_t block,
              int32_t sketch_kind, uint64_t seed, const icur_opts* opts, int64_t* I, int64_t* J,
              double* U, int64_t* rank, double* est_err) {
+  const auto t0 = std::chrono::steady_clock::now();
   t_error.clear();
-  return run_impl(A, m, n, lda, tol, block, sketch_kind, seed, opts, I, J, U, rank, est_err);
+  std::memset(&t_info, 0, sizeof(t_info));
+  Source src;
+  src.A = A;
+  src.lda = lda;
+  return run_impl(src, m, n, tol, block, sketch_kind, seed, opts, I, J, U, rank, est_err, t0);
+}
+
+int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals, int64_t m, int64_t n,
+                 int64_t nnz, double tol, int32_t block, int32_t sketch_kind, uint64_t seed,
+                 const icur_opts* opts, int64_t* I, int64_t* J, double* U, int64_t* rank, double* est_err) {
+  const auto t0 = std::chrono::steady_clock::now();
+  t_error.clear();
+  std::memset(&t_info, 0, sizeof(t_info));
+  if (!rowptr || (nnz > 0 && (!colind || !vals))) return arg_error("null CSR array");
+  if (nnz < 0 || nnz > 0x7fffffffLL) return arg_error("need 0 <= nnz < 2^31");
+  CsrMatrix csr{rowptr, colind, vals, m, n, nnz};
+  Source src;
+  src.csr = &csr;
+  return run_impl(src, m, n, tol, block, sketch_kind, seed, opts, I, J, U, rank, est_err, t0);
 }
 
 int icur_last_info(icur_info* info) {
@@ -645,7 +734,7 @@ int icur_sketch(const uint16_t* G_bf16, int64_t c, const float* A, int64_t m, in
   if (terms > 0) {
     ICUR_TRY(ensure(dc, kStepA, static_cast<size_t>(c) * n * 8, &p64));
     sk = sketch_product(G_bf16, m, c, A, m, n, lda, terms, false, static_cast<double*>(p64), n, nullptr, nullptr,
-                        pGemm, dc.buf[kGemmWs].bytes, st);
+                        pGemm, dc.buf[kGemmWs].bytes, st, nullptr, nullptr);
     if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
     if (sk == ICUR_OK)
       ICUR_TRY(convert_f64_f32_norm(static_cast<const double*>(p64), c, n, X0, n, static_cast<double*>(pNorm), &parts,

@@ -231,6 +231,141 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
   if (tid == 0) *info = 0;
 }
 
+// Register variant for k <= 128: thread (g, c), t = g k + c, owns column c of the rows
+// s = g, g + G, g + 2G, ... (G = 1024 / k row groups, at most RMAX rows) in registers.
+// Pivoting is implicit (no row swaps): step j picks the unused row p with the largest
+// |a(p, j)|, lowest index on ties, and eliminates column j from every other row; storage
+// row p_j then holds row j of the inverse with columns permuted, which the final write
+// undoes (inverse(j, p_c) = storage(p_j, c)).  Per step only the pivot column and the
+// pivot row travel through LDS (double buffered by step parity): two barriers per step.
+template <int RMAX>
+__global__ __launch_bounds__(1024) void gj_inverse_reg_kernel(double* __restrict__ Ng, int k,
+                                                              int* __restrict__ info,
+                                                              double* __restrict__ norms) {
+  __shared__ double colj[2][128];
+  __shared__ double prow[2][128];
+  __shared__ double red_v[2][16];
+  __shared__ int red_i[2][16];
+  __shared__ int perm[128];   // perm[j] = p_j
+  __shared__ int pinv[128];   // pinv[p_j] = j
+  __shared__ double cs[16][128];
+  const int tid = threadIdx.x;
+  const int G = min(1024 / k, 16);
+  const int g = tid / k, c = tid % k;
+  const bool own = g < G;  // threads beyond G k only join the barriers
+  double a[RMAX];
+  unsigned used = 0;  // bit q: row g + G q was a pivot
+#pragma unroll
+  for (int q = 0; q < RMAX; ++q) {
+    const int srow = g + G * q;
+    a[q] = (own && srow < k) ? Ng[srow * k + c] : 0.0;
+  }
+  // max column sum of |N| (an input norm for the caller's conditioning estimate)
+  auto colnorm = [&](int slot) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q)
+      if (own && g + G * q < k) sum += fabs(a[q]);
+    if (own) cs[g][c] = sum;
+    __syncthreads();
+    if (tid < 64) {
+      double mx = 0.0;
+      for (int cc = tid; cc < k; cc += 64) {
+        double t = 0.0;
+        for (int gg = 0; gg < G; ++gg) t += cs[gg][cc];
+        mx = fmax(mx, t);
+      }
+      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+      if (tid == 0) norms[slot] = mx;
+    }
+    __syncthreads();
+  };
+  colnorm(0);
+  for (int j = 0; j < k; ++j) {
+    const int b = j & 1;
+    // (1) the owners of column j publish it and their best unused row
+    if (own && c == j) {
+      double bv = -1.0;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q < RMAX; ++q) {
+        const int srow = g + G * q;
+        if (srow < k) {
+          colj[b][srow] = a[q];
+          const double v = fabs(a[q]);
+          if (!((used >> q) & 1u) && (v > bv || (v == bv && srow < bi))) {
+            bv = v;
+            bi = srow;
+          }
+        }
+      }
+      red_v[b][g] = bv;
+      red_i[b][g] = bi;
+    }
+    __syncthreads();
+    double piv_abs = -1.0;
+    int p = 0x7fffffff;
+    for (int gg = 0; gg < G; ++gg) {
+      const double v = red_v[b][gg];
+      const int i = red_i[b][gg];
+      if (v > piv_abs || (v == piv_abs && i < p)) {
+        piv_abs = v;
+        p = i;
+      }
+    }
+    if (!(piv_abs > 0.0)) {
+      if (tid == 0) *info = 1;
+      return;  // uniform: every thread reduced the same slots
+    }
+    const double piv = colj[b][p];
+    // (2) the owners of row p publish it
+    const int gp = p % G, qp = p / G;
+    if (own && g == gp) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < RMAX; ++q)
+        if (q == qp) v = a[q];
+      prow[b][c] = v;
+      used |= 1u << qp;
+    }
+    if (tid == 0) {
+      perm[j] = p;
+      pinv[p] = j;
+    }
+    __syncthreads();
+    // (3) eliminate column j from every row but p; row p is scaled
+    if (own) {
+      const double rinv = 1.0 / piv;
+      const double pr = (c == j) ? rinv : prow[b][c] * rinv;
+#pragma unroll
+      for (int q = 0; q < RMAX; ++q) {
+        const int srow = g + G * q;
+        if (srow < k) {
+          if (srow == p) {
+            a[q] = pr;
+          } else {
+            const double f = colj[b][srow];
+            a[q] = (c == j) ? -f * rinv : a[q] - f * pr;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // inverse(pinv[s], perm[c]) = storage(s, c)
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const int srow = g + G * q;
+      if (srow < k) Ng[pinv[srow] * k + perm[c]] = a[q];
+    }
+  }
+  // norm of the inverse: same columns, rows permuted (column sums are unchanged by
+  // the row permutation; the column permutation only relabels them)
+  colnorm(1);
+  if (tid == 0) *info = 0;
+}
+
 }  // namespace
 
 int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sa0,
@@ -269,6 +404,12 @@ size_t small_inverse_work_bytes(int64_t k) { return static_cast<size_t>(k) * k *
 int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
                          hipStream_t st) {
   if (k < 1 || k > 512) return arg_error("inverse: block size must be in 1..512");
+  if (k <= 128) {
+    auto fn = k <= 32 ? gj_inverse_reg_kernel<2> : (k <= 64 ? gj_inverse_reg_kernel<4> : gj_inverse_reg_kernel<16>);
+    hipLaunchKernelGGL(fn, dim3(1), dim3(1024), 0, st, N, static_cast<int>(k), info, norms);
+    ICUR_HIP(hipGetLastError());
+    return ICUR_OK;
+  }
   const bool use_lds = k <= 128;
   const size_t shmem = use_lds ? static_cast<size_t>(k) * k * sizeof(double) : 0;
   if (shmem > 64 * 1024)

@@ -47,6 +47,9 @@ int device_info(DeviceInfo* out);
 // ----- sketch operator (icur_rng.hip) -----
 // G is c x m BF16 bit patterns, row-major with leading dimension ldg >= m.
 int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t ldg, hipStream_t st);
+// Same values, entry (r, i) stored at G[r * sr + i * si] (si = ldgt, sr = 1: transposed).
+int launch_gaussian_G_strided(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t sr, int64_t si,
+                              hipStream_t st);
 int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* rows,
                        uint8_t* signs, uint16_t* G_dense, int64_t ldg, hipStream_t st);
 
@@ -84,11 +87,13 @@ int wide_gemm(const WideGemm& g, void* workspace, size_t workspace_bytes, hipStr
 // `terms` (1..3) BF16 pieces; FP32 sums over 128-row blocks are accumulated in FP64
 // (over 32-row chunks when precise, which needs terms 3); per-block FP64 partial sums of
 // X0^2 land in norm_partials (count in *nparts).  Returns ICUR_ERR_UNSUPPORTED for
-// shapes outside its fast path (misaligned A or G, terms 0, very long rows); the caller
-// then uses wide_gemm.
+// shapes outside its fast path (misaligned A or G, terms 0, very long rows) before
+// launching anything; the caller then uses wide_gemm.  ev_begin / ev_end (may be null)
+// are recorded around the first slice's sketch kernel.
 int sketch_product(const uint16_t* G, int64_t ldg, int64_t c, const float* A, int64_t m, int64_t n,
                    int64_t lda, int terms, bool precise, double* X0, int64_t ldx, double* norm_partials,
-                   int* nparts, void* workspace, size_t workspace_bytes, hipStream_t st);
+                   int* nparts, void* workspace, size_t workspace_bytes, hipStream_t st, hipEvent_t ev_begin,
+                   hipEvent_t ev_end);
 size_t sketch_workspace_bytes(int64_t c, int64_t m, int64_t n, int num_cus);
 // dst (FP32, ld ldd) = src (FP64 M x N, ld N), with per-block partial sums of dst^2
 // (at most 1024 blocks; count in *nparts).
@@ -107,6 +112,38 @@ int launch_split_f64(const double* src, int64_t rows, int64_t cols, int64_t lds,
 // Sum of per-block partials into out (device double, written in a fixed order).
 int launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st);
 
+// ----- sparse input (icur_csr.hip) -----
+struct CsrMatrix {
+  const int64_t* rowptr;  // m + 1
+  const int32_t* colind;  // nnz, sorted and unique within each row
+  const float* vals;      // nnz
+  int64_t m, n, nnz;
+};
+struct CscCopy {
+  int64_t* colptr;  // n + 1
+  int32_t* row;     // nnz, increasing within each column
+  float* val;       // nnz
+};
+// Device flag (bit 0 rowptr, bit 1 column range, bit 2 order within a row); 0 = valid.
+int csr_validate(const CsrMatrix& A, unsigned* flag_dev, hipStream_t st);
+size_t csc_workspace_bytes(int64_t nnz, int64_t n);
+int csc_build(const CsrMatrix& A, CscCopy* out, void* ws, size_t ws_bytes, hipStream_t st);
+// X0 (c x n FP64, ld ldx) = G A from the CSC copy, G drawn here from (kind, seed, zeta);
+// per-block norm partials (count in *nparts).  aux: csr_sketch_aux_bytes(m, c).
+size_t csr_sketch_aux_bytes(int64_t m, int64_t c);
+int csr_sketch(const CscCopy& csc, int64_t m, int64_t n, int64_t c, int kind, uint64_t seed, int zeta, double* X0,
+               int64_t ldx, double* norm_partials, int* nparts, void* aux, hipStream_t st);
+int csr_max_norm_partials(int64_t n);
+// Dense gathers: Ct row t = A(:, cols[t]); R row t = A(rows[t], :); M = A(I, J) (FP64).
+int csc_gather_cols_T(const CscCopy& csc, int64_t m, const int64_t* cols, int64_t k, float* Ct, int64_t ldct,
+                      hipStream_t st);
+int csc_gather_cols_T(const CscCopy& csc, int64_t m, const int64_t* cols, int64_t k, double* Ct, int64_t ldct,
+                      hipStream_t st);
+int csr_gather_rows(const CsrMatrix& A, const int64_t* rows, int64_t k, float* R, int64_t ldr, hipStream_t st);
+int csr_gather_rows(const CsrMatrix& A, const int64_t* rows, int64_t k, double* R, int64_t ldr, hipStream_t st);
+int csr_gather_cross(const CsrMatrix& A, const int64_t* I, int64_t rk, const int64_t* J, int64_t ck, double* M,
+                     int64_t ldm, hipStream_t st);
+
 // ----- selection (icur_lupp.hip) -----
 struct LuppWork {
   double* L;          // steps_cap x N_cap multipliers
@@ -116,14 +153,16 @@ struct LuppWork {
   void* slots;        // 2 * max_groups slot records
   unsigned* ctl;      // barrier counter and status words, cleared by every call
   int* status;        // [0] npiv, [1] fault flag, [2] ended early (inside ctl)
+  unsigned long long* ref;  // |first pivot| bit pattern (inside ctl)
   int64_t steps_cap, N_cap;
 };
 size_t lupp_workspace_bytes(int64_t steps, int64_t N);
 int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w);
 // Pivots of LUPP on T = X^T (see icur_lupp); X is FP32, or FP64 when x64.  piv is
-// device; the pivot count and a fault flag land in w.status.
+// device; the pivot count and a fault flag land in w.status.  rel_cut > 0 also ends the
+// selection at a pivot |p| <= rel_cut * |first pivot| (numerically zero Schur complement).
 int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps,
-                const uint8_t* excluded, int64_t* piv, const LuppWork& w, hipStream_t st);
+                const uint8_t* excluded, int64_t* piv, const LuppWork& w, hipStream_t st, double rel_cut = 0.0);
 
 // ----- gathers and small FP64 kernels (icur_gather.hip) -----
 int launch_gather_cols_T(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,

@@ -44,7 +44,7 @@ constexpr int kPT = 256;         // threads per workgroup of the prep kernel (= 
 constexpr int kMaxSteps = 1024;  // LDS of the prep kernel holds t0 x 16 pivot-row entries
 constexpr int kMaxGroups = 256;  // panel-kernel workgroups (one per CU at most)
 constexpr unsigned kSpinLimit = 1u << 22;
-constexpr size_t kCtlBytes = 256;  // barrier counter (word 0), status words (from byte 128)
+constexpr size_t kCtlBytes = 256;  // barrier (word 0), status words (byte 128), first pivot (byte 192)
 
 struct Slot {
   double val;  // |best entry| of the workgroup, 0 if it has no candidate with a nonzero entry
@@ -61,6 +61,7 @@ struct Work {
   Slot* slots;      // 2 x kMaxGroups, by step parity
   unsigned* bar;    // grid barrier counter: G arrivals per step
   int* status;      // [0] pivots found, [1] fault flag, [2] ended early
+  unsigned long long* ref;  // |first pivot| of the call (bit pattern), set by panel 0
   int64_t* piv;     // steps
 };
 
@@ -79,6 +80,7 @@ struct PanelArgs {
   int N;
   int steps;
   int t0;
+  double rel_cut;  // > 0: a pivot at or below rel_cut * |first pivot| ends the selection
   const uint8_t* excl;
   Work w;
 };
@@ -329,6 +331,8 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
   }
   int found = t0;
   bool stop = false;
+  // reference for the relative cut: |first pivot of the call| (known from panel 0 on)
+  unsigned long long ref_key = t0 > 0 ? *a.w.ref : 0ull;
 
   static_for<kPW>([&](auto ttc) {
     constexpr int tt = decltype(ttc)::value;
@@ -415,6 +419,12 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
         }
         block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);  // its barrier also publishes rows_sh
         if (gk == 0ull) stop = true;  // none left, or an exact zero column
+        if (t == 0) ref_key = gk;
+        // numerically zero: the Schur complement is rounding noise of the input's precision
+        if (a.rel_cut > 0.0 && t > 0 &&
+            gk <= static_cast<unsigned long long>(__double_as_longlong(a.rel_cut * __longlong_as_double(
+                      static_cast<long long>(ref_key)))))
+          stop = true;
       }
       if (!stop) {
         if (tid == 0) piv_sh[tt] = gi;
@@ -471,6 +481,7 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
     if (tid == 0) {
       a.w.status[0] = found;
       if (stop) a.w.status[2] = 1;
+      if (t0 == 0) *a.w.ref = ref_key;
     }
   }
 }
@@ -518,13 +529,15 @@ int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w) {
   // line) the status words
   w->ctl = reinterpret_cast<unsigned*>(p);
   w->status = reinterpret_cast<int*>(p + 128);
+  w->ref = reinterpret_cast<unsigned long long*>(p + 192);
   w->steps_cap = steps;
   w->N_cap = N;
   return ICUR_OK;
 }
 
 int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps,
-                const uint8_t* excluded, int64_t* piv, const LuppWork& w, hipStream_t st) {
+                const uint8_t* excluded, int64_t* piv, const LuppWork& w, hipStream_t st, double rel_cut) {
+  if (!(rel_cut >= 0.0 && rel_cut < 1.0)) return arg_error("lupp: need 0 <= rel_cut < 1");
   if (steps < 1 || steps > K) return arg_error("lupp: need 1 <= steps <= K");
   if (steps > kMaxSteps) return arg_error("lupp: steps above 1024 are not supported");
   if (N < 1 || ldx < N) return arg_error("lupp: need N >= 1 and ldx >= N");
@@ -552,6 +565,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   wk.chosen = w.chosen;
   wk.slots = static_cast<Slot*>(w.slots);
   wk.bar = w.ctl;
+  wk.ref = w.ref;
   wk.status = w.status;
   wk.piv = piv;
 
@@ -566,6 +580,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   PanelArgs qa;
   qa.N = static_cast<int>(N);
   qa.steps = steps;
+  qa.rel_cut = rel_cut;
   qa.excl = excluded;
   qa.w = wk;
 

@@ -48,7 +48,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-__global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t* __restrict__ G, int64_t ldg) {
+__global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t* __restrict__ G, int64_t sr,
+                                  int64_t si) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t r = blockIdx.y;
   if (i >= m || r >= c) return;
@@ -61,7 +62,7 @@ __global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t*
   const double u1 = (static_cast<double>(a) + 1.0) * 0x1.0p-53;  // (0, 1]
   const double u2 = static_cast<double>(b) * 0x1.0p-53;          // [0, 1)
   const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  G[r * ldg + i] = f32_to_bf16_rne(static_cast<float>(z));
+  G[r * sr + i * si] = f32_to_bf16_rne(static_cast<float>(z));
 }
 
 // One thread per column i of G (row i of A).  Writes the pattern and, when G_dense is
@@ -106,7 +107,17 @@ int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t 
   if (ldg < m) return arg_error("sketch: need ldg >= m");
   if (c > 65535) return arg_error("sketch rows c exceed 65535");
   dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(c));
-  hipLaunchKernelGGL(gaussian_G_kernel, grid, dim3(256), 0, st, seed, c, m, G, ldg);
+  hipLaunchKernelGGL(gaussian_G_kernel, grid, dim3(256), 0, st, seed, c, m, G, ldg, int64_t(1));
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int launch_gaussian_G_strided(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t sr, int64_t si,
+                              hipStream_t st) {
+  if (c <= 0 || m <= 0) return ICUR_OK;
+  if (c > 65535) return arg_error("sketch rows c exceed 65535");
+  dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(c));
+  hipLaunchKernelGGL(gaussian_G_kernel, grid, dim3(256), 0, st, seed, c, m, G, sr, si);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }

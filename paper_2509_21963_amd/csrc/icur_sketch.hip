@@ -355,7 +355,8 @@ int sketch_max_norm_partials(int64_t c, int64_t n) {
 
 int sketch_product(const uint16_t* G, int64_t ldg, int64_t c, const float* A, int64_t m, int64_t n,
                    int64_t lda, int terms, bool precise, double* X0, int64_t ldx, double* norm_partials,
-                   int* nparts, void* workspace, size_t workspace_bytes, hipStream_t st) {
+                   int* nparts, void* workspace, size_t workspace_bytes, hipStream_t st, hipEvent_t ev_begin,
+                   hipEvent_t ev_end) {
   if (terms < 1 || terms > 3) return ICUR_ERR_UNSUPPORTED;
   if (reinterpret_cast<uintptr_t>(A) & 3) return ICUR_ERR_UNSUPPORTED;
   if ((ldg & 7) || (reinterpret_cast<uintptr_t>(G) & 15)) return ICUR_ERR_UNSUPPORTED;
@@ -374,13 +375,17 @@ int sketch_product(const uint16_t* G, int64_t ldg, int64_t c, const float* A, in
   const int64_t k_per_split = ((blocks + nsplit - 1) / nsplit) * kKB;
   nsplit = static_cast<int>((m + k_per_split - 1) / k_per_split);
   const int64_t tiles = (n + kColsWG - 1) / kColsWG;
+  for (int64_t r0 = 0; r0 < c; r0 += kMaxMT * 16) {  // every slice has a kernel: check first
+    size_t lds = 0;
+    if (!pick(static_cast<int>((std::min<int64_t>(c - r0, kMaxMT * 16) + 15) / 16), terms, precise, &lds))
+      return ICUR_ERR_UNSUPPORTED;
+  }
   int parts = 0;
   for (int64_t r0 = 0; r0 < c; r0 += kMaxMT * 16) {
     const int64_t Ms = std::min<int64_t>(c - r0, kMaxMT * 16);
     const int mt = static_cast<int>((Ms + 15) / 16);
     size_t lds = 0;
     SketchFn fn = pick(mt, terms, precise, &lds);
-    if (!fn) return ICUR_ERR_UNSUPPORTED;
     Params p;
     p.G = G + r0 * ldg;
     p.ldg = ldg;
@@ -397,9 +402,11 @@ int sketch_product(const uint16_t* G, int64_t ldg, int64_t c, const float* A, in
     if (lds > 64 * 1024)
       ICUR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
+    if (r0 == 0 && ev_begin) ICUR_HIP(hipEventRecord(ev_begin, st));
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(nsplit)), dim3(kThreads),
                        lds, st, p);
     ICUR_HIP(hipGetLastError());
+    if (r0 == 0 && ev_end) ICUR_HIP(hipEventRecord(ev_end, st));
     if (nsplit > 1) {
       const int rblocks = static_cast<int>(std::min<int64_t>((Ms * n + 255) / 256, 1024));
       ICUR_TRY(wide::launch_reduce_f64(p.partial, nsplit, Ms, n, nullptr, 0, 0, p.out, ldx, p.norm_partials,

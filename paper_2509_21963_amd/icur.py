@@ -50,7 +50,7 @@ class Info(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["icur_run", "icur_last_info", "icur_last_error", "icur_release",
+EXPORTS = ["icur_run", "icur_run_csr", "icur_last_info", "icur_last_error", "icur_release",
            "icur_make_sketch", "icur_sketch", "icur_lupp", "icur_residual", "icur_gather",
            "icur_core_update"]
 
@@ -67,6 +67,8 @@ def load(path=LIB_PATH):
     P, I64, I32, D, U64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64
     lib.icur_run.argtypes = [P, I64, I64, I64, D, I32, I32, U64, ctypes.POINTER(Opts), P, P, P,
                              ctypes.POINTER(I64), ctypes.POINTER(D)]
+    lib.icur_run_csr.argtypes = [P, P, P, I64, I64, I64, D, I32, I32, U64, ctypes.POINTER(Opts), P, P, P,
+                                 ctypes.POINTER(I64), ctypes.POINTER(D)]
     lib.icur_last_info.argtypes = [ctypes.POINTER(Info)]
     lib.icur_last_error.restype = ctypes.c_char_p
     lib.icur_make_sketch.argtypes = [U64, I64, I64, I32, I32, P, P, P, P]
@@ -130,6 +132,36 @@ def run(A, tol, block, sketch_kind=GAUSSIAN, seed=0, precision=FP32, zeta=0, max
                       ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
                       I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
                       U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
+    _check(st, allow_warnings=True)
+    r = rank.value
+    return {"I": I[:r].copy(), "J": J[:r].copy(), "U": U[:r * r].reshape(r, r).copy(),
+            "rank": r, "rho": rho.value, "status": _STATUS_NAMES[st], "info": last_info()}
+
+
+def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, seed=0, precision=FP32,
+            zeta=0, max_rank=0, alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0):
+    """icur_run_csr on device CSR arrays (rowptr int64, colind int32, vals float32) of an
+    m x n matrix.  Returns the same dict as run()."""
+    import torch
+    lib = load()
+    m, n = shape
+    if rowptr.dtype != torch.int64 or colind.dtype != torch.int32 or vals.dtype != torch.float32:
+        raise ValueError("CSR arrays must be int64 rowptr, int32 colind, float32 vals")
+    for t, name in ((rowptr, "rowptr"), (colind, "colind"), (vals, "vals")):
+        if t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous device tensor" % name)
+    nnz = colind.numel()
+    rmax = min(m, n) if max_rank == 0 else min(int(max_rank), m, n)
+    I = np.zeros(rmax, np.int64)
+    J = np.zeros(rmax, np.int64)
+    U = np.zeros(rmax * rmax, np.float64)
+    rank = ctypes.c_int64(0)
+    rho = ctypes.c_double(0.0)
+    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), 0)
+    st = lib.icur_run_csr(_ptr(rowptr), _ptr(colind), _ptr(vals), m, n, nnz, float(tol), int(block),
+                          int(sketch_kind), ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
+                          I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
+                          U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
     _check(st, allow_warnings=True)
     r = rank.value
     return {"I": I[:r].copy(), "J": J[:r].copy(), "U": U[:r * r].reshape(r, r).copy(),

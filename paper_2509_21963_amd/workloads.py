@@ -14,7 +14,8 @@ these synthetic families):
 * exactly low rank  A = G1 G2^T with Gaussian factors (the paper's Low-Rank matrix,
   §5.1, at any size);
 * RBF kernel        A_ij = exp(-||x_i - y_j||^2 / (2 h^2)), x_i, y_j ~ U[0,1]^3;
-* batch of planted-spectrum matrices of uneven sizes and tolerances.
+* batch of planted-spectrum matrices of uneven sizes and tolerances;
+* sparse low rank plus noise (CSR): A = P Q + E with sparse Gaussian factors.
 """
 import math
 
@@ -144,6 +145,53 @@ def batch_specs(count=512, seed=0, m_range=(500, 8000), r0_range=(10.0, 400.0),
 
 def batch_sigma(r0, K):
     return np.exp(-np.arange(K) / r0)
+
+
+def _sparse_rows(rows, cols, per_row, g, scale=1.0):
+    """rows x cols CSR (scipy, FP64) with `per_row` distinct random columns per row and
+    N(0, scale^2) values."""
+    import scipy.sparse as sp
+    per_row = min(per_row, cols)
+    idx = np.argsort(g.random((rows, cols)), axis=1)[:, :per_row] if cols <= 4096 else \
+        np.stack([g.choice(cols, per_row, replace=False) for _ in range(rows)])
+    data = scale * g.standard_normal((rows, per_row))
+    indptr = np.arange(0, rows * per_row + 1, per_row, dtype=np.int64)
+    return sp.csr_matrix((data.ravel(), idx.ravel(), indptr), shape=(rows, cols))
+
+
+def sparse_lowrank(m, n, r=300, p_per_row=5, q_per_row=100, noise_per_row=20, noise=1e-8, seed=0, decay=0.0):
+    """A = P Q + E as a canonical scipy CSR matrix (FP64): P (m x r) with p_per_row
+    Gaussian entries per row, Q (r x n) with q_per_row per row, E with noise_per_row
+    entries of size `noise` per row (duplicates summed).  True rank r (the sparse
+    low-rank-plus-noise workload, default shape scaled by the caller).  decay > 0 scales
+    row k of Q by 10^(-k decay), giving a decaying spectrum."""
+    import scipy.sparse as sp
+    g = _rng(seed, 6)
+    P = _sparse_rows(m, r, p_per_row, g)
+    Q = _sparse_rows(r, n, q_per_row, g)
+    if decay:
+        Q = sp.diags(10.0 ** (-decay * np.arange(r))) @ Q
+    E = _sparse_rows(m, n, noise_per_row, g, scale=noise)
+    A = (P @ Q + E).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+def csr_to_f32(A):
+    """(rowptr int64, colind int32, vals float32) of a scipy CSR matrix, plus the FP64
+    dense copy of the rounded values (for the oracle; small matrices only)."""
+    A = A.tocsr()
+    A.sort_indices()
+    rowptr = A.indptr.astype(np.int64)
+    colind = A.indices.astype(np.int32)
+    vals = A.data.astype(np.float32)
+    return rowptr, colind, vals
+
+
+def csr_dense64(rowptr, colind, vals, shape):
+    import scipy.sparse as sp
+    return sp.csr_matrix((vals.astype(np.float64), colind, rowptr), shape=shape).toarray()
 
 
 def to_f32(A):

@@ -27,7 +27,7 @@ def declared_functions():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for want in ("icur_run", "icur_lupp", "icur_sketch", "icur_residual", "icur_gather",
+    for want in ("icur_run", "icur_run_csr", "icur_lupp", "icur_sketch", "icur_residual", "icur_gather",
                  "icur_core_update", "icur_make_sketch", "icur_release", "icur_last_error",
                  "icur_last_info"):
         assert want in names
@@ -98,3 +98,21 @@ def test_step_entry_points_reject_bad_shapes():
     assert lib.icur_gather(FAKE, 4, 4, 4, FAKE, FAKE, 2, FAKE, 4, FAKE, 4, None) == icur.ERR_ARG
     assert lib.icur_core_update(FAKE, 3, 2, 2, FAKE, FAKE, FAKE, None, None) == icur.ERR_ARG
     assert lib.icur_make_sketch(ctypes.c_uint64(0), 3, 5, 7, 0, FAKE, None, None, None) == icur.ERR_ARG
+
+
+def test_run_csr_rejects_bad_arguments_before_device_work():
+    icur, lib = _lib()
+    I = np.zeros(8, np.int64)
+    J = np.zeros(8, np.int64)
+    U = np.zeros(64)
+    rank = ctypes.c_int64(-1)
+    rho = ctypes.c_double(0.0)
+
+    def call(rowptr=FAKE, colind=FAKE, vals=FAKE, m=10, n=8, nnz=20, tol=1e-3, block=4, kind=1):
+        return lib.icur_run_csr(rowptr, colind, vals, m, n, nnz, tol, block, kind, ctypes.c_uint64(0), None,
+                                I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
+                                U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
+    for kw in (dict(rowptr=None), dict(colind=None), dict(vals=None), dict(nnz=-1), dict(nnz=2 ** 31),
+               dict(m=0), dict(n=0), dict(tol=0.0), dict(block=0), dict(block=9), dict(kind=3)):
+        assert call(**kw) == icur.ERR_ARG, kw
+        assert rank.value == -1

@@ -88,6 +88,20 @@ def test_residual_factor_precision_switch(icur, res64):
     assert got["status"] == "ok" and err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
 
 
+@pytest.mark.parametrize("form,tol", [(0, 1e-6), (1, 1e-4)])
+def test_exact_rank_inside_a_block(icur, form, tol):
+    # rank 25 with b = 10: the third block holds 5 real pivots and then noise (the FP32
+    # rounding of A, near 1e-7, and the form's own rounding).  The block stays stable
+    # (the row selection ends at a numerically zero pivot when the noise is the factors'
+    # rounding) and the loop stops after it
+    A32, _ = W.to_f32(W.exact_lowrank(500, 400, 25, seed=8))
+    got = icur.run(torch.from_numpy(A32).cuda(), tol, 10, 1, 2, precision=form)
+    A = A32.astype(np.float64)
+    err = exact_relative_error(A, got["I"].tolist(), got["J"].tolist(), got["U"])
+    assert got["status"] == "ok" and 25 <= got["rank"] <= 30
+    assert err < tol and got["rho"] < tol
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_exact_low_rank_recovery(icur, kind):
     A32, _ = W.to_f32(W.exact_lowrank(400, 300, 30, seed=5))
