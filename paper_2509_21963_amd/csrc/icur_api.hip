@@ -535,7 +535,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     }
     // N_k = S^{(k-1)}(I_k, J_k) and its inverse (FP64)
     ICUR_TRY(gather_w(Lk, m, nI, Ik, nI, true, Nblk, nI));
-    ICUR_TRY(launch_small_inverse(Nblk, nI, Nwork, &dscal->info, dscal->norms, st));
+    ICUR_TRY(launch_small_inverse(Nblk, nI, Nwork, &dscal->info, nullptr, st));
     // residual at the new rows: Sr = A(I_k,:) - Lc(I_k,:) Ur
     if (sparse) {
       if (res64)
@@ -600,7 +600,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     else
       ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
                                  false, M, r, st));
-    ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, dscal->norms, st));
+    ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, nullptr, st));
     ICUR_TRY(tm.mark(&ec1));
     std::vector<int> hinfo(nb);
     ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "icur_internal.h"
+#include "icur_wave.h"
 
 namespace icur {
 namespace {
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
   for (int e = tid; e < k * k; e += nt) a[e] = Ng[e];
   __syncthreads();
   auto colnorm_max = [&](int slot) {
+    if (norms == nullptr) return;  // uniform
     double cs = 0.0;
     if (tid < k) {
       double s = 0.0;
@@ -231,138 +233,110 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
   if (tid == 0) *info = 0;
 }
 
-// Register variant for k <= 128: thread (g, c), t = g k + c, owns column c of the rows
-// s = g, g + G, g + 2G, ... (G = 1024 / k row groups, at most RMAX rows) in registers.
-// Pivoting is implicit (no row swaps): step j picks the unused row p with the largest
-// |a(p, j)|, lowest index on ties, and eliminates column j from every other row; storage
-// row p_j then holds row j of the inverse with columns permuted, which the final write
-// undoes (inverse(j, p_c) = storage(p_j, c)).  Per step only the pivot column and the
-// pivot row travel through LDS (double buffered by step parity): two barriers per step.
-template <int RMAX>
+// Register variant for k <= 128 (no norms): thread (g, c), t = g k + c, owns column c
+// of the contiguous rows g R .. g R + R - 1 in registers (R = 4 for k <= 64, else 16;
+// every row has an owner because ceil(k / R) k <= 1024).  Pivoting is implicit (no row
+// swaps): step j picks the unused row p with the largest |a(p, j)|, lowest index on ties,
+// and eliminates column j from every other row; storage row p_j then holds row j of the
+// inverse with columns permuted, which the final write undoes (inverse(j, p_c) =
+// storage(p_j, c)).  Per step the owners of column j publish it with their best row, one
+// DPP argmax per wave reduces those candidates, the owners of row p publish it, and every
+// element takes one FMA (column j and row p are fixed up by their owners): two barriers.
+template <int R>
 __global__ __launch_bounds__(1024) void gj_inverse_reg_kernel(double* __restrict__ Ng, int k,
-                                                              int* __restrict__ info,
-                                                              double* __restrict__ norms) {
-  __shared__ double colj[2][128];
+                                                              int* __restrict__ info) {
+  __shared__ __attribute__((aligned(16))) double colj[2][256];
   __shared__ double prow[2][128];
-  __shared__ double red_v[2][16];
-  __shared__ int red_i[2][16];
+  __shared__ Red red[2][64];
   __shared__ int perm[128];   // perm[j] = p_j
   __shared__ int pinv[128];   // pinv[p_j] = j
-  __shared__ double cs[16][128];
-  const int tid = threadIdx.x;
-  const int G = min(1024 / k, 16);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int G = (k + R - 1) / R;  // row groups
   const int g = tid / k, c = tid % k;
-  const bool own = g < G;  // threads beyond G k only join the barriers
-  double a[RMAX];
-  unsigned used = 0;  // bit q: row g + G q was a pivot
+  const bool own = g < G;
+  const int r0 = g * R;
+  double a[R];
 #pragma unroll
-  for (int q = 0; q < RMAX; ++q) {
-    const int srow = g + G * q;
-    a[q] = (own && srow < k) ? Ng[srow * k + c] : 0.0;
+  for (int q = 0; q < R; ++q) {  // branch free: clamped address, then a select
+    const double v = Ng[min(r0 + q, k - 1) * k + c];
+    a[q] = (own && r0 + q < k) ? v : 0.0;
   }
-  // max column sum of |N| (an input norm for the caller's conditioning estimate)
-  auto colnorm = [&](int slot) {
-    double sum = 0.0;
-#pragma unroll
-    for (int q = 0; q < RMAX; ++q)
-      if (own && g + G * q < k) sum += fabs(a[q]);
-    if (own) cs[g][c] = sum;
-    __syncthreads();
-    if (tid < 64) {
-      double mx = 0.0;
-      for (int cc = tid; cc < k; cc += 64) {
-        double t = 0.0;
-        for (int gg = 0; gg < G; ++gg) t += cs[gg][cc];
-        mx = fmax(mx, t);
-      }
-      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-      if (tid == 0) norms[slot] = mx;
-    }
-    __syncthreads();
-  };
-  colnorm(0);
+  static_assert(R <= 64, "used-row mask is 64 bits");
+  unsigned long long used = 0;  // bit q: row r0 + q was a pivot
   for (int j = 0; j < k; ++j) {
     const int b = j & 1;
     // (1) the owners of column j publish it and their best unused row
     if (own && c == j) {
-      double bv = -1.0;
-      int bi = 0x7fffffff;
+      unsigned long long bk = 0ull;
+      int bi = INT_MAX;
 #pragma unroll
-      for (int q = 0; q < RMAX; ++q) {
-        const int srow = g + G * q;
-        if (srow < k) {
-          colj[b][srow] = a[q];
-          const double v = fabs(a[q]);
-          if (!((used >> q) & 1u) && (v > bv || (v == bv && srow < bi))) {
-            bv = v;
-            bi = srow;
-          }
+      for (int q = 0; q < R; ++q) {
+        colj[b][r0 + q] = a[q];
+        const unsigned long long kk =
+            (((used >> q) & 1ull) || r0 + q >= k) ? 0ull : cand_key(fabs(a[q]));
+        if (kk > bk) {  // rows increase with q: ties keep the lower row
+          bk = kk;
+          bi = r0 + q;
         }
       }
-      red_v[b][g] = bv;
-      red_i[b][g] = bi;
+      red[b][g] = Red{bk, bi, 0};
     }
     __syncthreads();
-    double piv_abs = -1.0;
-    int p = 0x7fffffff;
-    for (int gg = 0; gg < G; ++gg) {
-      const double v = red_v[b][gg];
-      const int i = red_i[b][gg];
-      if (v > piv_abs || (v == piv_abs && i < p)) {
-        piv_abs = v;
-        p = i;
-      }
+    // (2) every wave reduces the G candidates (lane l reads slot l); the owners of row p
+    //     publish it
+    unsigned long long sk = 0ull;
+    int si = INT_MAX;
+    if (lane < G) {
+      const Red rr = red[b][lane];
+      sk = rr.k;
+      si = rr.i;
     }
-    if (!(piv_abs > 0.0)) {
+    unsigned long long gk;
+    int p, gw;
+    wave_argmax(sk, si, 0, &gk, &p, &gw);
+    if (gk == 0ull) {
       if (tid == 0) *info = 1;
-      return;  // uniform: every thread reduced the same slots
+      return;  // uniform: every wave reduced the same slots
     }
     const double piv = colj[b][p];
-    // (2) the owners of row p publish it
-    const int gp = p % G, qp = p / G;
+    const int gp = p / R, qp = p - gp * R;
     if (own && g == gp) {
       double v = 0.0;
 #pragma unroll
-      for (int q = 0; q < RMAX; ++q)
-        if (q == qp) v = a[q];
+      for (int q = 0; q < R; ++q) v = (q == qp) ? a[q] : v;
       prow[b][c] = v;
-      used |= 1u << qp;
+      used |= 1ull << qp;
     }
     if (tid == 0) {
       perm[j] = p;
       pinv[p] = j;
     }
     __syncthreads();
-    // (3) eliminate column j from every row but p; row p is scaled
-    if (own) {
-      const double rinv = 1.0 / piv;
-      const double pr = (c == j) ? rinv : prow[b][c] * rinv;
+    // (3) a(i, c) -= a(i, j) a(p, c) / piv for all rows; then column j becomes
+    //     -a(i, j) / piv and row p becomes a(p, c) / piv (1 / piv at column j)
+    const double rinv = 1.0 / piv;
+    const double pr = prow[b][c] * rinv;
+    double f[R];
 #pragma unroll
-      for (int q = 0; q < RMAX; ++q) {
-        const int srow = g + G * q;
-        if (srow < k) {
-          if (srow == p) {
-            a[q] = pr;
-          } else {
-            const double f = colj[b][srow];
-            a[q] = (c == j) ? -f * rinv : a[q] - f * pr;
-          }
-        }
-      }
+    for (int q = 0; q < R; ++q) f[q] = colj[b][r0 + q];
+#pragma unroll
+    for (int q = 0; q < R; ++q) a[q] = a[q] - f[q] * pr;
+    if (c == j) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) a[q] = -f[q] * rinv;
+    }
+    if (g == gp) {
+      const double prr = (c == j) ? rinv : pr;
+#pragma unroll
+      for (int q = 0; q < R; ++q) a[q] = (q == qp) ? prr : a[q];
     }
   }
   __syncthreads();
-  // inverse(pinv[s], perm[c]) = storage(s, c)
   if (own) {
 #pragma unroll
-    for (int q = 0; q < RMAX; ++q) {
-      const int srow = g + G * q;
-      if (srow < k) Ng[pinv[srow] * k + perm[c]] = a[q];
-    }
+    for (int q = 0; q < R; ++q)
+      if (r0 + q < k) Ng[pinv[r0 + q] * k + perm[c]] = a[q];
   }
-  // norm of the inverse: same columns, rows permuted (column sums are unchanged by
-  // the row permutation; the column permutation only relabels them)
-  colnorm(1);
   if (tid == 0) *info = 0;
 }
 
@@ -404,9 +378,11 @@ size_t small_inverse_work_bytes(int64_t k) { return static_cast<size_t>(k) * k *
 int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
                          hipStream_t st) {
   if (k < 1 || k > 512) return arg_error("inverse: block size must be in 1..512");
-  if (k <= 128) {
-    auto fn = k <= 32 ? gj_inverse_reg_kernel<2> : (k <= 64 ? gj_inverse_reg_kernel<4> : gj_inverse_reg_kernel<16>);
-    hipLaunchKernelGGL(fn, dim3(1), dim3(1024), 0, st, N, static_cast<int>(k), info, norms);
+  if (k <= 128 && norms == nullptr) {
+    if (k <= 64)
+      hipLaunchKernelGGL((gj_inverse_reg_kernel<4>), dim3(1), dim3(1024), 0, st, N, static_cast<int>(k), info);
+    else
+      hipLaunchKernelGGL((gj_inverse_reg_kernel<16>), dim3(1), dim3(1024), 0, st, N, static_cast<int>(k), info);
     ICUR_HIP(hipGetLastError());
     return ICUR_OK;
   }

@@ -193,8 +193,8 @@ int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_
           int64_t sa1, const double* B, int64_t sb0, int64_t sb1, double beta, double* C,
           int64_t ldc, hipStream_t st);
 // In-place inverse of the k x k matrix N (ld k) by Gauss-Jordan elimination with
-// partial pivoting in FP64; info[0] = 0 on success, 1 on an exactly zero pivot;
-// info_d[1] (double) receives ||N||_1 and info_d[2] ||N^-1||_1.
+// partial pivoting in FP64; *info = 0 on success, 1 on an exactly zero pivot.  norms
+// (device, may be null) receives ||N||_1 and ||N^-1||_1 (max column sums).
 int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
                          hipStream_t st);
 size_t small_inverse_work_bytes(int64_t k);
