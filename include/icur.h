@@ -63,8 +63,10 @@ typedef struct icur_opts {
   int32_t split_terms;  /* BF16_SPLIT only: pieces per FP32 operand, 0 = from tol, 1..3 */
   int32_t sketch_fp32;  /* FP32 form only: 1 = form G A on FP32 matrix cores; 0 (default) =
                            exact products of three BF16 pieces of A with the BF16-valued G */
-  int32_t residual_fp64; /* residual-form factors in FP64 on FP64 matrix cores: 0 = when
-                            tol < 1e-5 (default), 1 = always, -1 = never */
+  int32_t residual_fp64; /* residual-form factors: 0 (default) or 1 = FP64 on the FP64
+                            matrix cores; -1 = FP32 (plain form) or BF16 pieces (split form),
+                            which round N_k^-1 before it multiplies, so the estimate can be
+                            off by about cond(N_k) 2^-24: only for well-conditioned blocks */
   int32_t reserved;      /* must be 0 */
 } icur_opts;
 

@@ -194,3 +194,17 @@ def test_strided_input_leading_dimension(icur):
     a = icur.run(view, 1e-4, 12, 0, 2)
     b = icur.run(torch.from_numpy(A32).cuda(), 1e-4, 12, 0, 2)
     assert a["J"].tolist() == b["J"].tolist() and a["I"].tolist() == b["I"].tolist()
+
+
+def test_smooth_kernel_estimate_matches_oracle(icur):
+    # RBF kernel: the pivots of one block of 100 decay by about five orders, so N_k is
+    # ill-conditioned.  The estimate after the first block must agree with the oracle's
+    # (an N_k^{-1} rounded to FP32 before it multiplies puts an error near 1e-2 on it and
+    # costs a second iteration); same rank, same iteration count
+    A32, _ = W.to_f32(W.rbf(6000, 5000, seed=0))
+    got, ora, err = check_against_oracle(icur, A32, 1e-4, 100, 1, 0, zeta=8)
+    assert got["status"] == "ok"
+    assert got["rank"] == ora["rank"]
+    assert got["info"]["iterations"] == len(ora["history"])
+    assert 0.8 <= got["rho"] / ora["rho"] <= 1.25
+    assert err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
