@@ -18,9 +18,11 @@
 //   panel kernel (one persistent grid, <= one workgroup per CU)  the 16 pivot steps on
 //       P held in registers, R rows per thread:
 //         local argmax (DPP within waves, LDS across them)  ->  the owner publishes
-//         (|value|, index, panel row) into its workgroup's slot and arrives at the grid
-//         barrier (release)  ->  every workgroup reads all slots and reduces them
-//         itself  ->  rank-one update.  One grid-wide exchange per step.
+//         (|value|, index, panel row) into its workgroup's slot with device-coherent
+//         stores, waits for them to complete and arrives at the grid barrier  ->  every
+//         workgroup reads all slots (device-coherent loads) and reduces them itself  ->
+//         rank-one update.  One grid-wide exchange per step, and no L2 write-back or
+//         invalidation: only the slot words cross workgroups inside the kernel.
 //       The multipliers replace the consumed panel entries in registers and are
 //       written to L once, at the end of the panel.
 // The panel grid is an ordinary dispatch (a cooperative launch costs about 10 us more
@@ -285,15 +287,23 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
             pub[jj] |= static_cast<unsigned long long>(__double_as_longlong(x[r][jj])) & mask;
         }
 #pragma unroll
-        for (int jj = tt; jj < kPW; ++jj) slot->row[jj] = __longlong_as_double(static_cast<long long>(pub[jj]));
-        slot->val = __longlong_as_double(static_cast<long long>(gk));
-        slot->idx = gi;
+        for (int jj = tt; jj < kPW; ++jj)
+          __hip_atomic_store(&slot->row[jj], __longlong_as_double(static_cast<long long>(pub[jj])), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot->val, __longlong_as_double(static_cast<long long>(gk)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot->idx, static_cast<long long>(gi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if (gk == 0ull && tid == 0) {
-        slot->val = 0.0;
-        slot->idx = INT_MAX;
+        __hip_atomic_store(&slot->val, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot->idx, static_cast<long long>(INT_MAX), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (owner || (gk == 0ull && tid == 0))
-        __hip_atomic_fetch_add(a.w.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (owner || (gk == 0ull && tid == 0)) {
+        // The slot words are device-coherent stores; waiting for their completion
+        // before the arrival orders them without a release fence, which would write
+        // back this XCD's whole L2 at every step.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __hip_atomic_fetch_add(a.w.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       // (c) wait for every workgroup's arrival (thread 0 polls, bounded)
       if (tid == 0) {
         const unsigned target = static_cast<unsigned>(t + 1) * static_cast<unsigned>(G);
@@ -312,7 +322,8 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
             break;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // no acquire fence: every slot word is read with device-coherent loads, issued
+        // after the counter was seen complete (and after the block barrier below)
         flag = ok;
       }
       __syncthreads();
