@@ -126,6 +126,37 @@ int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals
                  uint64_t seed, const icur_opts* opts, int64_t* I, int64_t* J, double* U,
                  int64_t* rank, double* est_err);
 
+/*
+ * icur_run_batched: Alg. 1 on `count` independent dense FP32 matrices of uneven sizes and
+ * tolerances (many small CUR problems at once; each follows Alg. 1 on its own).  The
+ * matrices run concurrently, four at a time, each on a worker stream of its own with its
+ * own cached workspace, largest first; the caller's stream (opts->stream) is waited on
+ * before any of them starts.  Each matrix gets exactly the result icur_run would return
+ * for it (same kernels, same arithmetic).
+ *   count        >= 0 (0 returns ICUR_OK at once).
+ *   A, m, n, lda host arrays of count entries: device pointer, rows, columns and leading
+ *                dimension of each matrix (row-major, lda[i] >= n[i]).
+ *   tol, seed    host arrays of count entries: tolerance and sketch seed per matrix.
+ *   block, sketch_kind, opts: shared by all matrices as in icur_run (opts->stream is
+ *                the caller's stream; opts->max_rank caps every matrix).
+ *   cap_offsets  host, count + 1 nondecreasing entries, cap_offsets[0] = 0.  Matrix i
+ *                owns I_pool / J_pool entries cap_offsets[i] .. cap_offsets[i+1]-1; this
+ *                capacity must be at least min(m[i], n[i], max_rank).
+ *   I_pool, J_pool  host int64, cap_offsets[count] entries each.
+ *   U_pool       host doubles, sum of cap_i^2 entries: matrix i's core (rank_i x rank_i,
+ *                leading dimension rank_i) starts at sum_{j<i} cap_j^2.
+ *   rank, est_err, status  host arrays of count entries: per-matrix rank, final rho and
+ *                return code of that matrix's run.
+ * Every argument of every matrix is checked before any device work.  Returns ICUR_OK when
+ * no matrix failed (warnings such as ICUR_MAXRANK are in status[]), else the error code of
+ * the lowest-numbered failed matrix, with icur_last_error naming it.
+ */
+int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, const int64_t* n,
+                     const int64_t* lda, const double* tol, int32_t block, int32_t sketch_kind,
+                     const uint64_t* seed, const icur_opts* opts, int64_t* I_pool, int64_t* J_pool,
+                     double* U_pool, const int64_t* cap_offsets, int64_t* rank, double* est_err,
+                     int32_t* status);
+
 /* Statistics of the calling thread's most recent icur_run (copied into *info). */
 int icur_last_info(icur_info* info);
 

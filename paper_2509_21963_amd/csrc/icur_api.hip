@@ -2,12 +2,15 @@
 // driver of Alg. 1 (IterativeCUR).  Every step of the loop runs in the kernels of the
 // other translation units; the host only orders launches, reads back three scalars per
 // iteration (two pivot counts and the residual norm) and decides when to stop.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "icur_internal.h"
@@ -54,21 +57,28 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// One workspace per (device, slot).  Slot 0 serves the single-matrix calls; the batched
+// call gives each of its concurrent workers a slot of its own, with its own stream.
 struct DeviceCache {
   std::mutex mu;
+  int device = 0;
   Buf buf[kNumSlots];
   void* host_pinned = nullptr;  // small staging area for scalar read-backs
   std::vector<hipEvent_t> events;
+  hipStream_t stream = nullptr;  // worker stream of a batched slot (default priority)
   ~DeviceCache() {}
 };
 
 std::mutex g_cache_mu;
-std::map<int, std::unique_ptr<DeviceCache>> g_cache;
+std::map<std::pair<int, int>, std::unique_ptr<DeviceCache>> g_cache;
 
-DeviceCache& cache_for(int dev) {
+DeviceCache& cache_for(int dev, int slot) {
   std::lock_guard<std::mutex> g(g_cache_mu);
-  auto& p = g_cache[dev];
-  if (!p) p.reset(new DeviceCache());
+  auto& p = g_cache[{dev, slot}];
+  if (!p) {
+    p.reset(new DeviceCache());
+    p->device = dev;
+  }
   return *p;
 }
 
@@ -176,19 +186,15 @@ int read_int(DeviceCache& dc, const int* dev, int* host, int count, hipStream_t 
   return ICUR_OK;
 }
 
-int prepare_device(DeviceCache** out) {
+int prepare_device(DeviceCache** out, int slot = 0) {
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
-  DeviceCache& dc = cache_for(dev.device);
+  DeviceCache& dc = cache_for(dev.device, slot);
   if (!dc.host_pinned) ICUR_HIP(hipHostMalloc(&dc.host_pinned, 4096, hipHostMallocDefault));
   *out = &dc;
   return ICUR_OK;
 }
 
-// BF16 pieces per FP32 operand for a tolerance.  One piece rounds with relative error
-// up to 2^-8, two with 2^-16, three reproduce FP32.  The sketched residual's noise
-// floor is this error amplified by the interpolation coefficients of the cross, so the
-// count leaves a wide margin: one piece only for very loose tolerances.
 // Sketch accumulation: FP32 sums over 128 rows of A give X0 a relative noise near
 // sqrt(128) 2^-24; the column residual subtracts X0(:,J) times interpolation coefficients
 // whose norm reaches tens on ill-conditioned crosses, which puts a floor near 1e-5 under
@@ -201,6 +207,10 @@ constexpr double kSketchChunkFlushBelow = 1e-4;
 constexpr double kRowCutFp64 = 0x1.0p-40;
 constexpr double kRowCutFp32 = 0x1.0p-16;
 
+// BF16 pieces per FP32 operand for a tolerance.  One piece rounds with relative error
+// up to 2^-8, two with 2^-16, three reproduce FP32.  The sketched residual's noise
+// floor is this error amplified by the interpolation coefficients of the cross, so the
+// count leaves a wide margin: one piece only for very loose tolerances.
 int terms_for_tol(double tol) {
   if (tol >= 1e-1) return 1;
   if (tol >= 5e-4) return 2;
@@ -231,13 +241,10 @@ struct Source {
   const CsrMatrix* csr = nullptr;  // checked and copied to CSC by run_impl
 };
 
-int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block, int32_t kind, uint64_t seed,
-             const icur_opts* opts, int64_t* I_out, int64_t* J_out, double* U_out, int64_t* rank_out,
-             double* est_out, std::chrono::steady_clock::time_point t_start) {
-  const float* A = src.A;
-  const int64_t lda = src.lda;
-  const bool sparse = (src.csr != nullptr);
-  // ---- arguments (before any device work)
+// Every argument check of a run, before any device work: shape, tolerance, block, sketch
+// kind and options.  On success *o holds the options with defaults applied.
+int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t lda, double tol, int32_t block,
+                   int32_t kind, const icur_opts* opts, icur_opts* o) {
   if (!A && !sparse) return arg_error("A is null");
   if (m < 1 || n < 1) return arg_error("need m >= 1 and n >= 1");
   if (!sparse && lda < n) return arg_error("need lda >= n");
@@ -245,23 +252,42 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   if (block < 1 || block > std::min(m, n)) return arg_error("need 1 <= block <= min(m, n)");
   if (kind != ICUR_SKETCH_GAUSSIAN && kind != ICUR_SKETCH_SPARSE_SIGN)
     return arg_error("unknown sketch kind");
-  if (!I_out || !J_out || !U_out || !rank_out || !est_out) return arg_error("null output pointer");
   if (m > 0x7fffffffLL || n > 0x7fffffffLL) return arg_error("m and n must be below 2^31");
-  icur_opts o;
-  std::memset(&o, 0, sizeof(o));
-  if (opts) o = *opts;
+  std::memset(o, 0, sizeof(*o));
+  if (opts) *o = *opts;
   const int64_t b = block;
   const int64_t c = (11 * b) / 10;
   if (c > 4096) return arg_error("sketch rows c = floor(1.1 b) above 4096 are not supported");
   if (b > 1024) return arg_error("block above 1024 is not supported");
   if (kind == ICUR_SKETCH_SPARSE_SIGN && c > 255) return arg_error("sparse-sign sketch needs c <= 255");
   if (sparse && c > 256) return arg_error("the CSR sketch needs c = floor(1.1 b) <= 256");
+  if (o->zeta < 0 || o->zeta > 8) return arg_error("zeta must be at most 8");
+  if (o->precision != ICUR_FP32 && o->precision != ICUR_BF16_SPLIT) return arg_error("unknown precision");
+  if (o->split_terms < 0 || o->split_terms > 3) return arg_error("split_terms must be 0..3");
+  if (o->residual_fp64 < -1 || o->residual_fp64 > 1) return arg_error("residual_fp64 must be -1, 0 or 1");
+  if (o->max_rank < 0) return arg_error("max_rank must be >= 0");
+  if (o->reserved != 0) return arg_error("reserved must be 0");
+  int st_risk = ICUR_OK;
+  (void)risk_factor(o->alpha, o->delta, c, &st_risk);
+  return st_risk;
+}
+
+// cache_slot: the workspace to use (0 for single calls); lupp_groups > 0 caps the
+// workgroups of the selection grids (concurrent batched workers share the CUs).
+int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block, int32_t kind, uint64_t seed,
+             const icur_opts* opts, int64_t* I_out, int64_t* J_out, double* U_out, int64_t* rank_out,
+             double* est_out, std::chrono::steady_clock::time_point t_start, int cache_slot = 0,
+             int lupp_groups = 0) {
+  const float* A = src.A;
+  const int64_t lda = src.lda;
+  const bool sparse = (src.csr != nullptr);
+  // ---- arguments (before any device work)
+  if (!I_out || !J_out || !U_out || !rank_out || !est_out) return arg_error("null output pointer");
+  icur_opts o;
+  ICUR_TRY(check_run_args(sparse, A, m, n, lda, tol, block, kind, opts, &o));
+  const int64_t b = block;
+  const int64_t c = (11 * b) / 10;
   const int zeta = o.zeta > 0 ? o.zeta : 8;
-  if (zeta > 8) return arg_error("zeta must be at most 8");
-  if (o.precision != ICUR_FP32 && o.precision != ICUR_BF16_SPLIT) return arg_error("unknown precision");
-  if (o.split_terms < 0 || o.split_terms > 3) return arg_error("split_terms must be 0..3");
-  if (o.residual_fp64 < -1 || o.residual_fp64 > 1) return arg_error("residual_fp64 must be -1, 0 or 1");
-  if (o.max_rank < 0) return arg_error("max_rank must be >= 0");
   const int64_t rmax = (o.max_rank == 0) ? std::min(m, n) : std::min(o.max_rank, std::min(m, n));
   int st_risk = ICUR_OK;
   const double xi = risk_factor(o.alpha, o.delta, c, &st_risk);
@@ -282,7 +308,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   hipStream_t st = as_stream(o.stream);
 
   DeviceCache* dcp = nullptr;
-  ICUR_TRY(prepare_device(&dcp));
+  ICUR_TRY(prepare_device(&dcp, cache_slot));
   DeviceCache& dc = *dcp;
   std::lock_guard<std::mutex> lock(dc.mu);
   DeviceInfo dev;
@@ -315,7 +341,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   ICUR_TRY(ensure(dc, kRowMask, static_cast<size_t>(m), &pRowMask));
   ICUR_TRY(ensure(dc, kJk, static_cast<size_t>(b) * 8, &pJk));
   ICUR_TRY(ensure(dc, kIk, static_cast<size_t>(b) * 8, &pIk));
-  ICUR_TRY(ensure(dc, kA22, static_cast<size_t>(b) * b * 8 + small_inverse_work_bytes(b), &pN));
+  ICUR_TRY(ensure(dc, kA22, static_cast<size_t>(b) * b * 16 + small_inverse_work_bytes(b), &pN));
   ICUR_TRY(ensure(dc, kLupp, lupp_workspace_bytes(b, std::max(m, n)), &pLupp));
   const int64_t BIGK = int64_t(1) << 40;
   size_t gemm_ws = wide_gemm_workspace_bytes(c, m, n, dev.num_cus);
@@ -331,10 +357,12 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
   LuppWork lw;
   lupp_bind_workspace(pLupp, b, std::max(m, n), &lw);
+  lw.max_groups = lupp_groups;
   Scal* dscal = static_cast<Scal*>(pScal);
   double* dnorm = static_cast<double*>(pNorm);
   double* Nblk = static_cast<double*>(pN);                 // b x b, then its inverse
-  double* Nwork = Nblk + static_cast<size_t>(b) * b;       // Gauss-Jordan work (b > 128)
+  double* N1inv = Nblk + static_cast<size_t>(b) * b;       // N_1^{-1}, kept for the core
+  double* Nwork = N1inv + static_cast<size_t>(b) * b;      // Gauss-Jordan work (b > 128)
   const int64_t bc = std::max(b, c);
 
   // ---- rank-sized buffers, grown geometrically: the residual-form factors
@@ -537,6 +565,8 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     // N_k = S^{(k-1)}(I_k, J_k) and its inverse (FP64)
     ICUR_TRY(gather_w(Lk, m, nI, Ik, nI, true, Nblk, nI));
     ICUR_TRY(launch_small_inverse(Nblk, nI, Nwork, &dscal->info, nullptr, st));
+    // N_1 = A(I_1, J_1) exactly: its inverse is the core's first diagonal block inverse
+    if (r == 0) ICUR_HIP(hipMemcpyAsync(N1inv, Nblk, static_cast<size_t>(nI) * nI * 8, hipMemcpyDeviceToDevice, st));
     // residual at the new rows: Sr = A(I_k,:) - Lc(I_k,:) Ur
     if (sparse) {
       if (res64)
@@ -601,7 +631,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     else
       ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
                                  false, M, r, st));
-    ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, nullptr, st));
+    ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, nullptr, st, N1inv));
     ICUR_TRY(tm.mark(&ec1));
     std::vector<int> hinfo(nb);
     ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -657,6 +687,122 @@ int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals
   return run_impl(src, m, n, tol, block, sketch_kind, seed, opts, I, J, U, rank, est_err, t0);
 }
 
+int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, const int64_t* n,
+                     const int64_t* lda, const double* tol, int32_t block, int32_t sketch_kind,
+                     const uint64_t* seed, const icur_opts* opts, int64_t* I_pool, int64_t* J_pool,
+                     double* U_pool, const int64_t* cap_offsets, int64_t* rank, double* est_err,
+                     int32_t* status) {
+  const auto t0 = std::chrono::steady_clock::now();
+  t_error.clear();
+  std::memset(&t_info, 0, sizeof(t_info));
+  if (count < 0) return arg_error("count must be >= 0");
+  if (count == 0) return ICUR_OK;
+  if (!A || !m || !n || !lda || !tol || !seed || !cap_offsets || !I_pool || !J_pool || !U_pool || !rank ||
+      !est_err || !status)
+    return arg_error("null array argument");
+  // ---- every argument of every matrix, before any device work
+  icur_opts o;
+  std::vector<int64_t> uoff(static_cast<size_t>(count) + 1, 0);
+  if (cap_offsets[0] != 0) return arg_error("cap_offsets[0] must be 0");
+  for (int32_t i = 0; i < count; ++i) {
+    const int e = check_run_args(false, A[i], m[i], n[i], lda[i], tol[i], block, sketch_kind, opts, &o);
+    if (e != ICUR_OK) {
+      set_error("matrix " + std::to_string(i) + ": " + t_error);
+      return e;
+    }
+    const int64_t cap = cap_offsets[i + 1] - cap_offsets[i];
+    const int64_t rmax = (o.max_rank == 0) ? std::min(m[i], n[i]) : std::min(o.max_rank, std::min(m[i], n[i]));
+    if (cap < rmax)
+      return arg_error("matrix " + std::to_string(i) + ": capacity " + std::to_string(cap) + " below its rank bound " +
+                       std::to_string(rmax));
+    uoff[i + 1] = uoff[i] + cap * cap;
+  }
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  const hipStream_t caller = as_stream(o.stream);
+
+  // ---- workers: kBatchWorkers concurrent runs, each on its own slot and stream.  The
+  // selection grids of concurrent runs share the CUs, so each is capped at its share;
+  // a matrix too large for the share runs afterwards, alone.
+  constexpr int kBatchWorkers = 4;
+  const int S = std::min<int32_t>(count, kBatchWorkers);
+  const int gcap = std::max(1, dev.num_cus / S);
+  std::vector<int> small, large;
+  for (int32_t i = 0; i < count; ++i)
+    (std::max(m[i], n[i]) <= lupp_max_candidates(gcap) ? small : large).push_back(i);
+  auto by_size = [&](int x, int y) { return m[x] * n[x] > m[y] * n[y] || (m[x] * n[x] == m[y] * n[y] && x < y); };
+  std::sort(small.begin(), small.end(), by_size);
+  std::sort(large.begin(), large.end(), by_size);
+  std::vector<hipStream_t> streams(S);
+  for (int s = 0; s < S; ++s) {
+    DeviceCache* dcp;
+    ICUR_TRY(prepare_device(&dcp, 1 + s));
+    std::lock_guard<std::mutex> lock(dcp->mu);
+    if (!dcp->stream) ICUR_HIP(hipStreamCreateWithFlags(&dcp->stream, hipStreamNonBlocking));
+    streams[s] = dcp->stream;
+  }
+  hipEvent_t ready;
+  ICUR_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  ICUR_HIP(hipEventRecord(ready, caller));
+  for (int s = 0; s < S; ++s) ICUR_HIP(hipStreamWaitEvent(streams[s], ready, 0));
+
+  // a matrix stays marked as not run unless a worker reaches it
+  std::vector<std::string> errs(static_cast<size_t>(count), "not run: no worker thread could select the device");
+  for (int32_t i = 0; i < count; ++i) status[i] = ICUR_ERR_HIP;
+  int64_t total_iters = 0;
+  std::mutex iters_mu;
+  auto run_one = [&](int i, int s, int groups) {
+    icur_opts oo = o;
+    oo.stream = streams[s];
+    t_error.clear();
+    std::memset(&t_info, 0, sizeof(t_info));
+    Source src;
+    src.A = A[i];
+    src.lda = lda[i];
+    const int st = run_impl(src, m[i], n[i], tol[i], block, sketch_kind, seed[i], &oo, I_pool + cap_offsets[i],
+                            J_pool + cap_offsets[i], U_pool + uoff[i], rank + i, est_err + i,
+                            std::chrono::steady_clock::now(), 1 + s, groups);
+    status[i] = st;
+    if (st < 0) {
+      errs[i] = t_error;
+      rank[i] = 0;
+      est_err[i] = 0.0;
+    }
+    std::lock_guard<std::mutex> g(iters_mu);
+    total_iters += t_info.iterations;
+  };
+  std::atomic<size_t> next{0};
+  std::vector<std::thread> pool;
+  for (int s = 0; s < S; ++s)
+    pool.emplace_back([&, s]() {
+      if (hipSetDevice(dev.device) != hipSuccess) return;
+      for (;;) {
+        const size_t q = next.fetch_add(1);
+        if (q >= small.size()) break;
+        run_one(small[q], s, gcap);
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (int i : large) run_one(i, 0, 0);
+  (void)hipEventDestroy(ready);
+  int first_err = ICUR_OK;
+  std::string msg;
+  for (int32_t i = 0; i < count; ++i) {
+    if (status[i] < 0 && first_err == ICUR_OK) {
+      first_err = status[i];
+      msg = "matrix " + std::to_string(i) + ": " + errs[i];
+    }
+  }
+  std::memset(&t_info, 0, sizeof(t_info));
+  t_info.iterations = static_cast<int32_t>(std::min<int64_t>(total_iters, INT32_MAX));
+  t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (first_err != ICUR_OK) {
+    set_error(msg);
+    return first_err;
+  }
+  return ICUR_OK;
+}
+
 int icur_last_info(icur_info* info) {
   if (!info) return ICUR_ERR_ARG;
   *info = t_info;
@@ -672,7 +818,9 @@ int icur_release(void) {
   for (auto& kv : g_cache) {
     DeviceCache& dc = *kv.second;
     std::lock_guard<std::mutex> l(dc.mu);
-    ICUR_HIP(hipSetDevice(kv.first));
+    ICUR_HIP(hipSetDevice(dc.device));
+    if (dc.stream) ICUR_HIP(hipStreamDestroy(dc.stream));
+    dc.stream = nullptr;
     for (auto& b : dc.buf) {
       if (b.p) ICUR_HIP(hipFree(b.p));
       b.p = nullptr;

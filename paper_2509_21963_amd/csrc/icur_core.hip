@@ -427,17 +427,27 @@ size_t core_update_ws_doubles(int64_t r, int64_t k) { return 2 * k * k + 2 * k *
 // forward and back substitution on the identity.  U (ld r) receives the inverse.
 // ws holds core_inverse_ws_doubles(r, bmax) doubles.
 int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblocks, int64_t bmax, double* U,
-                       double* ws, int* info, double* norms, hipStream_t st) {
+                       double* ws, int* info, double* norms, hipStream_t st, const double* D0inv) {
   double* Dinv = ws;                           // r x bmax: the diagonal block inverses, stacked
   double* T = Dinv + r * bmax;                 // bmax x r temporary
   double* gjw = T + bmax * r;                  // bmax x bmax Gauss-Jordan work
+  if (D0inv && nblocks == 1 && norms == nullptr) {
+    ICUR_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(info), 1, 0u, st));
+    ICUR_HIP(hipMemcpyAsync(U, D0inv, static_cast<size_t>(r) * r * 8, hipMemcpyDeviceToDevice, st));
+    return ICUR_OK;
+  }
   // block LU: M = L~ U~ with L~ unit block lower (stored below the diagonal blocks)
   int64_t q = 0;
   for (int64_t k = 0; k < nblocks; ++k) {
     const int64_t nk = blocks[k];
     double* Dk = Dinv + q * bmax;              // nk x nk, ld nk
-    ICUR_TRY(dcopy2d(nk, nk, 1.0, M + q * r + q, r, Dk, nk, st));
-    ICUR_TRY(launch_small_inverse(Dk, nk, gjw, info + k, norms, st));
+    if (k == 0 && D0inv && norms == nullptr) {
+      ICUR_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(info), 1, 0u, st));
+      ICUR_HIP(hipMemcpyAsync(Dk, D0inv, static_cast<size_t>(nk) * nk * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+      ICUR_TRY(dcopy2d(nk, nk, 1.0, M + q * r + q, r, Dk, nk, st));
+      ICUR_TRY(launch_small_inverse(Dk, nk, gjw, info + k, norms, st));
+    }
     const int64_t rest = r - q - nk;
     if (rest > 0) {
       // L~ panel: M[q+nk:, q:q+nk] <- M[q+nk:, q:q+nk] D_k^{-1}   (via T, rest x nk)

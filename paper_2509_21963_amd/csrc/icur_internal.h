@@ -155,8 +155,11 @@ struct LuppWork {
   int* status;        // [0] npiv, [1] fault flag, [2] ended early (inside ctl)
   unsigned long long* ref;  // |first pivot| bit pattern (inside ctl)
   int64_t steps_cap, N_cap;
+  int max_groups;     // > 0: cap on the panel grid's workgroups (0: one per CU)
 };
 size_t lupp_workspace_bytes(int64_t steps, int64_t N);
+// Candidates one panel grid of at most max_groups workgroups holds.
+int64_t lupp_max_candidates(int max_groups);
 int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w);
 // Pivots of LUPP on T = X^T (see icur_lupp); X is FP32, or FP64 when x64.  piv is
 // device; the pivot count and a fault flag land in w.status.  rel_cut > 0 also ends the
@@ -209,9 +212,12 @@ int core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y, i
 size_t core_update_ws_doubles(int64_t r, int64_t k);
 // U = A(I,J)^{-1} from the gathered cross M (r x r, ld r, overwritten): block LU in the
 // selection order, then block triangular solves on the identity.  info has one entry
-// per block (0 = regular).  ws: core_inverse_ws_doubles(r, bmax) doubles.
+// per block (0 = regular).  ws: core_inverse_ws_doubles(r, bmax) doubles.  D0inv, when
+// given, is the inverse of the first diagonal block M(0:b0, 0:b0) (b0 = blocks[0], ld b0),
+// already formed by the same kernel on the same values; it is used instead of inverting
+// that block again, and with a single block U is a copy of it.
 int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblocks, int64_t bmax, double* U,
-                       double* ws, int* info, double* norms, hipStream_t st);
+                       double* ws, int* info, double* norms, hipStream_t st, const double* D0inv = nullptr);
 size_t core_inverse_ws_doubles(int64_t r, int64_t bmax);
 int launch_fill_f64_identity(double* U, int64_t r, hipStream_t st);
 

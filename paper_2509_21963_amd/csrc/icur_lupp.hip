@@ -456,7 +456,13 @@ int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w) {
   w->ref = reinterpret_cast<unsigned long long*>(p + 192);
   w->steps_cap = steps;
   w->N_cap = N;
+  w->max_groups = 0;
   return ICUR_OK;
+}
+
+int64_t lupp_max_candidates(int max_groups) {
+  const PanelShape& big = kShape[kShapes - 1];
+  return static_cast<int64_t>(std::min(max_groups, kMaxGroups)) * big.R * big.LT;
 }
 
 int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps,
@@ -471,7 +477,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   ICUR_TRY(device_info(&dev));
   // Rows per workgroup: the per-step exchange costs more with more workgroups, so
   // pack more candidates per workgroup and aim for about 16 of them.
-  const int max_groups = std::min(dev.num_cus, kMaxGroups);
+  const int max_groups = std::min(std::min(dev.num_cus, kMaxGroups), w.max_groups > 0 ? w.max_groups : kMaxGroups);
   int sh = 0;
   while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * 16 < N) ++sh;
   const int64_t per_group = static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT;

@@ -50,7 +50,7 @@ class Info(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["icur_run", "icur_run_csr", "icur_last_info", "icur_last_error", "icur_release",
+EXPORTS = ["icur_run", "icur_run_csr", "icur_run_batched", "icur_last_info", "icur_last_error", "icur_release",
            "icur_make_sketch", "icur_sketch", "icur_lupp", "icur_residual", "icur_gather",
            "icur_core_update"]
 
@@ -69,6 +69,7 @@ def load(path=LIB_PATH):
                              ctypes.POINTER(I64), ctypes.POINTER(D)]
     lib.icur_run_csr.argtypes = [P, P, P, I64, I64, I64, D, I32, I32, U64, ctypes.POINTER(Opts), P, P, P,
                                  ctypes.POINTER(I64), ctypes.POINTER(D)]
+    lib.icur_run_batched.argtypes = [I32, P, P, P, P, P, I32, I32, P, ctypes.POINTER(Opts), P, P, P, P, P, P, P]
     lib.icur_last_info.argtypes = [ctypes.POINTER(Info)]
     lib.icur_last_error.restype = ctypes.c_char_p
     lib.icur_make_sketch.argtypes = [U64, I64, I64, I32, I32, P, P, P, P]
@@ -166,6 +167,54 @@ def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, se
     r = rank.value
     return {"I": I[:r].copy(), "J": J[:r].copy(), "U": U[:r * r].reshape(r, r).copy(),
             "rank": r, "rho": rho.value, "status": _STATUS_NAMES[st], "info": last_info()}
+
+
+def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP32, zeta=0, max_rank=0,
+                alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, check=True):
+    """icur_run_batched on a list of m_i x n_i FP32 device tensors with per-matrix tolerances
+    (and seeds, default 0..count-1).  Returns a list of dicts like run() (without info), each
+    with its own "status"; raises on a failed matrix when check is True."""
+    import torch
+    lib = load()
+    count = len(As)
+    if len(tols) != count:
+        raise ValueError("need one tolerance per matrix")
+    seeds = list(range(count)) if seeds is None else list(seeds)
+    if len(seeds) != count:
+        raise ValueError("need one seed per matrix")
+    for i, A in enumerate(As):
+        _require(A, torch.float32, "A[%d]" % i)
+    ptrs = (ctypes.c_void_p * max(count, 1))(*[A.data_ptr() for A in As])
+    m = np.array([A.shape[0] for A in As], np.int64)
+    n = np.array([A.shape[1] for A in As], np.int64)
+    lda = np.array([A.stride(0) for A in As], np.int64)
+    tol = np.array(tols, np.float64)
+    sd = np.array([int(x) & 0xFFFFFFFFFFFFFFFF for x in seeds], np.uint64)
+    cap = np.minimum(m, n) if max_rank == 0 else np.minimum(np.minimum(m, n), int(max_rank))
+    offs = np.zeros(count + 1, np.int64)
+    offs[1:] = np.cumsum(cap)
+    uoffs = np.zeros(count + 1, np.int64)
+    uoffs[1:] = np.cumsum(cap * cap)
+    I = np.zeros(max(int(offs[-1]), 1), np.int64)
+    J = np.zeros(max(int(offs[-1]), 1), np.int64)
+    U = np.zeros(max(int(uoffs[-1]), 1), np.float64)
+    rank = np.zeros(max(count, 1), np.int64)
+    est = np.zeros(max(count, 1), np.float64)
+    status = np.zeros(max(count, 1), np.int32)
+    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), 0)
+    c_ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    st = lib.icur_run_batched(count, ptrs, c_ptr(m), c_ptr(n), c_ptr(lda), c_ptr(tol), int(block), int(sketch_kind),
+                              c_ptr(sd), ctypes.byref(o), c_ptr(I), c_ptr(J), c_ptr(U), c_ptr(offs), c_ptr(rank),
+                              c_ptr(est), c_ptr(status))
+    if check:
+        _check(st)
+    out = []
+    for i in range(count):
+        r = int(rank[i])
+        out.append({"I": I[offs[i]:offs[i] + r].copy(), "J": J[offs[i]:offs[i] + r].copy(),
+                    "U": U[uoffs[i]:uoffs[i] + r * r].reshape(r, r).copy(), "rank": r, "rho": float(est[i]),
+                    "status": _STATUS_NAMES.get(int(status[i]), str(int(status[i])))})
+    return out
 
 
 def last_info():

@@ -27,7 +27,7 @@ def declared_functions():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for want in ("icur_run", "icur_run_csr", "icur_lupp", "icur_sketch", "icur_residual", "icur_gather",
+    for want in ("icur_run", "icur_run_csr", "icur_run_batched", "icur_lupp", "icur_sketch", "icur_residual", "icur_gather",
                  "icur_core_update", "icur_make_sketch", "icur_release", "icur_last_error",
                  "icur_last_info"):
         assert want in names
@@ -79,7 +79,7 @@ def test_run_rejects_bad_options():
     icur, lib = _lib()
     for o in (icur.Opts(precision=5), icur.Opts(zeta=9), icur.Opts(split_terms=4),
               icur.Opts(max_rank=-1), icur.Opts(alpha=1e-10),     # c = 2 < -4 ln(alpha)
-              icur.Opts(residual_fp64=2)):
+              icur.Opts(residual_fp64=2), icur.Opts(zeta=-1), icur.Opts(reserved=1)):
         st, _ = _run_args(lib, opts=ctypes.byref(o))
         assert st == icur.ERR_ARG, (o.precision, o.zeta)
     # sparse-sign needs c <= 255
@@ -116,3 +116,46 @@ def test_run_csr_rejects_bad_arguments_before_device_work():
                dict(m=0), dict(n=0), dict(tol=0.0), dict(block=0), dict(block=9), dict(kind=3)):
         assert call(**kw) == icur.ERR_ARG, kw
         assert rank.value == -1
+
+
+def test_run_batched_rejects_bad_arguments_before_device_work():
+    icur, lib = _lib()
+    count = 3
+
+    def arr(values, dt):
+        a = np.array(values, dt)
+        return a, a.ctypes.data_as(ctypes.c_void_p)
+
+    def call(ms=(10, 12, 9), ns=(8, 8, 7), ldas=(8, 8, 7), tols=(1e-3, 1e-3, 1e-3), caps=(8, 8, 7), block=2,
+             cnt=count, first_off=0, ptrs=True):
+        keep = []
+        P = (ctypes.c_void_p * count)(*([0x1000] * count))
+        m_, pm = arr(ms, np.int64)
+        n_, pn = arr(ns, np.int64)
+        l_, pl = arr(ldas, np.int64)
+        t_, pt = arr(tols, np.float64)
+        s_, ps = arr([0] * count, np.uint64)
+        offs = np.zeros(count + 1, np.int64)
+        offs[1:] = np.cumsum(caps)
+        offs[0] = first_off
+        I = np.zeros(64, np.int64)
+        J = np.zeros(64, np.int64)
+        U = np.zeros(4096)
+        rank = np.full(count, -1, np.int64)
+        est = np.zeros(count)
+        status = np.full(count, 99, np.int32)
+        keep += [m_, n_, l_, t_, s_]
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        st = lib.icur_run_batched(cnt, P if ptrs else None, pm, pn, pl, pt, block, 0, ps, None, c(I), c(J), c(U),
+                                  c(offs), c(rank), c(est), c(status))
+        return st, rank, status
+
+    for kw in (dict(cnt=-1), dict(ptrs=False), dict(ms=(10, 0, 9)), dict(ldas=(8, 7, 7)),
+               dict(tols=(1e-3, float("nan"), 1e-3)), dict(caps=(8, 7, 7)), dict(block=8), dict(first_off=1)):
+        st, rank, status = call(**kw)
+        assert st == icur.ERR_ARG, kw
+        assert (rank == -1).all() and (status == 99).all(), kw   # nothing ran, nothing written
+    st, _, _ = call(ms=(10, 0, 9))
+    assert b"matrix 1" in lib.icur_last_error()
+    # count 0 is a no-op
+    assert call(cnt=0)[0] == icur.OK

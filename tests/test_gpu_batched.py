@@ -1,0 +1,127 @@
+"""icur_run_batched: many uneven matrices with their own tolerances (GPU).
+
+Each matrix of a batch must come back exactly as icur_run returns it on its own (the
+batched call runs the same kernels on worker streams), and the results must meet the
+oracle's bar: the selected indices agree with the FP64 oracle up to its first near tie,
+the exact error ||A - CUR||_F / ||A||_F is at most 2 tol and the estimate within a
+factor 2 of it.  Inputs follow the uneven-batch recipe (planted spectra
+sigma_i = exp(-i / r0), log-uniform tolerances, block 32) at sizes the oracle runs in
+seconds.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.icur import exact_relative_error, iterative_cur   # noqa: E402
+from paper_2509_21963_amd import workloads as W               # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def icur():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_21963_amd import icur as m
+    m.load()
+    return m
+
+
+def _batch(count, seed, m_range=(150, 900), r0_range=(4.0, 40.0)):
+    specs = W.batch_specs(count, seed=seed, m_range=m_range, r0_range=r0_range)
+    mats = []
+    for i, sp in enumerate(specs):
+        A = W.planted(sp["m"], sp["n"], W.batch_sigma(sp["r0"], sp["K"]), seed=1000 * seed + i)
+        A32, _ = W.to_f32(A)
+        mats.append(A32)
+    return specs, mats
+
+
+def _same(a, b):
+    assert a["rank"] == b["rank"]
+    assert np.array_equal(a["I"], b["I"]) and np.array_equal(a["J"], b["J"])
+    assert np.array_equal(a["U"], b["U"])
+    assert a["rho"] == b["rho"]
+
+
+def test_batched_equals_single_calls(icur):
+    specs, mats = _batch(12, seed=1)
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    seeds = list(range(100, 112))
+    got = icur.run_batched(dev, tols, 32, icur.GAUSSIAN, seeds)
+    for i, A in enumerate(dev):
+        one = icur.run(A, tols[i], 32, icur.GAUSSIAN, seeds[i])
+        assert got[i]["status"] == one["status"]
+        _same(got[i], one)
+
+
+def _prefix(ora, margin):
+    pJ, pI = [], []
+    for h in ora["history"]:
+        for j, mg in zip(h["J_k"], h["col_margins"]):
+            if mg < margin:
+                return pJ, pI
+            pJ.append(j)
+        for i, mg in zip(h["I_k"], h["row_margins"]):
+            if mg < margin:
+                return pJ, pI
+            pI.append(i)
+    return pJ, pI
+
+
+def test_batched_meets_the_oracle(icur):
+    specs, mats = _batch(6, seed=2, m_range=(120, 500))
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    got = icur.run_batched(dev, tols, 32, icur.GAUSSIAN, list(range(6)))
+    for i, A32 in enumerate(mats):
+        A64 = A32.astype(np.float64)
+        ora = iterative_cur(A64, tols[i], 32, kind=0, seed=i, record=True)
+        g = got[i]
+        assert g["status"] == "ok"
+        pJ, pI = _prefix(ora, 1e-3)
+        assert g["J"][:len(pJ)].tolist() == pJ and g["I"][:len(pI)].tolist() == pI
+        err = exact_relative_error(A64, g["I"].tolist(), g["J"].tolist(), g["U"])
+        info = (i, specs[i], g["rank"], ora["rank"], g["rho"], ora["rho"], err)
+        assert err <= 2 * tols[i], info
+        assert g["rho"] <= tols[i], info
+        # the estimate tracks the exact error down to the plain form's rounding floor (the
+        # FP32 sums of the sketch, near 1e-6 of ||GA||); once a block reaches the exact
+        # rank of the planted spectrum the exact error drops far below that floor
+        if err > 1e-5:
+            assert 0.5 <= g["rho"] / err <= 2.0, info
+
+
+def test_batched_edge_cases(icur):
+    # one zero matrix (rank 0), one capped by max_rank (maxrank), one wide matrix whose
+    # column selection needs more candidates than a concurrent worker's share of the CUs
+    # (it runs alone after the others), and a single-matrix batch
+    rng = np.random.default_rng(5)
+    zero = torch.zeros((300, 200), dtype=torch.float32, device="cuda")
+    lowr = torch.from_numpy(W.to_f32(W.exact_lowrank(400, 300, 60, seed=3))[0]).cuda()
+    wide = torch.from_numpy(rng.standard_normal((8, 140000)).astype(np.float32)).cuda()
+    got = icur.run_batched([zero, lowr, wide], [1e-3, 1e-9, 1e-3], 4, icur.GAUSSIAN, [0, 1, 2],
+                           max_rank=8, check=False)
+    assert got[0]["status"] == "ok" and got[0]["rank"] == 0 and got[0]["rho"] == 0.0
+    assert got[1]["status"] == "maxrank" and got[1]["rank"] == 8
+    one = icur.run(wide, 1e-3, 4, icur.GAUSSIAN, 2, max_rank=8)
+    assert got[2]["status"] == one["status"]
+    _same(got[2], one)
+    single = icur.run_batched([lowr], [1e-2], 4, icur.GAUSSIAN, [7])
+    _same(single[0], icur.run(lowr, 1e-2, 4, icur.GAUSSIAN, 7))
+
+
+def test_batched_waits_for_the_callers_stream(icur):
+    # the matrices are written on the caller's stream just before the call
+    specs, mats = _batch(4, seed=3)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dev = [torch.empty(A.shape, dtype=torch.float32, device="cuda") for A in mats]
+        for d, A in zip(dev, mats):
+            d.copy_(torch.from_numpy(A).pin_memory(), non_blocking=True)
+        got = icur.run_batched(dev, [sp["tol"] for sp in specs], 32, icur.GAUSSIAN, [0, 1, 2, 3])
+    torch.cuda.synchronize()
+    for i, A in enumerate(dev):
+        _same(got[i], icur.run(A, specs[i]["tol"], 32, icur.GAUSSIAN, i))
