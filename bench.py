@@ -12,7 +12,14 @@ Prints one JSON line (the contract described in the repository's design doc):
                device events around its launches inside the timed calls
   cpu_baseline the FP64 NumPy oracle timed on the host cores, one run on the same
                matrix (copied from the device and widened to FP64)
+Other workloads (each prints its own line; the default is the one above):
+  --workload batched   the uneven batch: 512 planted FP32 matrices, m, n uniform in
+                       [500, 8000], sigma_i = exp(-i / r0) with r0 uniform in [10, 400],
+                       tol log-uniform in [1e-6, 1e-2], block 32, Gaussian sketch; value =
+                       time-to-tolerance of the whole batch through icur_run_batched, beside
+                       the same matrices through one icur_run call each (plain FP32 loop)
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--form fp32|bf16]
+                       [--workload rbf|batched] [--count N]
 """
 import argparse
 import hashlib
@@ -56,11 +63,7 @@ def cpu_baseline(A_dev, tol=1e-4, b=100):
     iterations and core) with the same tolerance, block and sketch family."""
     import numpy as np
     from oracle.icur import iterative_cur
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = oracle_threads()
     A64 = A_dev.cpu().numpy().astype(np.float64)
     m, n = A64.shape
     t0 = time.perf_counter()
@@ -73,6 +76,111 @@ def cpu_baseline(A_dev, tol=1e-4, b=100):
                        "rank %d, rho %.2e; no extrapolation" % (m, n, tol, b, out["rank"], out["rho"]))}
 
 
+def oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def bench_batched(a):
+    """The uneven batch through icur_run_batched, and through one icur_run per matrix."""
+    import numpy as np
+    import torch
+    from paper_2509_21963_amd import icur
+    from paper_2509_21963_amd import workloads as W
+
+    icur.load()
+    b = 32
+    specs = W.batch_specs(a.count, seed=0)
+    print("generating %d planted matrices on the device" % a.count, file=sys.stderr, flush=True)
+    As = []
+    for i, sp in enumerate(specs):
+        As.append(W.planted_device(sp["m"], sp["n"], W.batch_sigma(sp["r0"], sp["K"]), seed=i))
+        if (i + 1) % 64 == 0:
+            torch.cuda.synchronize()
+            print("  %d generated" % (i + 1), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tols = [sp["tol"] for sp in specs]
+    seeds = list(range(a.count))
+    elems = float(sum(sp["m"] * sp["n"] for sp in specs))
+    # warm-up: one batched call (sizes every worker's workspace) and single calls on the
+    # four largest matrices (sizes the single-call workspace)
+    for _ in range(a.warmup):
+        icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
+        print("batched warm-up done", file=sys.stderr, flush=True)
+    order = sorted(range(a.count), key=lambda i: -specs[i]["m"] * specs[i]["n"])
+    if a.warmup:
+        for i in order[:4]:
+            icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i])
+    torch.cuda.synchronize()
+    tb = []
+    for s in range(a.steps):
+        t0 = time.perf_counter()
+        got = icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        print("batched step %d: %.3f s" % (s, tb[-1]), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plain, sk_ms, sk_bytes = [], 0.0, 0.0
+    for i in range(a.count):
+        out = icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i])
+        plain.append(out)
+        sk_ms += out["info"]["ms_sketch_product"]
+        m, n = As[i].shape
+        c = (11 * b) // 10
+        sk_bytes += 4.0 * m * n + 2.0 * c * m + 8.0 * c * n
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print("plain loop: %.3f s" % t_plain, file=sys.stderr, flush=True)
+    same = all(g["rank"] == p["rank"] and np.array_equal(g["I"], p["I"]) and np.array_equal(g["J"], p["J"])
+               for g, p in zip(got, plain))
+    ranks = [g["rank"] for g in got]
+    value = statistics.median(tb)
+    achieved = sk_bytes / (sk_ms * 1e-3) / 1e9 if sk_ms > 0 else None
+    line = {
+        "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": value * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": "uneven batch: %d planted FP32 matrices, m,n ~ U{500..8000}, sigma_i = exp(-i/r0), "
+                        "r0 ~ U[10,400], tol ~ 10^U[-6,-2], block 32, Gaussian sketch, fp32 form" % a.count,
+            "count": a.count, "elements": elems, "block": b, "workers": a.workers or 8,
+            "plain_loop_s": t_plain, "speedup_vs_plain_loop": t_plain / value,
+            "identical_to_plain_loop": bool(same),
+            "rank_min": min(ranks), "rank_median": statistics.median(ranks), "rank_max": max(ranks),
+            "statuses": {k: sum(1 for g in got if g["status"] == k) for k in set(g["status"] for g in got)},
+        },
+        "roofline": {
+            "kernel": "sketch product G A over the batch (sketch_kernel, from the plain loop's device events)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "avg_ms": sk_ms / a.count, "algorithmic_bytes": sk_bytes / a.count,
+        },
+    }
+    if not a.no_cpu:
+        from oracle.icur import iterative_cur
+        print("timing the CPU oracle on a sample of the batch", file=sys.stderr, flush=True)
+        spent, done_elems, k = 0.0, 0.0, 0
+        for i in sorted(range(a.count), key=lambda q: specs[q]["m"] * specs[q]["n"]):
+            A64 = As[i].cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            iterative_cur(A64, tols[i], b, kind=0, seed=seeds[i])
+            spent += time.perf_counter() - t0
+            done_elems += A64.size
+            k += 1
+            if spent > 15.0:
+                break
+        line["cpu_baseline"] = {
+            "value": spent * elems / done_elems, "unit": "s", "cores": int(oracle_threads()), "kind": "oracle",
+            "sample": "FP64 NumPy oracle on the %d smallest matrices of the batch (%.1f s measured), scaled by "
+                      "total m n / sampled m n to the whole batch" % (k, spent)}
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,11 +189,20 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--form", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--size", type=int, default=40000)
+    ap.add_argument("--workload", choices=["rbf", "batched"], default="rbf")
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--workers", type=int, default=0)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path (requested %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batched":
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(1)
+        return bench_batched(a)
 
     import torch
     from paper_2509_21963_amd import icur

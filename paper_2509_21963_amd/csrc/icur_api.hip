@@ -266,7 +266,7 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
   if (o->split_terms < 0 || o->split_terms > 3) return arg_error("split_terms must be 0..3");
   if (o->residual_fp64 < -1 || o->residual_fp64 > 1) return arg_error("residual_fp64 must be -1, 0 or 1");
   if (o->max_rank < 0) return arg_error("max_rank must be >= 0");
-  if (o->reserved != 0) return arg_error("reserved must be 0");
+  if (o->batch_workers < 0 || o->batch_workers > 16) return arg_error("batch_workers must be 0..16");
   int st_risk = ICUR_OK;
   (void)risk_factor(o->alpha, o->delta, c, &st_risk);
   return st_risk;
@@ -721,11 +721,12 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   ICUR_TRY(device_info(&dev));
   const hipStream_t caller = as_stream(o.stream);
 
-  // ---- workers: kBatchWorkers concurrent runs, each on its own slot and stream.  The
+  // ---- workers: batch_workers concurrent runs, each on its own slot and stream.  The
   // selection grids of concurrent runs share the CUs, so each is capped at its share;
   // a matrix too large for the share runs afterwards, alone.
-  constexpr int kBatchWorkers = 4;
-  const int S = std::min<int32_t>(count, kBatchWorkers);
+  // 8 measured about 25% faster than 4 on the uneven batch, 16 no faster than 8
+  constexpr int kBatchWorkers = 8;
+  const int S = std::min<int32_t>(count, o.batch_workers > 0 ? o.batch_workers : kBatchWorkers);
   const int gcap = std::max(1, dev.num_cus / S);
   std::vector<int> small, large;
   for (int32_t i = 0; i < count; ++i)

@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
                 ("max_rank", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("delta", ctypes.c_double),
                 ("split_terms", ctypes.c_int32), ("sketch_fp32", ctypes.c_int32),
-                ("residual_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("residual_fp64", ctypes.c_int32), ("batch_workers", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -170,7 +170,7 @@ def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, se
 
 
 def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP32, zeta=0, max_rank=0,
-                alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, check=True):
+                alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, workers=0, check=True):
     """icur_run_batched on a list of m_i x n_i FP32 device tensors with per-matrix tolerances
     (and seeds, default 0..count-1).  Returns a list of dicts like run() (without info), each
     with its own "status"; raises on a failed matrix when check is True."""
@@ -201,7 +201,7 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
     rank = np.zeros(max(count, 1), np.int64)
     est = np.zeros(max(count, 1), np.float64)
     status = np.zeros(max(count, 1), np.int32)
-    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), 0)
+    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), int(workers))
     c_ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     st = lib.icur_run_batched(count, ptrs, c_ptr(m), c_ptr(n), c_ptr(lda), c_ptr(tol), int(block), int(sketch_kind),
                               c_ptr(sd), ctypes.byref(o), c_ptr(I), c_ptr(J), c_ptr(U), c_ptr(offs), c_ptr(rank),

@@ -147,6 +147,25 @@ def batch_sigma(r0, K):
     return np.exp(-np.arange(K) / r0)
 
 
+def planted_device(m, n, sigma, seed, device="cuda"):
+    """A = P diag(sigma) Q^T with P, Q orthonormal from the QR of Gaussians drawn by the
+    device's own generator (seeded), computed in FP64 on the device, returned as FP32.
+    For large batches, where drawing the Gaussians on the host would dominate."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) * 2 + 1)
+    s = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+    K = s.numel()
+    P, Rp = torch.linalg.qr(torch.randn((m, K), generator=gen, dtype=torch.float64, device=device))
+    P = P * torch.sign(torch.diagonal(Rp))[None, :]
+    del Rp
+    Q, Rq = torch.linalg.qr(torch.randn((n, K), generator=gen, dtype=torch.float64, device=device))
+    Q = Q * torch.sign(torch.diagonal(Rq))[None, :]
+    del Rq
+    A = ((P * s[None, :]) @ Q.T).to(torch.float32)
+    return A
+
+
 def _sparse_rows(rows, cols, per_row, g, scale=1.0):
     """rows x cols CSR (scipy, FP64) with `per_row` distinct random columns per row and
     N(0, scale^2) values."""

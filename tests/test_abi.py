@@ -79,7 +79,8 @@ def test_run_rejects_bad_options():
     icur, lib = _lib()
     for o in (icur.Opts(precision=5), icur.Opts(zeta=9), icur.Opts(split_terms=4),
               icur.Opts(max_rank=-1), icur.Opts(alpha=1e-10),     # c = 2 < -4 ln(alpha)
-              icur.Opts(residual_fp64=2), icur.Opts(zeta=-1), icur.Opts(reserved=1)):
+              icur.Opts(residual_fp64=2), icur.Opts(zeta=-1), icur.Opts(batch_workers=17),
+              icur.Opts(batch_workers=-1)):
         st, _ = _run_args(lib, opts=ctypes.byref(o))
         assert st == icur.ERR_ARG, (o.precision, o.zeta)
     # sparse-sign needs c <= 255
