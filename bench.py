@@ -18,8 +18,16 @@ Other workloads (each prints its own line; the default is the one above):
                        tol log-uniform in [1e-6, 1e-2], block 32, Gaussian sketch; value =
                        time-to-tolerance of the whole batch through icur_run_batched, beside
                        the same matrices through one icur_run call each (plain FP32 loop)
+  --workload precision the precision form: A = P diag((1+i)^-2) Q^T + E, 60000 x 40000
+                       FP32 (K = 4096 planted terms, ||E||_F = 1e-9 ||A||_F), block 128,
+                       Gaussian sketch, tol 1e-3 and 1e-5; value = BF16-split time-to-tol at
+                       1e-3, beside the plain FP32 form and both forms at 1e-5
+  --workload csr       the sparse form: A = P Q + E as CSR FP32, 200000 x 100000 (P with 5,
+                       Q with 100 Gaussian entries per row over 300 latent dimensions, E with
+                       20 entries of size 1e-8 per row), tol 1e-6, block 64, sparse-sign
+                       sketch; value = BF16-split time-to-tol, beside the plain FP32 form
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--form fp32|bf16]
-                       [--workload rbf|batched] [--count N]
+                       [--workload rbf|batched|precision|csr] [--count N]
 """
 import argparse
 import hashlib
@@ -181,6 +189,160 @@ def bench_batched(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_precision(a):
+    """The precision form against the plain FP32 form on the 60000 x 40000 planted matrix."""
+    import numpy as np
+    import torch
+    from paper_2509_21963_amd import icur
+    from paper_2509_21963_amd import workloads as W
+
+    icur.load()
+    m, n, b = 60000, 40000, 128
+    c = (11 * b) // 10
+    print("generating the %dx%d planted matrix on the device" % (m, n), file=sys.stderr, flush=True)
+    A = W.precision_form_device(m, n, seed=0)
+    torch.cuda.synchronize()
+    runs = {}
+    for tol in (1e-3, 1e-5):
+        for form, prec in (("bf16", icur.BF16_SPLIT), ("fp32", icur.FP32)):
+            for i in range(a.warmup):
+                icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
+            torch.cuda.synchronize()
+            times, outs = [], []
+            for i in range(a.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                outs.append(out)
+            last = outs[-1]
+            runs["%s@%g" % (form, tol)] = {
+                "s": statistics.median(times), "rank": last["rank"], "rho": last["rho"],
+                "iterations": last["info"]["iterations"], "split_terms": last["info"]["split_terms"],
+                "sketch_ms": statistics.mean(o["info"]["ms_sketch_product"] for o in outs)}
+            print("%s tol %g: %.2f ms, rank %d, rho %.3e, %d iterations" % (
+                form, tol, runs["%s@%g" % (form, tol)]["s"] * 1e3, last["rank"], last["rho"],
+                last["info"]["iterations"]), file=sys.stderr, flush=True)
+    head = runs["bf16@0.001"]
+    # the sketch kernel in the BF16-split form at tol 1e-3 (2 pieces of A): algorithmic
+    # bytes read A once, the BF16 G, and write X0 in FP64
+    alg_bytes = 4.0 * m * n + 2.0 * c * m + 8.0 * c * n
+    achieved = alg_bytes / (head["sketch_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": head["s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": head["s"] * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {
+            "workload": "precision form: A = P diag((1+i)^-2) Q^T + E, %dx%d FP32, K=4096, ||E||_F = 1e-9 ||A||_F, "
+                        "block %d, Gaussian sketch; value = BF16-split at tol 1e-3" % (m, n, b),
+            "m": m, "n": n, "block": b, "sketch_rows": c, "runs": runs,
+            "speedup_bf16_vs_fp32": {t: runs["fp32@%s" % t]["s"] / runs["bf16@%s" % t]["s"] for t in ("0.001", "1e-05")},
+        },
+        "roofline": {
+            "kernel": "sketch product G A, BF16-split form at tol 1e-3 (sketch_kernel, %d BF16 pieces of A)"
+                      % head["split_terms"],
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_ms": head["sketch_ms"],
+            "algorithmic_bytes": alg_bytes,
+        },
+    }
+    if not a.no_cpu:
+        from oracle.icur import iterative_cur
+        print("timing the CPU oracle on the same matrix at tol 1e-3", file=sys.stderr, flush=True)
+        A64 = A.cpu().numpy().astype(np.float64)
+        del A
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        ora = iterative_cur(A64, 1e-3, b, kind=0, seed=0)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {
+            "value": dt, "unit": "s", "cores": int(oracle_threads()), "kind": "oracle",
+            "sample": "one FP64 NumPy oracle run on the full %dx%d matrix at tol 1e-3 (copied from the device, "
+                      "widened to FP64): rank %d, rho %.2e" % (m, n, ora["rank"], ora["rho"])}
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def bench_csr(a):
+    """The sparse form through icur_run_csr, BF16-split and plain FP32."""
+    import numpy as np
+    import torch
+    from paper_2509_21963_amd import icur
+    from paper_2509_21963_amd import workloads as W
+
+    icur.load()
+    m, n, b, tol = 200000, 100000, 64, 1e-6
+    c = (11 * b) // 10
+    print("generating the %dx%d sparse matrix on the host" % (m, n), file=sys.stderr, flush=True)
+    rowptr, colind, vals = W.csr_to_f32(W.sparse_lowrank(m, n, seed=0))
+    nnz = int(colind.size)
+    d = [torch.from_numpy(x).cuda() for x in (rowptr, colind, vals)]
+    torch.cuda.synchronize()
+    runs = {}
+    for form, prec in (("bf16", icur.BF16_SPLIT), ("fp32", icur.FP32)):
+        for i in range(a.warmup):
+            icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=i, precision=prec)
+        torch.cuda.synchronize()
+        times, outs = [], []
+        for i in range(a.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=i, precision=prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            outs.append(out)
+        last = outs[-1]
+        runs[form] = {"s": statistics.median(times), "rank": last["rank"], "rho": last["rho"],
+                      "iterations": last["info"]["iterations"],
+                      "sketch_ms": statistics.mean(o["info"]["ms_sketch_product"] for o in outs)}
+        print("%s: %.2f ms, rank %d, rho %.3e, %d iterations" % (form, runs[form]["s"] * 1e3, last["rank"],
+                                                                 last["rho"], last["info"]["iterations"]),
+              file=sys.stderr, flush=True)
+    head = runs["bf16"]
+    # the CSR sketch reads every stored entry once from the column-compressed copy
+    # (4-byte value + 4-byte row index) and writes X0 in FP64
+    alg_bytes = 8.0 * nnz + 8.0 * c * n
+    achieved = alg_bytes / (head["sketch_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": head["s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": head["s"] * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {
+            "workload": "sparse form: A = P Q + E, CSR FP32 %dx%d (nnz %d), 300 latent dims, tol %g, block %d, "
+                        "sparse-sign sketch zeta=8; value = BF16-split" % (m, n, nnz, tol, b),
+            "m": m, "n": n, "nnz": nnz, "block": b, "sketch_rows": c, "runs": runs,
+            "speedup_bf16_vs_fp32": runs["fp32"]["s"] / head["s"],
+        },
+        "roofline": {
+            "kernel": "CSR sketch X0 = G A (column-compressed copy, FP64 accumulation)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_ms": head["sketch_ms"],
+            "algorithmic_bytes": alg_bytes,
+        },
+    }
+    if not a.no_cpu:
+        # the dense oracle cannot hold the full matrix: time it on a smaller instance of
+        # the same recipe and scale by the stored entries
+        from oracle.icur import iterative_cur
+        ms_, ns_ = 20000, 10000
+        print("timing the CPU oracle on a %dx%d instance of the recipe" % (ms_, ns_), file=sys.stderr, flush=True)
+        rp, ci, vv = W.csr_to_f32(W.sparse_lowrank(ms_, ns_, seed=0))
+        A64 = W.csr_dense64(rp, ci, vv, (ms_, ns_))
+        t0 = time.perf_counter()
+        ora = iterative_cur(A64, tol, b, kind=1, seed=0)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {
+            "value": dt * nnz / float(ci.size), "unit": "s", "cores": int(oracle_threads()), "kind": "oracle",
+            "sample": "dense FP64 NumPy oracle on a %dx%d instance of the same recipe (nnz %d): %.2f s, rank %d, "
+                      "rho %.2e; scaled by the ratio of stored entries to the full matrix" % (
+                          ms_, ns_, ci.size, dt, ora["rank"], ora["rho"])}
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,7 +351,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--form", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--size", type=int, default=40000)
-    ap.add_argument("--workload", choices=["rbf", "batched"], default="rbf")
+    ap.add_argument("--workload", choices=["rbf", "batched", "precision", "csr"], default="rbf")
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--workers", type=int, default=0)
     a = ap.parse_args()
@@ -197,12 +359,12 @@ def main():
         print("bench.py measures one GPU; this build has no multi-GPU path (requested %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if a.workload == "batched":
+    if a.workload != "rbf":
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
             sys.exit(1)
-        return bench_batched(a)
+        return {"batched": bench_batched, "precision": bench_precision, "csr": bench_csr}[a.workload](a)
 
     import torch
     from paper_2509_21963_amd import icur

@@ -114,6 +114,21 @@ __global__ void sign_masks_kernel(const uint8_t* __restrict__ rows, const uint8_
   }
 }
 
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int t) {
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(v), t);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(v >> 32), t);
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int t) {
+  return __longlong_as_double(static_cast<long long>(readlane_u64(static_cast<unsigned long long>(__double_as_longlong(v)), t)));
+}
+
+// One wave per column j of A; lane l accumulates sketch row 64 w + l.  The column's
+// entries are taken 64 at a time: each lane loads one entry (row index, value and, for
+// the sparse-sign kind, the masks of that row of A) so that the 64 loads are in flight
+// together, then the wave walks the 64 entries in order, each broadcast from its lane.
+// Every row's sum runs over the entries in column order, one FP64 fma per entry.
 template <int W, bool SIGN>
 __global__ __launch_bounds__(64 * kSkWaves) void csc_sketch_kernel(
     const int64_t* __restrict__ colptr, const int32_t* __restrict__ csc_row, const float* __restrict__ csc_val,
@@ -127,23 +142,52 @@ __global__ __launch_bounds__(64 * kSkWaves) void csc_sketch_kernel(
   for (int w = 0; w < W; ++w) acc[w] = 0.0;
   if (j < n) {
     const int64_t b = colptr[j], e = colptr[j + 1];
-    for (int64_t p = b; p < e; ++p) {
-      const int64_t i = csc_row[p];
-      const double a = static_cast<double>(csc_val[p]);
+    for (int64_t p0 = b; p0 < e; p0 += 64) {
+      const int64_t p = p0 + lane;
+      const bool valid = p < e;
+      const int64_t i = valid ? csc_row[p] : 0;
+      const double a = valid ? static_cast<double>(csc_val[p]) : 0.0;
+      const int cnt = static_cast<int>(e - p0 < 64 ? e - p0 : 64);
       if constexpr (SIGN) {
+        unsigned long long mk[W], sg[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          const unsigned long long mk = masks[(i * W + w) * 2];
-          const unsigned long long sg = masks[(i * W + w) * 2 + 1];
-          const double coef = ((mk >> lane) & 1ull) ? (((sg >> lane) & 1ull) ? -1.0 : 1.0) : 0.0;
-          acc[w] = fma(coef, a, acc[w]);
+          mk[w] = valid ? masks[(i * W + w) * 2] : 0ull;
+          sg[w] = valid ? masks[(i * W + w) * 2 + 1] : 0ull;
+        }
+        for (int t = 0; t < cnt; ++t) {
+          const double at = readlane_f64(a, t);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            const unsigned long long mt = readlane_u64(mk[w], t);
+            const unsigned long long st = readlane_u64(sg[w], t);
+            const double coef = ((mt >> lane) & 1ull) ? (((st >> lane) & 1ull) ? -1.0 : 1.0) : 0.0;
+            acc[w] = fma(coef, at, acc[w]);
+          }
         }
       } else {
+        // 8 entries per round: their G rows are loaded before any of them is used
+        for (int t0 = 0; t0 < cnt; t0 += 8) {
+          double g[8][W], av[8];
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const int r = 64 * w + lane;
-          const double g = r < c ? static_cast<double>(__uint_as_float(static_cast<unsigned>(Gt[i * ldgt + r]) << 16)) : 0.0;
-          acc[w] = fma(g, a, acc[w]);
+          for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u < cnt ? t0 + u : t0;  // beyond the count: a repeat, weighted 0
+            const int64_t it = static_cast<int64_t>(__builtin_amdgcn_readlane(static_cast<int>(i), t));
+            av[u] = t0 + u < cnt ? readlane_f64(a, t) : 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              const int r = 64 * w + lane;
+              g[u][w] = r < c ? static_cast<double>(__uint_as_float(static_cast<unsigned>(Gt[it * ldgt + r]) << 16))
+                              : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (t0 + u < cnt) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) acc[w] = fma(g[u][w], av[u], acc[w]);
+            }
+          }
         }
       }
     }

@@ -126,6 +126,26 @@ def precision_form_sigma(K=4096):
     return (1.0 + np.arange(K)) ** -2.0
 
 
+def precision_form_device(m=60000, n=40000, K=4096, seed=0, noise_rel=1e-9, device="cuda"):
+    """The precision-form test matrix A = P diag((1+i)^-2) Q^T + E on the device, FP32:
+    P (m x K), Q (n x K) orthonormal from device-drawn Gaussians (K = 4096 terms; the tail
+    beyond them is about 2e-6 relative), E Gaussian scaled so that ||E||_F = noise_rel
+    ||P diag Q^T||_F (a literal 1e-9 N(0,1) per entry would exceed a 1e-5 tolerance at
+    this size)."""
+    import torch
+    A = planted_device(m, n, precision_form_sigma(K), seed, device=device)
+    if noise_rel:
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed) * 2 + 7919)
+        scale = noise_rel * float(np.sqrt(np.sum(precision_form_sigma(K) ** 2))) / np.sqrt(float(m) * n)
+        for r0 in range(0, m, 4096):
+            r1 = min(m, r0 + 4096)
+            E = torch.randn((r1 - r0, n), generator=gen, dtype=torch.float64, device=device)
+            A[r0:r1] = (A[r0:r1].double() + scale * E).float()
+            del E
+    return A
+
+
 def batch_specs(count=512, seed=0, m_range=(500, 8000), r0_range=(10.0, 400.0),
                 logtol_range=(-6.0, -2.0)):
     """Per-matrix (m, n, r0, tol, K) for the uneven batch: m, n uniform integers,

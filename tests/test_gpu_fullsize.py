@@ -76,3 +76,69 @@ def test_rbf_40000_matches_oracle(icur):
     assert 0.8 <= got["rho"] / ora["rho"] <= 1.25
     err = _relative_error_blocked(A64, I, J, got["U"])
     assert err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
+
+
+def test_precision_form_60000x40000_matches_oracle(icur):
+    # the precision form's matrix at full size, BF16-split at tol 1e-3 (two BF16 pieces)
+    m, n, b, tol = 60000, 40000, 128, 1e-3
+    A = W.precision_form_device(m, n, seed=0)
+    torch.cuda.synchronize()
+    got = icur.run(A, tol, b, icur.GAUSSIAN, seed=0, precision=icur.BF16_SPLIT)
+    A64 = A.cpu().numpy().astype(np.float64)
+    del A
+    torch.cuda.empty_cache()
+    ora = iterative_cur(A64, tol, b, kind=0, seed=0, record=True)
+    I, J = got["I"].tolist(), got["J"].tolist()
+    assert got["status"] == "ok" and got["info"]["split_terms"] == 2
+    assert got["rank"] == ora["rank"]
+    assert got["info"]["iterations"] == len(ora["history"])
+    # BF16 pieces agree with the FP64 oracle on pivots whose margin exceeds 1e-2
+    pJ, pI = _prefix(ora, 1e-2)
+    assert J[:len(pJ)] == pJ and I[:len(pI)] == pI
+    X0 = ora["X0"]
+    assert abs(X0[0, J[0]]) >= (1 - 1e-2) * np.abs(X0[0]).max()
+    assert 0.5 <= got["rho"] / ora["rho"] <= 2.0
+    err = _relative_error_blocked(A64, I, J, got["U"])
+    assert err <= 2 * tol and 0.5 <= got["rho"] / err <= 2.0
+
+
+def test_csr_200000x100000_full_size(icur):
+    # the sparse low-rank-plus-noise CSR matrix at full size (about 1.04e8 entries), BF16-split
+    # form, tol 1e-6, block 64.  The dense oracle cannot hold it, so its results are checked
+    # at this size through what the oracle computes one piece at a time: the first column
+    # selection (LUPP on the oracle's own sketch X0 = G A, formed with a sparse product),
+    # the core against the exact cross A(I,J), and the exact error on sampled rows.
+    import scipy.sparse as sp
+    from oracle.lupp import lupp_pivots
+    from oracle.rng import make_G
+    m, n, b, tol = 200000, 100000, 64, 1e-6
+    A = W.sparse_lowrank(m, n, seed=0)
+    rowptr, colind, vals = W.csr_to_f32(A)
+    A = sp.csr_matrix((vals.astype(np.float64), colind, rowptr), shape=(m, n))  # the values the GPU reads
+    d = [torch.from_numpy(x).cuda() for x in (rowptr, colind, vals)]
+    got = icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=0, precision=icur.BF16_SPLIT)
+    del d
+    torch.cuda.empty_cache()
+    r = got["rank"]
+    I, J, U = got["I"].tolist(), got["J"].tolist(), got["U"]
+    assert got["status"] == "ok" and got["rho"] <= tol
+    assert 300 <= r <= 384 and len(set(I)) == r and len(set(J)) == r   # true rank 300
+    # first column block: LUPP on the oracle's sketch
+    c = (11 * b) // 10
+    G = make_G(0, c, m, 1, zeta=8)
+    X0 = np.asarray((A.T @ G.T).T)
+    J1, margins = lupp_pivots(X0.T, b, return_margins=True)
+    k = 0
+    while k < len(J1) and margins[k] >= 1e-2:
+        k += 1
+    assert k >= 8 and J[:k] == list(J1[:k])
+    # the core is the inverse of the cross
+    C = A[I][:, J].toarray()
+    resid = np.abs(C @ U - np.eye(r)).max()
+    assert resid <= 1e-6 * max(1.0, np.linalg.cond(C) * 1e-12), resid
+    # exact error on 1000 sampled rows
+    S = np.random.default_rng(0).choice(m, 1000, replace=False)
+    R = A[I].toarray()
+    AS = A[S].toarray()
+    E = AS - (A[S][:, J].toarray() @ U) @ R
+    assert np.linalg.norm(E) <= 2 * tol * np.linalg.norm(AS)
