@@ -11,6 +11,8 @@
 // partial pivoting in one workgroup.
 #include <algorithm>
 
+#include <utility>
+
 #include "icur_internal.h"
 #include "icur_wave.h"
 
@@ -233,110 +235,144 @@ __global__ __launch_bounds__(1024) void gj_inverse_kernel(double* __restrict__ N
   if (tid == 0) *info = 0;
 }
 
-// Register variant for k <= 128 (no norms): thread (g, c), t = g k + c, owns column c
-// of the contiguous rows g R .. g R + R - 1 in registers (R = 4 for k <= 64, else 16;
-// every row has an owner because ceil(k / R) k <= 1024).  Pivoting is implicit (no row
-// swaps): step j picks the unused row p with the largest |a(p, j)|, lowest index on ties,
-// and eliminates column j from every other row; storage row p_j then holds row j of the
-// inverse with columns permuted, which the final write undoes (inverse(j, p_c) =
-// storage(p_j, c)).  Per step the owners of column j publish it with their best row, one
-// DPP argmax per wave reduces those candidates, the owners of row p publish it, and every
-// element takes one FMA (column j and row p are fixed up by their owners): two barriers.
-template <int R>
-__global__ __launch_bounds__(1024) void gj_inverse_reg_kernel(double* __restrict__ Ng, int k,
-                                                              int* __restrict__ info) {
-  __shared__ __attribute__((aligned(16))) double colj[2][256];
+template <class F, int... I>
+__device__ __forceinline__ void tile_static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void tile_static_for(F&& f) {
+  tile_static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Gauss-Jordan inverse of a k x k block, k <= 128, in one workgroup of four waves (one
+// per SIMD, so no wave repeats another's work on a shared SIMD).  Thread (tr, tc) of a
+// 16 x 16 grid holds the 8 x 8 tile at rows 8 tr, columns 8 tc in registers.  Pivoting
+// is implicit (no row swaps): step j takes the unused row p with the largest |a(p, j)|,
+// lowest index on ties, and eliminates column j from every other row; the final write
+// undoes the permutation (inverse(j, p_c) = storage(p_j, c)).  Per step the tile column
+// holding column j publishes that column and its per-tile best rows, every wave reduces
+// the 16 candidates, the tile row holding row p publishes that row, and every thread
+// updates its tile: two barriers per step.
+__global__ __launch_bounds__(256) void gj_inverse_tile_kernel(double* __restrict__ Ng, int k, int* __restrict__ info) {
+  __shared__ double colj[2][128];
   __shared__ double prow[2][128];
-  __shared__ Red red[2][64];
-  __shared__ int perm[128];   // perm[j] = p_j
-  __shared__ int pinv[128];   // pinv[p_j] = j
+  __shared__ Red red[2][16];
+  __shared__ int perm[128];  // perm[j] = p_j
+  __shared__ int pinv[128];  // pinv[p_j] = j
   const int tid = threadIdx.x, lane = tid & 63;
-  const int G = (k + R - 1) / R;  // row groups
-  const int g = tid / k, c = tid % k;
-  const bool own = g < G;
-  const int r0 = g * R;
-  double a[R];
+  const int tr = tid >> 4, tc = tid & 15;
+  const int r0 = 8 * tr, c0 = 8 * tc;
+  double a[8][8];
 #pragma unroll
-  for (int q = 0; q < R; ++q) {  // branch free: clamped address, then a select
-    const double v = Ng[min(r0 + q, k - 1) * k + c];
-    a[q] = (own && r0 + q < k) ? v : 0.0;
-  }
-  static_assert(R <= 64, "used-row mask is 64 bits");
-  unsigned long long used = 0;  // bit q: row r0 + q was a pivot
-  for (int j = 0; j < k; ++j) {
-    const int b = j & 1;
-    // (1) the owners of column j publish it and their best unused row
-    if (own && c == j) {
-      unsigned long long bk = 0ull;
-      int bi = INT_MAX;
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        colj[b][r0 + q] = a[q];
-        const unsigned long long kk =
-            (((used >> q) & 1ull) || r0 + q >= k) ? 0ull : cand_key(fabs(a[q]));
-        if (kk > bk) {  // rows increase with q: ties keep the lower row
-          bk = kk;
-          bi = r0 + q;
+    for (int jj = 0; jj < 8; ++jj) {
+      const int r = r0 + i, c = c0 + jj;
+      a[i][jj] = (r < k && c < k) ? Ng[r * k + c] : 0.0;
+    }
+  unsigned used = 0;  // bit i: row r0 + i was a pivot
+  // Steps go eight at a time so that the column inside a tile is a compile-time index;
+  // the pivot row inside its tile is wave-uniform, so it is chosen by uniform branches.
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    const int tj = j0 >> 3;
+    bool fail = false;
+    tile_static_for<8>([&](auto jcc) __attribute__((always_inline)) {
+      constexpr int jc = decltype(jcc)::value;
+      const int j = j0 + jc;
+      if (fail || j >= k) return;
+      const int b = j & 1;
+      // (1) tile column tj publishes column j and its best unused row
+      if (tc == tj) {
+        unsigned long long bk = 0ull;
+        int bi = INT_MAX;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const double v = a[i][jc];
+          colj[b][r0 + i] = v;
+          const unsigned long long kk = (((used >> i) & 1u) || r0 + i >= k) ? 0ull : cand_key(fabs(v));
+          if (kk > bk) {  // rows increase with i: ties keep the lower row
+            bk = kk;
+            bi = r0 + i;
+          }
+        }
+        red[b][tr] = Red{bk, bi, 0};
+      }
+      __syncthreads();
+      // (2) every wave reduces the 16 candidates (lane l < 16 reads slot l)
+      unsigned long long sk = 0ull;
+      int si = INT_MAX;
+      if (lane < 16) {
+        const Red rr = red[b][lane];
+        sk = rr.k;
+        si = rr.i;
+      }
+      unsigned long long gk;
+      int p, gw;
+      wave_argmax(sk, si, 0, &gk, &p, &gw);
+      if (gk == 0ull) {  // uniform: every wave reduced the same slots
+        fail = true;
+        return;
+      }
+      const int tp = p >> 3, ip = p & 7;
+      if (tr == tp) {
+        switch (ip) {
+#define ICUR_GJ_PUB(I)                                                    \
+  case I:                                                                 \
+    for (int jj = 0; jj < 8; ++jj) prow[b][c0 + jj] = a[I][jj];           \
+    break;
+          ICUR_GJ_PUB(0) ICUR_GJ_PUB(1) ICUR_GJ_PUB(2) ICUR_GJ_PUB(3)
+          ICUR_GJ_PUB(4) ICUR_GJ_PUB(5) ICUR_GJ_PUB(6) ICUR_GJ_PUB(7)
+#undef ICUR_GJ_PUB
+        }
+        used |= 1u << ip;
+      }
+      if (tid == 0) {
+        perm[j] = p;
+        pinv[p] = j;
+      }
+      __syncthreads();
+      // (3) a(i, c) -= a(i, j) a(p, c) / piv for all rows; then column j becomes
+      //     -a(i, j) / piv and row p becomes a(p, c) / piv (1 / piv at column j)
+      const double rinv = 1.0 / colj[b][p];
+      double pr[8], f[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) pr[jj] = prow[b][c0 + jj] * rinv;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) f[i] = colj[b][r0 + i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) a[i][jj] = a[i][jj] - f[i] * pr[jj];
+      if (tc == tj) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i][jc] = -f[i] * rinv;
+      }
+      if (tr == tp) {
+        switch (ip) {
+#define ICUR_GJ_ROW(I)                                                    \
+  case I:                                                                 \
+    for (int jj = 0; jj < 8; ++jj) a[I][jj] = pr[jj];                     \
+    if (tc == tj) a[I][jc] = rinv;                                        \
+    break;
+          ICUR_GJ_ROW(0) ICUR_GJ_ROW(1) ICUR_GJ_ROW(2) ICUR_GJ_ROW(3)
+          ICUR_GJ_ROW(4) ICUR_GJ_ROW(5) ICUR_GJ_ROW(6) ICUR_GJ_ROW(7)
+#undef ICUR_GJ_ROW
         }
       }
-      red[b][g] = Red{bk, bi, 0};
-    }
-    __syncthreads();
-    // (2) every wave reduces the G candidates (lane l reads slot l); the owners of row p
-    //     publish it
-    unsigned long long sk = 0ull;
-    int si = INT_MAX;
-    if (lane < G) {
-      const Red rr = red[b][lane];
-      sk = rr.k;
-      si = rr.i;
-    }
-    unsigned long long gk;
-    int p, gw;
-    wave_argmax(sk, si, 0, &gk, &p, &gw);
-    if (gk == 0ull) {
+    });
+    if (fail) {
       if (tid == 0) *info = 1;
-      return;  // uniform: every wave reduced the same slots
-    }
-    const double piv = colj[b][p];
-    const int gp = p / R, qp = p - gp * R;
-    if (own && g == gp) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < R; ++q) v = (q == qp) ? a[q] : v;
-      prow[b][c] = v;
-      used |= 1ull << qp;
-    }
-    if (tid == 0) {
-      perm[j] = p;
-      pinv[p] = j;
-    }
-    __syncthreads();
-    // (3) a(i, c) -= a(i, j) a(p, c) / piv for all rows; then column j becomes
-    //     -a(i, j) / piv and row p becomes a(p, c) / piv (1 / piv at column j)
-    const double rinv = 1.0 / piv;
-    const double pr = prow[b][c] * rinv;
-    double f[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) f[q] = colj[b][r0 + q];
-#pragma unroll
-    for (int q = 0; q < R; ++q) a[q] = a[q] - f[q] * pr;
-    if (c == j) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) a[q] = -f[q] * rinv;
-    }
-    if (g == gp) {
-      const double prr = (c == j) ? rinv : pr;
-#pragma unroll
-      for (int q = 0; q < R; ++q) a[q] = (q == qp) ? prr : a[q];
+      return;
     }
   }
   __syncthreads();
-  if (own) {
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (r0 + q < k) Ng[pinv[r0 + q] * k + perm[c]] = a[q];
-  }
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int r = r0 + i, c = c0 + jj;
+      if (r < k && c < k) Ng[pinv[r] * k + perm[c]] = a[i][jj];
+    }
   if (tid == 0) *info = 0;
 }
 
@@ -379,10 +415,7 @@ int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* 
                          hipStream_t st) {
   if (k < 1 || k > 512) return arg_error("inverse: block size must be in 1..512");
   if (k <= 128 && norms == nullptr) {
-    if (k <= 64)
-      hipLaunchKernelGGL((gj_inverse_reg_kernel<4>), dim3(1), dim3(1024), 0, st, N, static_cast<int>(k), info);
-    else
-      hipLaunchKernelGGL((gj_inverse_reg_kernel<16>), dim3(1), dim3(1024), 0, st, N, static_cast<int>(k), info);
+    hipLaunchKernelGGL(gj_inverse_tile_kernel, dim3(1), dim3(256), 0, st, N, static_cast<int>(k), info);
     ICUR_HIP(hipGetLastError());
     return ICUR_OK;
   }

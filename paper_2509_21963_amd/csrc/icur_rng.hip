@@ -66,7 +66,8 @@ __global__ void gaussian_G_kernel(uint64_t seed, int64_t c, int64_t m, uint16_t*
 }
 
 // One thread per column i of G (row i of A).  Writes the pattern and, when G_dense is
-// given, the whole dense column (zeros included) as BF16 bit patterns.
+// given, the column's nonzeros as BF16 bit patterns (its zeros are written first by a
+// separate fill).
 __global__ void sparse_sign_kernel(uint64_t seed, int c, int64_t m, int z,
                                    uint8_t* __restrict__ rows, uint8_t* __restrict__ signs,
                                    uint16_t* __restrict__ G, int64_t ldg) {
@@ -90,14 +91,16 @@ __global__ void sparse_sign_kernel(uint64_t seed, int c, int64_t m, int z,
     for (int t = 0; t < z; ++t) rows[i * z + t] = static_cast<uint8_t>(chosen[t]);
   }
   if (signs) signs[i] = static_cast<uint8_t>(sbits);
-  if (G) {
-    for (int r = 0; r < c; ++r) {
-      uint16_t v = 0;
-      for (int t = 0; t < z; ++t)
-        if (chosen[t] == r) v = ((sbits >> t) & 1u) ? 0xBF80u : 0x3F80u;  // -1 / +1
-      G[static_cast<int64_t>(r) * ldg + i] = v;
-    }
+  if (G) {  // the column's zeros were written by zero_columns_kernel
+    for (int t = 0; t < z; ++t)
+      G[static_cast<int64_t>(chosen[t]) * ldg + i] = ((sbits >> t) & 1u) ? 0xBF80u : 0x3F80u;  // -1 / +1
   }
+}
+
+// Zeros in columns 0 .. m-1 of every row of a c x ldg BF16 matrix.
+__global__ void zero_columns_kernel(uint16_t* __restrict__ G, int64_t m, int64_t ldg) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < m) G[static_cast<int64_t>(blockIdx.y) * ldg + i] = 0;
 }
 
 }  // namespace
@@ -129,6 +132,11 @@ int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* r
   if (c > 255) return arg_error("sparse-sign sketch needs c <= 255");
   const int z = zeta < c ? zeta : static_cast<int>(c);
   if (z < 1 || z > 8) return arg_error("sparse-sign zeta must be in 1..8");
+  if (G_dense) {
+    hipLaunchKernelGGL(zero_columns_kernel, dim3(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(c)),
+                       dim3(256), 0, st, G_dense, m, ldg);
+    ICUR_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(sparse_sign_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256),
                      0, st, seed, static_cast<int>(c), m, z, rows, signs, G_dense, ldg);
   ICUR_HIP(hipGetLastError());
