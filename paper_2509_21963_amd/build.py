@@ -3,7 +3,7 @@
     python -m paper_2509_21963_amd.build [--jobs N]
 
 Every .hip file under csrc/ is compiled to an object with hipcc and the objects are
-linked into one shared library.  Packed-FP32 instructions are disabled for all device
+linked into one shared library (with rocBLAS, used for the plain FP64 GEMMs of the core).  Packed-FP32 instructions are disabled for all device
 code; the selection kernels are compiled without floating-point contraction so that
 their rounding matches a plain FP64 elimination step by step.
 """
@@ -51,7 +51,7 @@ def build(jobs=None, verbose=False):
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-o", tmp] + objs + ["--offload-arch=" + ARCH, "-fPIC"]
+    cmd = [hipcc(), "-shared", "-o", tmp] + objs + ["--offload-arch=" + ARCH, "-fPIC", "-lrocblas"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (res.stdout, res.stderr))

@@ -13,6 +13,10 @@
 
 #include <utility>
 
+#include <map>
+
+#include <rocblas/rocblas.h>
+
 #include "icur_internal.h"
 #include "icur_wave.h"
 
@@ -378,10 +382,50 @@ __global__ __launch_bounds__(256) void gj_inverse_tile_kernel(double* __restrict
 
 }  // namespace
 
+namespace {
+// rocBLAS handles, one per host thread and device (a handle must not be shared by
+// threads that issue at the same time); atomics off so that every product is
+// reproducible run to run.
+thread_local std::map<int, rocblas_handle> t_blas;
+
+int blas_handle(rocblas_handle* out) {
+  int dev = 0;
+  ICUR_HIP(hipGetDevice(&dev));
+  auto it = t_blas.find(dev);
+  if (it == t_blas.end()) {
+    rocblas_handle h;
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+      set_error("rocblas_create_handle failed");
+      return ICUR_ERR_HIP;
+    }
+    rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
+    it = t_blas.emplace(dev, h).first;
+  }
+  *out = it->second;
+  return ICUR_OK;
+}
+}  // namespace
+
 int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sa0,
           int64_t sa1, const double* B, int64_t sb0, int64_t sb1, double beta, double* C,
           int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return ICUR_OK;
+  // Row-major operands with unit column strides are a plain library GEMM: the
+  // column-major product C^T = alpha B^T A^T + beta C^T on FP64 matrix cores.
+  if (sa1 == 1 && sb1 == 1 && K > 0 && M <= INT32_MAX && N <= INT32_MAX && K <= INT32_MAX && sa0 <= INT32_MAX &&
+      sb0 <= INT32_MAX && ldc <= INT32_MAX) {
+    rocblas_handle h;
+    ICUR_TRY(blas_handle(&h));
+    if (rocblas_set_stream(h, st) != rocblas_status_success ||
+        rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, static_cast<rocblas_int>(N),
+                      static_cast<rocblas_int>(M), static_cast<rocblas_int>(K), &alpha, B,
+                      static_cast<rocblas_int>(sb0), A, static_cast<rocblas_int>(sa0), &beta, C,
+                      static_cast<rocblas_int>(ldc)) != rocblas_status_success) {
+      set_error("rocblas_dgemm failed");
+      return ICUR_ERR_HIP;
+    }
+    return ICUR_OK;
+  }
   if ((N + kTN - 1) / kTN > 0x7fffffff || (M + kTM - 1) / kTM > 65535)
     return arg_error("dgemm: matrix too large");
   dim3 grid(static_cast<unsigned>((N + kTN - 1) / kTN), static_cast<unsigned>((M + kTM - 1) / kTM));
