@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "icur_internal.h"
+#include "icur_wide_kernel.h"
 
 namespace icur {
 
@@ -205,6 +206,10 @@ constexpr double kSketchChunkFlushBelow = 1e-4;
 // exact rank of A), and inverting that noise in N_k would wreck the residual recurrence.
 // What is dropped is at most this fraction of the block's largest residual entry.
 constexpr double kRowCutFp64 = 0x1.0p-40;
+// FP64 residual products at least this deep and this tall go to the library GEMM
+// (measured: faster for blocks of 128 rows at depth >= 256, slower for blocks of 32).
+constexpr int64_t kLibraryGemmMinK = 256;
+constexpr int64_t kLibraryGemmMinM = 96;
 constexpr double kRowCutFp32 = 0x1.0p-16;
 
 // BF16 pieces per FP32 operand for a tolerance.  One piece rounds with relative error
@@ -397,6 +402,22 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
                      int* parts) -> int {
     // res64: W and B are FP64 and OUT is FP64 (FP64 matrix cores); else W is split into
     // BF16 pieces (or rounded to FP32) and B is FP32.
+    if (res64 && K >= kLibraryGemmMinK && M >= kLibraryGemmMinM &&
+        ((X == OUT && subtract) || (X == nullptr && !subtract))) {
+      // deep products in place (OUT -= W B) or plain: a library FP64 GEMM, then the
+      // norm partials of OUT in a pass of their own when asked for; shallow ones stay
+      // on the short-M kernel, which fuses the norm and has less launch overhead
+      ICUR_TRY(dgemm(M, N, K, subtract ? -1.0 : 1.0, W64, K, 1, static_cast<const double*>(B), ldb, 1,
+                     subtract ? 1.0 : 0.0, static_cast<double*>(OUT), ldo, st));
+      if (norm) {
+        const int blocks = static_cast<int>(std::min<int64_t>((M * N + 255) / 256, 1024));
+        ICUR_TRY(wide::launch_reduce_f64(nullptr, 0, M, N, OUT, ldo, 1, OUT, ldo, dnorm, blocks, st));
+        *parts = blocks;
+      } else {
+        *parts = 0;
+      }
+      return ICUR_OK;
+    }
     if (K > 0 && !res64) ICUR_TRY(launch_split_f64(W64, M, K, K, false, T, pWp, K, M * K, st));
     WideGemm g{};
     g.X = X;
