@@ -140,13 +140,19 @@ struct Scal {
   int pad;
 };
 
+// Device-event timing of the phases (icur_info).  When off (the batched workers), every
+// call is a no-op and every duration reads 0, saving nine runtime calls per iteration.
 struct Timer {
   DeviceCache* dc;
   hipStream_t st;
+  bool on = true;
   size_t used = 0;
-  std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;
   // An event slot that the caller records itself (or that mark() records now).
   int reserve(size_t* idx) {
+    if (!on) {
+      *idx = 0;
+      return ICUR_OK;
+    }
     if (used == dc->events.size()) {
       hipEvent_t e;
       ICUR_HIP(hipEventCreate(&e));
@@ -157,11 +163,15 @@ struct Timer {
   }
   int mark(size_t* idx) {
     ICUR_TRY(reserve(idx));
-    ICUR_HIP(hipEventRecord(dc->events[*idx], st));
+    return record(*idx);
+  }
+  int record(size_t idx) {
+    if (on) ICUR_HIP(hipEventRecord(dc->events[idx], st));
     return ICUR_OK;
   }
-  hipEvent_t event(size_t idx) const { return dc->events[idx]; }
+  hipEvent_t event(size_t idx) const { return on ? dc->events[idx] : nullptr; }
   float ms(size_t a, size_t b) {
+    if (!on) return 0.f;
     float v = 0.f;
     if (hipEventElapsedTime(&v, dc->events[a], dc->events[b]) != hipSuccess) {
       (void)hipGetLastError();
@@ -278,11 +288,12 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
 }
 
 // cache_slot: the workspace to use (0 for single calls); lupp_groups > 0 caps the
-// workgroups of the selection grids (concurrent batched workers share the CUs).
+// workgroups of the selection grids (concurrent batched workers share the CUs); timing
+// false skips the per-phase device events.
 int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block, int32_t kind, uint64_t seed,
              const icur_opts* opts, int64_t* I_out, int64_t* J_out, double* U_out, int64_t* rank_out,
              double* est_out, std::chrono::steady_clock::time_point t_start, int cache_slot = 0,
-             int lupp_groups = 0) {
+             int lupp_groups = 0, bool timing = true) {
   const float* A = src.A;
   const int64_t lda = src.lda;
   const bool sparse = (src.csr != nullptr);
@@ -319,6 +330,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
   Timer tm{&dc, st};
+  tm.on = timing;
   CscCopy csc{};
   if (sparse) {
     // a canonical CSR is required: rowptr from 0 to nnz, columns in range, sorted and
@@ -467,7 +479,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
       sk = sketch_product(G, ldg, c, A, m, n, lda, sketch_terms, tol < kSketchChunkFlushBelow, S, n, dnorm,
                           &parts, pGemm, dc.buf[kGemmWs].bytes, st, tm.event(ev_p0), tm.event(ev_p1));
     if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
-    if (sk == ICUR_ERR_UNSUPPORTED) ICUR_HIP(hipEventRecord(tm.event(ev_p0), st));
+    if (sk == ICUR_ERR_UNSUPPORTED) ICUR_TRY(tm.record(ev_p0));
     WideGemm g{};
     g.W = G;
     g.ldw = ldg;
@@ -487,7 +499,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     g.nparts = &parts;
     if (sk == ICUR_ERR_UNSUPPORTED) {
       ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
-      ICUR_HIP(hipEventRecord(tm.event(ev_p1), st));
+      ICUR_TRY(tm.record(ev_p1));
     }
     ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
   }
@@ -610,10 +622,8 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     ICUR_TRY(launch_gather_f64(S, n, nullptr, c, Jk, nI, false, W64, nI, st));
     ICUR_TRY(product(W64, c, nI, S, n, Urk, n, n, true, S, n, true, true, &parts));
     ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_s, st));
-    ICUR_TRY(launch_set_mask(static_cast<uint8_t*>(pColMask), Jk, nI, st));
-    ICUR_TRY(launch_set_mask(static_cast<uint8_t*>(pRowMask), Ik, nI, st));
-    ICUR_HIP(hipMemcpyAsync(static_cast<int64_t*>(pJall) + r, Jk, nI * 8, hipMemcpyDeviceToDevice, st));
-    ICUR_HIP(hipMemcpyAsync(static_cast<int64_t*>(pIall) + r, Ik, nI * 8, hipMemcpyDeviceToDevice, st));
+    ICUR_TRY(launch_commit_block(static_cast<uint8_t*>(pColMask), static_cast<uint8_t*>(pRowMask), Jk, Ik, nI,
+                                 static_cast<int64_t*>(pJall) + r, static_cast<int64_t*>(pIall) + r, st));
     ICUR_TRY(tm.mark(&e4));
     ICUR_TRY(read_scal(dc, dscal, &hs, st));
     if (hs.info != 0) {
@@ -783,7 +793,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
     src.lda = lda[i];
     const int st = run_impl(src, m[i], n[i], tol[i], block, sketch_kind, seed[i], &oo, I_pool + cap_offsets[i],
                             J_pool + cap_offsets[i], U_pool + uoff[i], rank + i, est_err + i,
-                            std::chrono::steady_clock::now(), 1 + s, groups);
+                            std::chrono::steady_clock::now(), 1 + s, groups, false);
     status[i] = st;
     if (st < 0) {
       errs[i] = t_error;

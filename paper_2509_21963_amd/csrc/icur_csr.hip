@@ -60,26 +60,15 @@ __global__ void csr_validate_kernel(const int64_t* __restrict__ rowptr, const in
 }
 
 // ---------------------------------------------------------------- CSC copy
-__global__ void iota_kernel(int32_t* p, int64_t n) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = static_cast<int32_t>(e);
-}
-
-// row index of every entry (one thread per row)
-__global__ void expand_rows_kernel(const int64_t* __restrict__ rowptr, int64_t m, int32_t* __restrict__ rowidx) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+// Every entry packed as (row << 32) | FP32 bits of its value, in CSR order: one wave per
+// row, lanes striding over the row's entries.
+__global__ void pack_entries_kernel(const int64_t* __restrict__ rowptr, const float* __restrict__ vals, int64_t m,
+                                    unsigned long long* __restrict__ ent) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= m) return;
-  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) rowidx[p] = static_cast<int32_t>(i);
-}
-
-__global__ void permute_entries_kernel(const int32_t* __restrict__ perm, const int32_t* __restrict__ rowidx,
-                                       const float* __restrict__ vals, int64_t nnz, int32_t* __restrict__ csc_row,
-                                       float* __restrict__ csc_val) {
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  const int32_t q = perm[p];
-  csc_row[p] = rowidx[q];
-  csc_val[p] = vals[q];
+  const unsigned long long hi = static_cast<unsigned long long>(i) << 32;
+  for (int64_t p = rowptr[i] + (threadIdx.x & 63); p < rowptr[i + 1]; p += 64)
+    ent[p] = hi | __float_as_uint(vals[p]);
 }
 
 // colptr[j] = first position of column j in the sorted column indices
@@ -131,7 +120,7 @@ __device__ __forceinline__ double readlane_f64(double v, int t) {
 // Every row's sum runs over the entries in column order, one FP64 fma per entry.
 template <int W, bool SIGN>
 __global__ __launch_bounds__(64 * kSkWaves) void csc_sketch_kernel(
-    const int64_t* __restrict__ colptr, const int32_t* __restrict__ csc_row, const float* __restrict__ csc_val,
+    const int64_t* __restrict__ colptr, const unsigned long long* __restrict__ ent,
     int64_t n, int c, const unsigned long long* __restrict__ masks, const uint16_t* __restrict__ Gt, int64_t ldgt,
     double* __restrict__ X0, int64_t ldx, double* __restrict__ norm_partials) {
   __shared__ double red[kSkWaves];
@@ -145,8 +134,9 @@ __global__ __launch_bounds__(64 * kSkWaves) void csc_sketch_kernel(
     for (int64_t p0 = b; p0 < e; p0 += 64) {
       const int64_t p = p0 + lane;
       const bool valid = p < e;
-      const int64_t i = valid ? csc_row[p] : 0;
-      const double a = valid ? static_cast<double>(csc_val[p]) : 0.0;
+      const unsigned long long en = valid ? ent[p] : 0ull;
+      const int64_t i = static_cast<int64_t>(en >> 32);
+      const double a = static_cast<double>(__uint_as_float(static_cast<unsigned>(en)));
       const int cnt = static_cast<int>(e - p0 < 64 ? e - p0 : 64);
       if constexpr (SIGN) {
         unsigned long long mk[W], sg[W];
@@ -213,18 +203,123 @@ __global__ __launch_bounds__(64 * kSkWaves) void csc_sketch_kernel(
   }
 }
 
+// Sparse-sign sketch with lane-private accumulators in LDS, for c <= 128.  One wave per
+// column j.  Lane l owns a private FP64 vector of the c sketch rows (LDS, row stride 65
+// so that lanes stay on separate banks).  It walks the column's entries l, l+64, ... in
+// order and adds +-a into the z rows its entry's row of A maps to (z <= 8 distinct
+// rows, so each entry costs z read-add-writes instead of a pass over all c rows).  At
+// the end lane r sums row r over the 64 private vectors in lane order.  Every sum has a
+// fixed order, so the result is deterministic.
+constexpr int kLdsStride = 65;
+
+__global__ void csc_sketch_sign_lds_kernel(const int64_t* __restrict__ colptr, const unsigned long long* __restrict__ ent,
+                                           int64_t n, int c,
+                                           const uint8_t* __restrict__ rows, const uint8_t* __restrict__ signs, int z,
+                                           double* __restrict__ X0, int64_t ldx, double* __restrict__ norm_partials) {
+  extern __shared__ double sk_lds[];
+  __shared__ double red[kSkWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  double* acc = sk_lds + static_cast<int64_t>(wave) * c * kLdsStride;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * waves + wave;
+  for (int r = 0; r < c; ++r) acc[r * kLdsStride + lane] = 0.0;
+  if (j < n) {
+    const int64_t b = colptr[j], e = colptr[j + 1];
+    // software pipeline over this lane's entries: the row pattern of the next entry and
+    // the index of the one after are loaded while the current entry is added in
+    auto pattern = [&](int64_t i, unsigned long long* rr, unsigned* sb) {
+      if (z == 8) {
+        *rr = *reinterpret_cast<const unsigned long long*>(rows + i * 8);
+      } else {
+        unsigned long long v = 0;
+        for (int t = 0; t < z; ++t) v |= static_cast<unsigned long long>(rows[i * z + t]) << (8 * t);
+        *rr = v;
+      }
+      *sb = signs[i];
+    };
+    int64_t p0 = b + lane;
+    int64_t i0 = 0, i1 = 0;
+    double a0 = 0.0, a1 = 0.0;
+    unsigned long long rr0 = 0;
+    unsigned sb0 = 0;
+    if (p0 < e) {
+      {
+        const unsigned long long en = ent[p0];
+        i0 = static_cast<int64_t>(en >> 32);
+        a0 = static_cast<double>(__uint_as_float(static_cast<unsigned>(en)));
+      }
+      pattern(i0, &rr0, &sb0);
+    }
+    int64_t p1 = p0 + 64;
+    if (p1 < e) {
+      {
+        const unsigned long long en = ent[p1];
+        i1 = static_cast<int64_t>(en >> 32);
+        a1 = static_cast<double>(__uint_as_float(static_cast<unsigned>(en)));
+      }
+    }
+    while (p0 < e) {
+      unsigned long long rr1 = 0;
+      unsigned sb1 = 0;
+      if (p1 < e) pattern(i1, &rr1, &sb1);
+      const int64_t p2 = p1 + 64;
+      int64_t i2 = 0;
+      double a2 = 0.0;
+      if (p2 < e) {
+        const unsigned long long en = ent[p2];
+        i2 = static_cast<int64_t>(en >> 32);
+        a2 = static_cast<double>(__uint_as_float(static_cast<unsigned>(en)));
+      }
+      for (int t = 0; t < z; ++t) {
+        const int r = static_cast<int>((rr0 >> (8 * t)) & 0xFFu);
+        double* slot = acc + r * kLdsStride + lane;
+        *slot = *slot + (((sb0 >> t) & 1u) ? -a0 : a0);
+      }
+      p0 = p1;
+      a0 = a1;
+      rr0 = rr1;
+      sb0 = sb1;
+      p1 = p2;
+      i1 = i2;
+      a1 = a2;
+    }
+  }
+  // lane-private slots were written by their own lane only; the row sums read every lane
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  double sq = 0.0;
+  if (j < n) {
+    for (int r = lane; r < c; r += 64) {
+      const double* row = acc + r * kLdsStride;
+      double s = 0.0;
+      for (int q = 0; q < 64; ++q) s += row[q];
+      X0[r * ldx + j] = s;
+      sq += s * s;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < waves; ++w) s += red[w];
+    norm_partials[blockIdx.x] = s;
+  }
+}
+
 // ---------------------------------------------------------------- gathers
 // Ct row t = column cols[t] of A (dense, length m); Ct is cleared first by the caller.
 template <typename DstT>
-__global__ void csc_scatter_cols_kernel(const int64_t* __restrict__ colptr, const int32_t* __restrict__ csc_row,
-                                        const float* __restrict__ csc_val, const int64_t* __restrict__ cols,
-                                        DstT* __restrict__ Ct, int64_t ldct) {
+__global__ void csc_scatter_cols_kernel(const int64_t* __restrict__ colptr, const unsigned long long* __restrict__ ent,
+                                        const int64_t* __restrict__ cols, DstT* __restrict__ Ct, int64_t ldct) {
   const int t = blockIdx.y;
   const int64_t j = cols[t];
   const int64_t b = colptr[j], e = colptr[j + 1];
   for (int64_t p = b + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; p < e;
-       p += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    Ct[t * ldct + csc_row[p]] = static_cast<DstT>(csc_val[p]);
+       p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const unsigned long long en = ent[p];
+    Ct[t * ldct + static_cast<int64_t>(en >> 32)] = static_cast<DstT>(__uint_as_float(static_cast<unsigned>(en)));
+  }
 }
 
 // R row t = row rows[t] of A (dense, length n); R is cleared first by the caller.
@@ -294,11 +389,12 @@ size_t csc_workspace_bytes(int64_t nnz, int64_t n) {
   size_t tmp = 0;
   const int64_t cnt = std::max<int64_t>(nnz, 1);
   (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, static_cast<const int32_t*>(nullptr),
-                                           static_cast<int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                                           static_cast<int32_t*>(nullptr), static_cast<int>(cnt), 0, 31);
+                                           static_cast<int32_t*>(nullptr),
+                                           static_cast<const unsigned long long*>(nullptr),
+                                           static_cast<unsigned long long*>(nullptr), static_cast<int>(cnt), 0, 31);
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  // colptr, csc_row, csc_val, then scratch: sorted keys, perm in/out, rowidx, sort temp
-  return al((n + 1) * 8) + 2 * al(cnt * 4) + 4 * al(cnt * 4) + al(tmp);
+  // colptr, packed entries, then scratch: sorted keys, packed entries in CSR order, sort temp
+  return al((n + 1) * 8) + al(cnt * 8) + al(cnt * 4) + al(cnt * 8) + al(tmp);
 }
 
 int csc_build(const CsrMatrix& A, CscCopy* out, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -308,31 +404,23 @@ int csc_build(const CsrMatrix& A, CscCopy* out, void* ws, size_t ws_bytes, hipSt
   char* p = static_cast<char*>(ws);
   out->colptr = reinterpret_cast<int64_t*>(p);
   p += al((A.n + 1) * 8);
-  out->row = reinterpret_cast<int32_t*>(p);
-  p += al(cnt * 4);
-  out->val = reinterpret_cast<float*>(p);
-  p += al(cnt * 4);
+  unsigned long long* ent_sorted = reinterpret_cast<unsigned long long*>(p);
+  out->ent = ent_sorted;
+  p += al(cnt * 8);
   int32_t* keys = reinterpret_cast<int32_t*>(p);
   p += al(cnt * 4);
-  int32_t* perm_in = reinterpret_cast<int32_t*>(p);
-  p += al(cnt * 4);
-  int32_t* perm_out = reinterpret_cast<int32_t*>(p);
-  p += al(cnt * 4);
-  int32_t* rowidx = reinterpret_cast<int32_t*>(p);
-  p += al(cnt * 4);
+  unsigned long long* ent_rows = reinterpret_cast<unsigned long long*>(p);
+  p += al(cnt * 8);
   void* tmp = p;
   size_t tmp_bytes = ws_bytes - static_cast<size_t>(p - static_cast<char*>(ws));
   if (A.nnz > 0) {
-    const unsigned gb = static_cast<unsigned>((A.nnz + 255) / 256);
-    hipLaunchKernelGGL(iota_kernel, dim3(gb), dim3(256), 0, st, perm_in, A.nnz);
-    hipLaunchKernelGGL(expand_rows_kernel, dim3(static_cast<unsigned>((A.m + 255) / 256)), dim3(256), 0, st,
-                       A.rowptr, A.m, rowidx);
+    // pack (row, value) in CSR order, then a stable sort by column carries the packed
+    // entries along: rows stay increasing within each column
+    hipLaunchKernelGGL(pack_entries_kernel, dim3(static_cast<unsigned>((A.m + 3) / 4)), dim3(256), 0, st, A.rowptr,
+                       A.vals, A.m, ent_rows);
     ICUR_HIP(hipGetLastError());
-    ICUR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, A.colind, keys, perm_in, perm_out,
+    ICUR_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, A.colind, keys, ent_rows, ent_sorted,
                                                 static_cast<int>(A.nnz), 0, sort_bits(A.n), st));
-    hipLaunchKernelGGL(permute_entries_kernel, dim3(gb), dim3(256), 0, st, perm_out, rowidx, A.vals, A.nnz, out->row,
-                       out->val);
-    ICUR_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(colptr_kernel, dim3(static_cast<unsigned>((A.n + 1 + 255) / 256)), dim3(256), 0, st, keys,
                      A.nnz, A.n, out->colptr);
@@ -352,6 +440,24 @@ int csr_sketch(const CscCopy& csc, int64_t m, int64_t n, int64_t c, int kind, ui
   const int W = static_cast<int>((c + 63) / 64);
   const unsigned blocks = static_cast<unsigned>((n + kSkWaves - 1) / kSkWaves);
   char* p = static_cast<char*>(aux);
+  if (kind == ICUR_SKETCH_SPARSE_SIGN && c <= 128) {
+    const int z = std::min<int>(zeta, static_cast<int>(c));
+    uint8_t* rows = reinterpret_cast<uint8_t*>(p);
+    uint8_t* signs = rows + static_cast<size_t>(m) * 8;
+    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, rows, signs, nullptr, 0, st));
+    const size_t per_wave = static_cast<size_t>(c) * kLdsStride * sizeof(double);
+    const int waves = static_cast<int>(std::max<size_t>(1, std::min<size_t>(kSkWaves, (160 * 1024) / per_wave)));
+    const size_t lds = per_wave * waves;
+    if (lds > 64 * 1024)
+      ICUR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(csc_sketch_sign_lds_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    const unsigned lblocks = static_cast<unsigned>((n + waves - 1) / waves);
+    hipLaunchKernelGGL(csc_sketch_sign_lds_kernel, dim3(lblocks), dim3(64 * waves), lds, st, csc.colptr, csc.ent, n,
+                       static_cast<int>(c), rows, signs, z, X0, ldx, norm_partials);
+    ICUR_HIP(hipGetLastError());
+    if (nparts) *nparts = static_cast<int>(lblocks);
+    return ICUR_OK;
+  }
   if (kind == ICUR_SKETCH_SPARSE_SIGN) {
     const int z = std::min<int>(zeta, static_cast<int>(c));
     unsigned long long* masks = reinterpret_cast<unsigned long long*>(p);
@@ -365,7 +471,7 @@ int csr_sketch(const CscCopy& csc, int64_t m, int64_t n, int64_t c, int kind, ui
 #define ICUR_CSR_SIGN(X)                                                                                        \
   case X:                                                                                                       \
     hipLaunchKernelGGL((csc_sketch_kernel<X, true>), dim3(blocks), dim3(64 * kSkWaves), 0, st, csc.colptr,       \
-                       csc.row, csc.val, n, static_cast<int>(c), masks, nullptr, 0, X0, ldx, norm_partials); \
+                       csc.ent, n, static_cast<int>(c), masks, nullptr, 0, X0, ldx, norm_partials);           \
     break;
       ICUR_CSR_SIGN(1)
       ICUR_CSR_SIGN(2)
@@ -381,7 +487,7 @@ int csr_sketch(const CscCopy& csc, int64_t m, int64_t n, int64_t c, int kind, ui
 #define ICUR_CSR_GAUSS(X)                                                                                       \
   case X:                                                                                                       \
     hipLaunchKernelGGL((csc_sketch_kernel<X, false>), dim3(blocks), dim3(64 * kSkWaves), 0, st, csc.colptr,      \
-                       csc.row, csc.val, n, static_cast<int>(c), nullptr, Gt, ldgt, X0, ldx, norm_partials); \
+                       csc.ent, n, static_cast<int>(c), nullptr, Gt, ldgt, X0, ldx, norm_partials);           \
     break;
       ICUR_CSR_GAUSS(1)
       ICUR_CSR_GAUSS(2)
@@ -395,7 +501,7 @@ int csr_sketch(const CscCopy& csc, int64_t m, int64_t n, int64_t c, int kind, ui
   return ICUR_OK;
 }
 
-int csr_max_norm_partials(int64_t n) { return static_cast<int>((n + kSkWaves - 1) / kSkWaves); }
+int csr_max_norm_partials(int64_t n) { return static_cast<int>(n); }  // one wave per block at most
 
 template <typename DstT>
 int csc_gather_cols_T_t(const CscCopy& csc, int64_t m, const int64_t* cols, int64_t k, DstT* Ct, int64_t ldct,
@@ -407,7 +513,7 @@ int csc_gather_cols_T_t(const CscCopy& csc, int64_t m, const int64_t* cols, int6
     for (int64_t t = 0; t < k; ++t) ICUR_TRY(zero(Ct + t * ldct, m, st));
   }
   hipLaunchKernelGGL(csc_scatter_cols_kernel<DstT>, dim3(8, static_cast<unsigned>(k)), dim3(256), 0, st, csc.colptr,
-                     csc.row, csc.val, cols, Ct, ldct);
+                     csc.ent, cols, Ct, ldct);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }

@@ -80,9 +80,18 @@ __global__ void gather_f64_kernel(const SrcT* __restrict__ src, int64_t lds,
     dst[i * ldd + j] = v;
 }
 
-__global__ void set_mask_kernel(uint8_t* mask, const int64_t* idx, int64_t k) {
+// The end of an iteration: the k new columns and rows are masked out of later selections
+// and appended to J and I.
+__global__ void commit_block_kernel(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, const int64_t* Ik,
+                                    int64_t k, int64_t* Jall, int64_t* Iall) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < k) mask[idx[t]] = 1;
+  if (t < k) {
+    const int64_t j = Jk[t], i = Ik[t];
+    colmask[j] = 1;
+    rowmask[i] = 1;
+    Jall[t] = j;
+    Iall[t] = i;
+  }
 }
 
 __global__ void fill_u8_kernel(uint8_t* p, int64_t n, uint8_t v) {
@@ -175,10 +184,11 @@ int launch_gather_f64(const double* src, int64_t lds, const int64_t* rows, int64
   return gather_f64_t(src, lds, rows, rk, cols, ck, trans, dst, ldd, st);
 }
 
-int launch_set_mask(uint8_t* mask, const int64_t* idx, int64_t k, hipStream_t st) {
+int launch_commit_block(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, const int64_t* Ik, int64_t k,
+                        int64_t* Jall, int64_t* Iall, hipStream_t st) {
   if (k <= 0) return ICUR_OK;
-  hipLaunchKernelGGL(set_mask_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st,
-                     mask, idx, k);
+  hipLaunchKernelGGL(commit_block_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st, colmask,
+                     rowmask, Jk, Ik, k, Jall, Iall);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }

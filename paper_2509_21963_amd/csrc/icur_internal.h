@@ -120,9 +120,8 @@ struct CsrMatrix {
   int64_t m, n, nnz;
 };
 struct CscCopy {
-  int64_t* colptr;  // n + 1
-  int32_t* row;     // nnz, increasing within each column
-  float* val;       // nnz
+  int64_t* colptr;          // n + 1
+  unsigned long long* ent;  // nnz entries (row << 32) | FP32 bits, rows increasing within each column
 };
 // Device flag (bit 0 rowptr, bit 1 column range, bit 2 order within a row); 0 = valid.
 int csr_validate(const CsrMatrix& A, unsigned* flag_dev, hipStream_t st);
@@ -185,7 +184,9 @@ int launch_gather_f64(const float* src, int64_t lds, const int64_t* rows, int64_
 int launch_gather_f64(const double* src, int64_t lds, const int64_t* rows, int64_t rk,
                       const int64_t* cols, int64_t ck, bool trans, double* dst, int64_t ldd,
                       hipStream_t st);
-int launch_set_mask(uint8_t* mask, const int64_t* idx, int64_t k, hipStream_t st);
+// colmask[Jk[t]] = rowmask[Ik[t]] = 1 and Jall[t] = Jk[t], Iall[t] = Ik[t] for t < k.
+int launch_commit_block(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, const int64_t* Ik, int64_t k,
+                        int64_t* Jall, int64_t* Iall, hipStream_t st);
 int launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 
