@@ -115,7 +115,13 @@ __device__ __forceinline__ void load_l16(const double* L, int N, int k0, int64_t
 
 template <typename InT>
 __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
-  if (a.w.status[1] != 0 || a.w.status[2] != 0) return;  // fault, or no pivots left
+  if (a.t0 == 0) {
+    // first panel of a call: clear the control words (barrier counter, status, first
+    // pivot) for the panel kernels that follow on the stream
+    if (blockIdx.x == 0 && threadIdx.x < kCtlBytes / sizeof(unsigned)) a.w.bar[threadIdx.x] = 0u;
+  } else if (a.w.status[1] != 0 || a.w.status[2] != 0) {
+    return;  // fault, or no pivots left
+  }
   const InT* X = static_cast<const InT*>(a.X);
   extern __shared__ double Upan[];  // t0 x kPW: pivot rows 0..t0-1 at 16 columns
   const int tid = threadIdx.x;
@@ -486,7 +492,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
     return ICUR_ERR_UNSUPPORTED;
   }
   const int groups = static_cast<int>((N + per_group - 1) / per_group);
-  ICUR_TRY(launch_fill_u32(w.ctl, kCtlBytes / sizeof(unsigned), 0u, st));  // barrier and status
+  // the control words (barrier and status) are cleared by the first prep launch
 
   Work wk;
   wk.L = w.L;
