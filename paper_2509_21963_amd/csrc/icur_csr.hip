@@ -30,33 +30,29 @@ constexpr int kMaxWords = 4;  // c <= 256 rows of G
 // ---------------------------------------------------------------- validation
 // flag bit 0: rowptr not monotone or wrong ends; bit 1: column out of range; bit 2:
 // columns not strictly increasing within a row.
+// One wave per row (wave m checks rowptr[m]); lanes stride over the row's entries, each
+// comparing its column with the previous entry's.
 __global__ void csr_validate_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                                     int64_t m, int64_t n, int64_t nnz, unsigned* flag) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i > m) return;
-  if (i == 0 && rowptr[0] != 0) atomicOr(flag, 1u);
   if (i == m) {
-    if (rowptr[m] != nnz) atomicOr(flag, 1u);
+    if (lane == 0 && (rowptr[0] != 0 || rowptr[m] != nnz)) atomicOr(flag, 1u);
     return;
   }
   const int64_t b = rowptr[i], e = rowptr[i + 1];
   if (e < b || b < 0 || e > nnz) {
-    atomicOr(flag, 1u);
+    if (lane == 0) atomicOr(flag, 1u);
     return;
   }
-  int64_t prev = -1;
-  for (int64_t p = b; p < e; ++p) {
+  unsigned bad = 0;
+  for (int64_t p = b + lane; p < e; p += 64) {
     const int64_t j = colind[p];
-    if (j < 0 || j >= n) {
-      atomicOr(flag, 2u);
-      return;
-    }
-    if (j <= prev) {
-      atomicOr(flag, 4u);
-      return;
-    }
-    prev = j;
+    if (j < 0 || j >= n) bad |= 2u;
+    if (p > b && j <= static_cast<int64_t>(colind[p - 1])) bad |= 4u;
   }
+  if (bad) atomicOr(flag, bad);
 }
 
 // ---------------------------------------------------------------- CSC copy
@@ -378,9 +374,9 @@ int sort_bits(int64_t n) {
 
 int csr_validate(const CsrMatrix& A, unsigned* flag_dev, hipStream_t st) {
   ICUR_TRY(launch_fill_u32(flag_dev, 1, 0u, st));
-  const int64_t threads = A.m + 1;
-  hipLaunchKernelGGL(csr_validate_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, st,
-                     A.rowptr, A.colind, A.m, A.n, A.nnz, flag_dev);
+  const int64_t waves = A.m + 1;
+  hipLaunchKernelGGL(csr_validate_kernel, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, st, A.rowptr,
+                     A.colind, A.m, A.n, A.nnz, flag_dev);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }
