@@ -597,7 +597,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     }
     // N_k = S^{(k-1)}(I_k, J_k) and its inverse (FP64)
     ICUR_TRY(gather_w(Lk, m, nI, Ik, nI, true, Nblk, nI));
-    ICUR_TRY(launch_small_inverse(Nblk, nI, Nwork, &dscal->info, nullptr, st));
+    ICUR_TRY(launch_inorder_inverse(Nblk, nI, Nwork, &dscal->info, st));
     // N_1 = A(I_1, J_1) exactly: its inverse is the core's first diagonal block inverse
     if (r == 0) ICUR_HIP(hipMemcpyAsync(N1inv, Nblk, static_cast<size_t>(nI) * nI * 8, hipMemcpyDeviceToDevice, st));
     // residual at the new rows: Sr = A(I_k,:) - Lc(I_k,:) Ur

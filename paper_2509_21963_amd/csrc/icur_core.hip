@@ -380,6 +380,84 @@ __global__ __launch_bounds__(256) void gj_inverse_tile_kernel(double* __restrict
   if (tid == 0) *info = 0;
 }
 
+// The same inverse for a block whose rows are already in partial-pivoting order: the
+// pivot block N_k of a row selection (rows I_k in selection order, columns J_k) is the
+// leading part of an LU with partial pivoting, so eliminating on the diagonal in order
+// keeps every multiplier within 1 and needs no pivot search.  Per step the tile column
+// and the tile row holding column and row j publish them, one barrier, then the update.
+// A zero pivot reports info = 1.
+__global__ __launch_bounds__(256) void gj_inverse_inorder_kernel(double* __restrict__ Ng, int k,
+                                                                 int* __restrict__ info) {
+  __shared__ double colj[2][128];
+  __shared__ double prow[2][128];
+  const int tid = threadIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
+  const int r0 = 8 * tr, c0 = 8 * tc;
+  double a[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int r = r0 + i, c = c0 + jj;
+      a[i][jj] = (r < k && c < k) ? Ng[r * k + c] : 0.0;
+    }
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    const int tj = j0 >> 3;
+    bool fail = false;
+    tile_static_for<8>([&](auto jcc) __attribute__((always_inline)) {
+      constexpr int jc = decltype(jcc)::value;
+      const int j = j0 + jc;
+      if (fail || j >= k) return;
+      const int b = j & 1;
+      if (tc == tj) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) colj[b][r0 + i] = a[i][jc];
+      }
+      if (tr == tj) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) prow[b][c0 + jj] = a[jc][jj];
+      }
+      __syncthreads();
+      const double piv = colj[b][j];
+      if (piv == 0.0) {  // uniform: every thread read the same word
+        fail = true;
+        return;
+      }
+      const double rinv = 1.0 / piv;
+      double pr[8], f[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) pr[jj] = prow[b][c0 + jj] * rinv;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) f[i] = colj[b][r0 + i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) a[i][jj] = a[i][jj] - f[i] * pr[jj];
+      if (tc == tj) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i][jc] = -f[i] * rinv;
+      }
+      if (tr == tj) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) a[jc][jj] = pr[jj];
+        if (tc == tj) a[jc][jc] = rinv;
+      }
+    });
+    if (fail) {
+      if (tid == 0) *info = 1;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int r = r0 + i, c = c0 + jj;
+      if (r < k && c < k) Ng[r * k + c] = a[i][jj];
+    }
+  if (tid == 0) *info = 0;
+}
+
 }  // namespace
 
 namespace {
@@ -474,6 +552,15 @@ int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* 
   return ICUR_OK;
 }
 
+int launch_inorder_inverse(double* N, int64_t k, double* work, int* info, hipStream_t st) {
+  if (k >= 1 && k <= 128) {
+    hipLaunchKernelGGL(gj_inverse_inorder_kernel, dim3(1), dim3(256), 0, st, N, static_cast<int>(k), info);
+    ICUR_HIP(hipGetLastError());
+    return ICUR_OK;
+  }
+  return launch_small_inverse(N, k, work, info, nullptr, st);
+}
+
 // U (ldu) grows from r x r to (r+k) x (r+k).  ws must hold k*k + 2*k*r + k*k doubles.
 int core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y, int64_t ldy,
                 const double* A21, const double* A22, double* ws, int* info, double* norms,
@@ -523,7 +610,12 @@ int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblo
       ICUR_HIP(hipMemcpyAsync(Dk, D0inv, static_cast<size_t>(nk) * nk * 8, hipMemcpyDeviceToDevice, st));
     } else {
       ICUR_TRY(dcopy2d(nk, nk, 1.0, M + q * r + q, r, Dk, nk, st));
-      ICUR_TRY(launch_small_inverse(Dk, nk, gjw, info + k, norms, st));
+      // the diagonal blocks are Schur complements in selection order: partial-pivoting
+      // order already (unless a norm estimate is asked for, which the general kernel makes)
+      if (norms == nullptr)
+        ICUR_TRY(launch_inorder_inverse(Dk, nk, gjw, info + k, st));
+      else
+        ICUR_TRY(launch_small_inverse(Dk, nk, gjw, info + k, norms, st));
     }
     const int64_t rest = r - q - nk;
     if (rest > 0) {

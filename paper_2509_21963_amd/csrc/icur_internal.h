@@ -201,6 +201,10 @@ int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_
 // (device, may be null) receives ||N||_1 and ||N^-1||_1 (max column sums).
 int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
                          hipStream_t st);
+// Inverse of a k x k block whose rows are in partial-pivoting order (the pivot block of a
+// row selection, or a Schur complement of the cross in selection order): elimination on
+// the diagonal without a pivot search (k <= 128; larger k use launch_small_inverse).
+int launch_inorder_inverse(double* N, int64_t k, double* work, int* info, hipStream_t st);
 size_t small_inverse_work_bytes(int64_t k);
 int dcopy2d(int64_t M, int64_t N, double alpha, const double* src, int64_t lds, double* dst,
             int64_t ldd, hipStream_t st);
