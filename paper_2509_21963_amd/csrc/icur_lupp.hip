@@ -275,14 +275,10 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
       unsigned long long gk;
       int gi, gw;
       block_argmax<LT>(cand_key(bv), bi, 0, red[0], &gk, &gi, &gw);
-      // (b) the owner (or thread 0 when the workgroup has no candidate) publishes the
-      // slot and arrives at the grid barrier; the release orders its slot stores.
-      Slot* slot = a.w.slots + (t & 1) * kMaxGroups + blockIdx.x;
       const bool owner = gk != 0ull && br >= 0 && bi == gi;
-      if (owner) {
-        // select row br with bit masks (a read x[br] with a run-time index would force x
-        // into scratch memory); entries before tt are no longer needed
-        unsigned long long pub[kPW];
+      // the owner's row from column tt on, selected with bit masks (a read x[br] with a
+      // run-time index would force x into scratch memory)
+      auto owner_row = [&](unsigned long long (&pub)[kPW]) {
 #pragma unroll
         for (int jj = tt; jj < kPW; ++jj) pub[jj] = 0ull;
 #pragma unroll
@@ -292,69 +288,94 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
           for (int jj = tt; jj < kPW; ++jj)
             pub[jj] |= static_cast<unsigned long long>(__double_as_longlong(x[r][jj])) & mask;
         }
-#pragma unroll
-        for (int jj = tt; jj < kPW; ++jj)
-          __hip_atomic_store(&slot->row[jj], __longlong_as_double(static_cast<long long>(pub[jj])), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&slot->val, __longlong_as_double(static_cast<long long>(gk)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&slot->idx, static_cast<long long>(gi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else if (gk == 0ull && tid == 0) {
-        __hip_atomic_store(&slot->val, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&slot->idx, static_cast<long long>(INT_MAX), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (owner || (gk == 0ull && tid == 0)) {
-        // The slot words are device-coherent stores; waiting for their completion
-        // before the arrival orders them without a release fence, which would write
-        // back this XCD's whole L2 at every step.
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __hip_atomic_fetch_add(a.w.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      // (c) wait for every workgroup's arrival (thread 0 polls, bounded)
-      if (tid == 0) {
-        const unsigned target = static_cast<unsigned>(t + 1) * static_cast<unsigned>(G);
-        unsigned spins = 0;
-        int ok = 1;
-        while (__hip_atomic_load(a.w.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-          __builtin_amdgcn_s_sleep(1);
-          if ((++spins & 255u) == 0 &&
-              __hip_atomic_load(a.w.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            ok = 0;
-            break;
-          }
-          if (spins > kSpinLimit) {
-            atomicExch(a.w.status + 1, 1);
-            ok = 0;
-            break;
-          }
-        }
-        // no acquire fence: every slot word is read with device-coherent loads, issued
-        // after the counter was seen complete (and after the block barrier below)
-        flag = ok;
-      }
-      __syncthreads();
-      if (!flag) {
-        stop = true;
-      } else {
-        // (d) read every slot (header and row in one round trip) and reduce
-        const Slot* sl = a.w.slots + (t & 1) * kMaxGroups;
-        for (int e = tid; e < G * kPW; e += LT)
-          rows_sh[e] = __hip_atomic_load(&sl[e / kPW].row[e % kPW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long ck = 0ull;
-        int ci = INT_MAX, cw = -1;
-        if (tid < G) {
-          ck = cand_key(__hip_atomic_load(&sl[tid].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          ci = static_cast<int>(__hip_atomic_load(&sl[tid].idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          cw = tid;
-        }
-        block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);  // its barrier also publishes rows_sh
-        if (gk == 0ull) stop = true;  // none left, or an exact zero column
+      };
+      // the pivot (key gk, row gi): none left, an exact zero column, or (with the relative
+      // cut) a Schur complement that is rounding noise of the input's precision ends it
+      auto accept = [&]() {
+        if (gk == 0ull) stop = true;
         if (t == 0) ref_key = gk;
-        // numerically zero: the Schur complement is rounding noise of the input's precision
         if (a.rel_cut > 0.0 && t > 0 &&
             gk <= static_cast<unsigned long long>(__double_as_longlong(a.rel_cut * __longlong_as_double(
                       static_cast<long long>(ref_key)))))
           stop = true;
+      };
+      if (G == 1) {
+        // one workgroup holds every candidate: the pivot row goes through LDS, no grid
+        // exchange (rows_sh was last read before the barrier inside block_argmax above)
+        if (owner) {
+          unsigned long long pub[kPW];
+          owner_row(pub);
+#pragma unroll
+          for (int jj = tt; jj < kPW; ++jj) rows_sh[jj] = __longlong_as_double(static_cast<long long>(pub[jj]));
+        }
+        __syncthreads();
+        gw = 0;
+        accept();
+      } else {
+        // (b) the owner (or thread 0 when the workgroup has no candidate) publishes the
+        // slot and arrives at the grid barrier.
+        Slot* slot = a.w.slots + (t & 1) * kMaxGroups + blockIdx.x;
+        if (owner) {
+          unsigned long long pub[kPW];
+          owner_row(pub);
+#pragma unroll
+          for (int jj = tt; jj < kPW; ++jj)
+            __hip_atomic_store(&slot->row[jj], __longlong_as_double(static_cast<long long>(pub[jj])), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&slot->val, __longlong_as_double(static_cast<long long>(gk)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&slot->idx, static_cast<long long>(gi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (gk == 0ull && tid == 0) {
+          __hip_atomic_store(&slot->val, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&slot->idx, static_cast<long long>(INT_MAX), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (owner || (gk == 0ull && tid == 0)) {
+          // The slot words are device-coherent stores; waiting for their completion
+          // before the arrival orders them without a release fence, which would write
+          // back this XCD's whole L2 at every step.
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          __hip_atomic_fetch_add(a.w.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // (c) wait for every workgroup's arrival (thread 0 polls, bounded)
+        if (tid == 0) {
+          const unsigned target = static_cast<unsigned>(t + 1) * static_cast<unsigned>(G);
+          unsigned spins = 0;
+          int ok = 1;
+          while (__hip_atomic_load(a.w.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 255u) == 0 &&
+                __hip_atomic_load(a.w.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              ok = 0;
+              break;
+            }
+            if (spins > kSpinLimit) {
+              atomicExch(a.w.status + 1, 1);
+              ok = 0;
+              break;
+            }
+          }
+          // no acquire fence: every slot word is read with device-coherent loads, issued
+          // after the counter was seen complete (and after the block barrier below)
+          flag = ok;
+        }
+        __syncthreads();
+        if (!flag) {
+          stop = true;
+        } else {
+          // (d) read every slot (header and row in one round trip) and reduce
+          const Slot* sl = a.w.slots + (t & 1) * kMaxGroups;
+          for (int e = tid; e < G * kPW; e += LT)
+            rows_sh[e] = __hip_atomic_load(&sl[e / kPW].row[e % kPW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          unsigned long long ck = 0ull;
+          int ci = INT_MAX, cw = -1;
+          if (tid < G) {
+            ck = cand_key(__hip_atomic_load(&sl[tid].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            ci = static_cast<int>(__hip_atomic_load(&sl[tid].idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            cw = tid;
+          }
+          block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);  // its barrier also publishes rows_sh
+          accept();
+        }
       }
       if (!stop) {
         if (tid == 0) piv_sh[tt] = gi;
@@ -481,11 +502,17 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   if (steps > w.steps_cap || N > w.N_cap) return arg_error("lupp: workspace too small");
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
-  // Rows per workgroup: the per-step exchange costs more with more workgroups, so
-  // pack more candidates per workgroup and aim for about 16 of them.
+  // Rows per workgroup: up to 2048 candidates fit one workgroup, which needs no grid
+  // exchange; beyond that the per-step exchange costs more with more workgroups, so pack
+  // more candidates per workgroup and aim for about 16 of them.
   const int max_groups = std::min(std::min(dev.num_cus, kMaxGroups), w.max_groups > 0 ? w.max_groups : kMaxGroups);
   int sh = 0;
-  while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * 16 < N) ++sh;
+  if (N <= static_cast<int64_t>(kShape[kShapes - 1].R) * kShape[kShapes - 1].LT) {
+    // one workgroup holds them all: no grid exchange at all (the pivot row goes through LDS)
+    while (static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT < N) ++sh;
+  } else {
+    while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * 16 < N) ++sh;
+  }
   const int64_t per_group = static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT;
   if (per_group * max_groups < N) {
     set_error("lupp: N exceeds the candidates one grid can hold in registers");
