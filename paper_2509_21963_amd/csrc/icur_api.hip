@@ -864,6 +864,7 @@ int icur_release(void) {
     dc.events.clear();
   }
   g_cache.clear();
+  release_blas_handles();
   ICUR_HIP(hipSetDevice(dev0));
   return ICUR_OK;
 }

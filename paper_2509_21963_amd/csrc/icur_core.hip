@@ -14,6 +14,8 @@
 #include <utility>
 
 #include <map>
+#include <memory>
+#include <mutex>
 
 #include <rocblas/rocblas.h>
 
@@ -461,28 +463,46 @@ __global__ __launch_bounds__(256) void gj_inverse_inorder_kernel(double* __restr
 }  // namespace
 
 namespace {
-// rocBLAS handles, one per host thread and device (a handle must not be shared by
-// threads that issue at the same time); atomics off so that every product is
-// reproducible run to run.
-thread_local std::map<int, rocblas_handle> t_blas;
+// rocBLAS handles, one per (device, stream), kept for the life of the process (or until
+// icur_release): the batched workers reuse theirs call after call.  Each handle has a
+// mutex held across set_stream and the product, so threads sharing a stream cannot
+// interleave on it.  Atomics off so that every product is reproducible run to run.
+struct BlasEntry {
+  rocblas_handle h = nullptr;
+  std::mutex mu;
+};
+std::mutex g_blas_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<BlasEntry>> g_blas;
 
-int blas_handle(rocblas_handle* out) {
+int blas_entry(hipStream_t st, BlasEntry** out) {
   int dev = 0;
   ICUR_HIP(hipGetDevice(&dev));
-  auto it = t_blas.find(dev);
-  if (it == t_blas.end()) {
-    rocblas_handle h;
-    if (rocblas_create_handle(&h) != rocblas_status_success) {
+  std::lock_guard<std::mutex> g(g_blas_mu);
+  auto& e = g_blas[{dev, st}];
+  if (!e) {
+    std::unique_ptr<BlasEntry> ne(new BlasEntry());
+    if (rocblas_create_handle(&ne->h) != rocblas_status_success) {
+      g_blas.erase({dev, st});
       set_error("rocblas_create_handle failed");
       return ICUR_ERR_HIP;
     }
-    rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
-    it = t_blas.emplace(dev, h).first;
+    rocblas_set_atomics_mode(ne->h, rocblas_atomics_not_allowed);
+    e = std::move(ne);
   }
-  *out = it->second;
+  *out = e.get();
   return ICUR_OK;
 }
 }  // namespace
+
+void release_blas_handles() {
+  std::lock_guard<std::mutex> g(g_blas_mu);
+  for (auto& kv : g_blas) {
+    std::lock_guard<std::mutex> l(kv.second->mu);
+    if (kv.second->h) rocblas_destroy_handle(kv.second->h);
+    kv.second->h = nullptr;
+  }
+  g_blas.clear();
+}
 
 int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sa0,
           int64_t sa1, const double* B, int64_t sb0, int64_t sb1, double beta, double* C,
@@ -492,8 +512,10 @@ int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_
   // column-major product C^T = alpha B^T A^T + beta C^T on FP64 matrix cores.
   if (sa1 == 1 && sb1 == 1 && K > 0 && M <= INT32_MAX && N <= INT32_MAX && K <= INT32_MAX && sa0 <= INT32_MAX &&
       sb0 <= INT32_MAX && ldc <= INT32_MAX) {
-    rocblas_handle h;
-    ICUR_TRY(blas_handle(&h));
+    BlasEntry* be;
+    ICUR_TRY(blas_entry(st, &be));
+    std::lock_guard<std::mutex> l(be->mu);
+    rocblas_handle h = be->h;
     if (rocblas_set_stream(h, st) != rocblas_status_success ||
         rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, static_cast<rocblas_int>(N),
                       static_cast<rocblas_int>(M), static_cast<rocblas_int>(K), &alpha, B,

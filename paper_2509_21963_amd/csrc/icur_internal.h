@@ -193,6 +193,8 @@ int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 // ----- FP64 dense kernels (icur_core.hip) -----
 // C(M x N) = alpha * A(M x K) B(K x N) + beta * C with element strides:
 // A(i,k) = A[i*sa0 + k*sa1], B(k,j) = B[k*sb0 + j*sb1], C(i,j) = C[i*ldc + j].
+// Destroys the library GEMM handles (icur_release).
+void release_blas_handles();
 int dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sa0,
           int64_t sa1, const double* B, int64_t sb0, int64_t sb1, double beta, double* C,
           int64_t ldc, hipStream_t st);
