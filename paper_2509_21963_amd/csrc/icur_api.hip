@@ -804,16 +804,21 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
     total_iters += t_info.iterations;
   };
   std::atomic<size_t> next{0};
+  auto worker = [&](int s) {
+    if (hipSetDevice(dev.device) != hipSuccess) return;
+    for (;;) {
+      const size_t q = next.fetch_add(1);
+      if (q >= small.size()) break;
+      run_one(small[q], s, gcap);
+    }
+  };
   std::vector<std::thread> pool;
-  for (int s = 0; s < S; ++s)
-    pool.emplace_back([&, s]() {
-      if (hipSetDevice(dev.device) != hipSuccess) return;
-      for (;;) {
-        const size_t q = next.fetch_add(1);
-        if (q >= small.size()) break;
-        run_one(small[q], s, gcap);
-      }
-    });
+  try {
+    for (int s = 1; s < S; ++s) pool.emplace_back(worker, s);
+  } catch (...) {
+    // fewer threads than asked for: the ones started and this thread share the queue
+  }
+  worker(0);  // the calling thread is worker 0 (its device is already current)
   for (auto& th : pool) th.join();
   for (int i : large) run_one(i, 0, 0);
   (void)hipEventDestroy(ready);
@@ -832,6 +837,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
     set_error(msg);
     return first_err;
   }
+  t_error.clear();
   return ICUR_OK;
 }
 

@@ -125,3 +125,16 @@ def test_batched_waits_for_the_callers_stream(icur):
     torch.cuda.synchronize()
     for i, A in enumerate(dev):
         _same(got[i], icur.run(A, specs[i]["tol"], 32, icur.GAUSSIAN, i))
+
+
+@pytest.mark.parametrize("workers", [1, 3, 16])
+def test_batched_worker_counts_agree(icur, workers):
+    # the concurrency only changes which worker runs a matrix, never its result
+    specs, mats = _batch(7, seed=4)
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    ref = icur.run_batched(dev, tols, 32, icur.GAUSSIAN, list(range(7)))
+    got = icur.run_batched(dev, tols, 32, icur.GAUSSIAN, list(range(7)), workers=workers)
+    for a, b in zip(got, ref):
+        assert a["status"] == b["status"]
+        _same(a, b)
