@@ -268,8 +268,9 @@ __global__ void csc_sketch_sign_lds_kernel(const int64_t* __restrict__ colptr, c
       }
       for (int t = 0; t < z; ++t) {
         const int r = static_cast<int>((rr0 >> (8 * t)) & 0xFFu);
-        double* slot = acc + r * kLdsStride + lane;
-        *slot = *slot + (((sb0 >> t) & 1u) ? -a0 : a0);
+        // an LDS add on a slot only this lane touches: in program order, no result wait
+        __hip_atomic_fetch_add(acc + r * kLdsStride + lane, ((sb0 >> t) & 1u) ? -a0 : a0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       p0 = p1;
       a0 = a1;
