@@ -64,11 +64,19 @@ struct DeviceCache {
   std::mutex mu;
   int device = 0;
   Buf buf[kNumSlots];
-  void* host_pinned = nullptr;  // small staging area for scalar read-backs
+  // pinned staging area: scalars (byte 0), status words (byte 256) and, from
+  // kStageOffset on, the results of a call (infos, I, J and U when they fit)
+  void* host_pinned = nullptr;
   std::vector<hipEvent_t> events;
-  hipStream_t stream = nullptr;  // worker stream of a batched slot (default priority)
+  hipEvent_t sync_event = nullptr;  // marks the end of the work a read-back waits for
+  bool spin = true;                 // wait for read-backs by polling (single calls)
+  hipStream_t stream = nullptr;     // worker stream of a batched slot (default priority)
   ~DeviceCache() {}
 };
+
+constexpr size_t kStageOffset = 4096;
+constexpr size_t kStageBytes = size_t(2) << 20;
+constexpr size_t kPinnedBytes = kStageOffset + kStageBytes;
 
 std::mutex g_cache_mu;
 std::map<std::pair<int, int>, std::unique_ptr<DeviceCache>> g_cache;
@@ -79,6 +87,7 @@ DeviceCache& cache_for(int dev, int slot) {
   if (!p) {
     p.reset(new DeviceCache());
     p->device = dev;
+    p->spin = slot == 0;
   }
   return *p;
 }
@@ -181,10 +190,29 @@ struct Timer {
   }
 };
 
+// Waits for the work queued on st.  A single call polls an event: the blocking wait of
+// the runtime wakes up tens of microseconds after the work ends, and a call makes a few
+// read-backs per iteration.  The batched workers, which share the host cores, block.
+int sync_stream(DeviceCache& dc, hipStream_t st) {
+  if (!dc.spin) {
+    ICUR_HIP(hipStreamSynchronize(st));
+    return ICUR_OK;
+  }
+  if (!dc.sync_event) ICUR_HIP(hipEventCreateWithFlags(&dc.sync_event, hipEventDisableTiming));
+  ICUR_HIP(hipEventRecord(dc.sync_event, st));
+  for (;;) {
+    const hipError_t e = hipEventQuery(dc.sync_event);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) ICUR_HIP(e);
+    __builtin_ia32_pause();
+  }
+  return ICUR_OK;
+}
+
 int read_scal(DeviceCache& dc, const Scal* dev, Scal* host, hipStream_t st) {
   Scal* pin = static_cast<Scal*>(dc.host_pinned);
   ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(Scal), hipMemcpyDeviceToHost, st));
-  ICUR_HIP(hipStreamSynchronize(st));
+  ICUR_TRY(sync_stream(dc, st));
   *host = *pin;
   return ICUR_OK;
 }
@@ -192,8 +220,21 @@ int read_scal(DeviceCache& dc, const Scal* dev, Scal* host, hipStream_t st) {
 int read_int(DeviceCache& dc, const int* dev, int* host, int count, hipStream_t st) {
   int* pin = reinterpret_cast<int*>(static_cast<char*>(dc.host_pinned) + 256);
   ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
-  ICUR_HIP(hipStreamSynchronize(st));
+  ICUR_TRY(sync_stream(dc, st));
   std::memcpy(host, pin, sizeof(int) * count);
+  return ICUR_OK;
+}
+
+// Status words and the scalars in one synchronisation.
+int read_int_scal(DeviceCache& dc, const int* dev, int* host, int count, const Scal* dscal, Scal* hscal,
+                  hipStream_t st) {
+  Scal* spin = static_cast<Scal*>(dc.host_pinned);
+  int* pin = reinterpret_cast<int*>(static_cast<char*>(dc.host_pinned) + 256);
+  ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+  ICUR_HIP(hipMemcpyAsync(spin, dscal, sizeof(Scal), hipMemcpyDeviceToHost, st));
+  ICUR_TRY(sync_stream(dc, st));
+  std::memcpy(host, pin, sizeof(int) * count);
+  *hscal = *spin;
   return ICUR_OK;
 }
 
@@ -201,7 +242,7 @@ int prepare_device(DeviceCache** out, int slot = 0) {
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
   DeviceCache& dc = cache_for(dev.device, slot);
-  if (!dc.host_pinned) ICUR_HIP(hipHostMalloc(&dc.host_pinned, 4096, hipHostMallocDefault));
+  if (!dc.host_pinned) ICUR_HIP(hipHostMalloc(&dc.host_pinned, kPinnedBytes, hipHostMallocDefault));
   *out = &dc;
   return ICUR_OK;
 }
@@ -506,24 +547,32 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pColMask), n, 0, st));
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pRowMask), m, 0, st));
   ICUR_TRY(tm.mark(&ev_s1));
-  Scal hs;
-  ICUR_TRY(read_scal(dc, dscal, &hs, st));
-  const double gnorm2 = hs.normsq_x0;
-  t_info.sketch_norm = std::sqrt(gnorm2);
   t_info.threshold = thr;
   t_info.split_terms = T;
-  t_info.ms_sketch = tm.ms(ev_s0, ev_s1);
-  t_info.ms_sketch_product = tm.ms(ev_p0, ev_p1);
-  if (!std::isfinite(gnorm2)) {
-    set_error("||G A||_F is not finite: A holds Inf or NaN");
-    return ICUR_ERR_NONFINITE;
-  }
-  if (gnorm2 == 0.0) {
-    *rank_out = 0;
-    *est_out = 0.0;
-    t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    return ICUR_OK;
-  }
+  // ||G A||_F^2 is read back with the first selection's status (one synchronisation
+  // less); the selection on a zero or non-finite sketch is harmless and discarded.
+  // Returns 1 when the call ends here (rank 0, or an error in *err).
+  Scal hs;
+  double gnorm2 = -1.0;
+  int norm_err = ICUR_OK;
+  auto take_norm = [&]() -> bool {
+    gnorm2 = hs.normsq_x0;
+    t_info.sketch_norm = std::sqrt(gnorm2);
+    t_info.ms_sketch = tm.ms(ev_s0, ev_s1);
+    t_info.ms_sketch_product = tm.ms(ev_p0, ev_p1);
+    if (!std::isfinite(gnorm2)) {
+      set_error("||G A||_F is not finite: A holds Inf or NaN");
+      norm_err = ICUR_ERR_NONFINITE;
+      return true;
+    }
+    if (gnorm2 == 0.0) {
+      *rank_out = 0;
+      *est_out = 0.0;
+      t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+      return true;
+    }
+    return false;
+  };
 
   // ---- the loop of Alg. 1, residual form
   int64_t r = 0;
@@ -552,7 +601,12 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     // column selection: LUPP on (S^col)^T
     ICUR_TRY(lupp_launch(S, true, c, n, n, static_cast<int>(s), static_cast<const uint8_t*>(pColMask), Jk, lw, st));
     int lst[2];
-    ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
+    if (gnorm2 < 0.0) {
+      ICUR_TRY(read_int_scal(dc, lw.status, lst, 2, dscal, &hs, st));
+      if (take_norm()) return norm_err;
+    } else {
+      ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
+    }
     if (lst[1]) {
       set_error("selection kernel: grid barrier did not complete");
       return ICUR_ERR_HIP;
@@ -640,6 +694,10 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     t_info.ms_residual += tm.ms(e1, e2) + tm.ms(e3, e4);
     tm.used = ev_s1 + 1;  // recycle the iteration's events
   }
+  if (gnorm2 < 0.0) {  // no iteration ran
+    ICUR_TRY(read_scal(dc, dscal, &hs, st));
+    if (take_norm()) return norm_err;
+  }
   if (status == ICUR_OK && rho > thr) status = ICUR_MAXRANK;
 
   // ---- the core U = A(I,J)^{-1} in FP64 from the exact cross entries: block LU in the
@@ -664,18 +722,40 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
                                  false, M, r, st));
     ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, nullptr, st, N1inv));
     ICUR_TRY(tm.mark(&ec1));
+    // the pivot-block flags and the results: through the pinned staging area in one
+    // synchronisation when they fit, else the flags first and the results directly
+    const size_t info_bytes = (static_cast<size_t>(nb) * sizeof(int) + 7) & ~size_t(7);
+    const size_t ij_bytes = static_cast<size_t>(r) * 8;
+    const size_t u_bytes = static_cast<size_t>(r) * r * 8;
+    char* stage = static_cast<char*>(dc.host_pinned) + kStageOffset;
+    const bool staged = info_bytes + 2 * ij_bytes + u_bytes <= kStageBytes;
     std::vector<int> hinfo(nb);
-    ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
-    ICUR_HIP(hipStreamSynchronize(st));
+    if (staged) {
+      ICUR_HIP(hipMemcpyAsync(stage, infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+      ICUR_HIP(hipMemcpyAsync(stage + info_bytes, pIall, ij_bytes, hipMemcpyDeviceToHost, st));
+      ICUR_HIP(hipMemcpyAsync(stage + info_bytes + ij_bytes, pJall, ij_bytes, hipMemcpyDeviceToHost, st));
+      ICUR_HIP(hipMemcpyAsync(stage + info_bytes + 2 * ij_bytes, U, u_bytes, hipMemcpyDeviceToHost, st));
+      ICUR_TRY(sync_stream(dc, st));
+      std::memcpy(hinfo.data(), stage, nb * sizeof(int));
+    } else {
+      ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+      ICUR_HIP(hipStreamSynchronize(st));
+    }
     for (int v : hinfo)
       if (v != 0) {
         set_error("core assembly: a pivot block of A(I,J) is exactly singular");
         return ICUR_ERR_HIP;
       }
     t_info.ms_core = tm.ms(ec0, ec1);
-    ICUR_HIP(hipMemcpyAsync(I_out, pIall, r * 8, hipMemcpyDeviceToHost, st));
-    ICUR_HIP(hipMemcpyAsync(J_out, pJall, r * 8, hipMemcpyDeviceToHost, st));
-    ICUR_HIP(hipMemcpyAsync(U_out, U, r * r * 8, hipMemcpyDeviceToHost, st));
+    if (staged) {
+      std::memcpy(I_out, stage + info_bytes, ij_bytes);
+      std::memcpy(J_out, stage + info_bytes + ij_bytes, ij_bytes);
+      std::memcpy(U_out, stage + info_bytes + 2 * ij_bytes, u_bytes);
+    } else {
+      ICUR_HIP(hipMemcpyAsync(I_out, pIall, r * 8, hipMemcpyDeviceToHost, st));
+      ICUR_HIP(hipMemcpyAsync(J_out, pJall, r * 8, hipMemcpyDeviceToHost, st));
+      ICUR_HIP(hipMemcpyAsync(U_out, U, r * r * 8, hipMemcpyDeviceToHost, st));
+    }
   }
   ICUR_HIP(hipStreamSynchronize(st));
   *rank_out = r;
@@ -868,6 +948,8 @@ int icur_release(void) {
     dc.host_pinned = nullptr;
     for (auto e : dc.events) (void)hipEventDestroy(e);
     dc.events.clear();
+    if (dc.sync_event) (void)hipEventDestroy(dc.sync_event);
+    dc.sync_event = nullptr;
   }
   g_cache.clear();
   release_blas_handles();

@@ -44,7 +44,9 @@ namespace {
 
 constexpr int kPW = 16;          // panel width
 constexpr int kPT = 256;         // threads per workgroup of the prep kernel (= 16 x 16)
-constexpr int kMaxSteps = 1024;  // LDS of the prep kernel holds t0 x 16 pivot-row entries
+constexpr int kRowsPrep = kPT / 2;  // candidate rows per prep workgroup (two threads per row)
+constexpr int kLC = 64;          // pivot-row multipliers staged in LDS per round (prep)
+constexpr int kMaxSteps = 1024;  // LDS of the prep kernel holds (t0 + 64) x 16 doubles
 constexpr int kMaxGroups = 256;  // panel-kernel workgroups (one per CU at most)
 constexpr unsigned kSpinLimit = 1u << 22;
 constexpr size_t kCtlBytes = 256;  // barrier (word 0), status words (byte 128), first pivot (byte 192)
@@ -123,7 +125,8 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
     return;  // fault, or no pivots left
   }
   const InT* X = static_cast<const InT*>(a.X);
-  extern __shared__ double Upan[];  // t0 x kPW: pivot rows 0..t0-1 at 16 columns
+  // t0 x kPW: pivot rows 0..t0-1 at the 16 columns, then kLC x kPW staged multipliers
+  extern __shared__ double Upan[];
   const int tid = threadIdx.x;
   const int N = a.N, t0 = a.t0, steps = a.steps;
   const bool cand = static_cast<int>(blockIdx.x) < a.ncand;
@@ -131,41 +134,43 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
 
   if (t0 > 0) {
     const int nb = t0 - kPW;  // the previous panel's pivots are steps nb .. t0-1
+    double* Lst = Upan + static_cast<size_t>(t0) * kPW;
     // (1) older pivot rows at these columns, extended by earlier launches
     for (int e = tid; e < nb * kPW; e += kPT) {
       const int k = e / kPW, jj = e % kPW;
       const int col = col0 + jj;
       Upan[e] = col < steps ? a.w.U[static_cast<int64_t>(k) * steps + col] : 0.0;
     }
-    __syncthreads();
     // (2) the previous panel's pivot rows at these columns.  Thread (jj, q) owns column
     // col0 + jj of the pivot row of step nb + q; the 16 rows of one column sit in one
-    // wave, so the recurrence among them runs on shuffles without block barriers.
+    // wave, so the recurrence among them runs on shuffles without block barriers.  The
+    // multipliers of the 16 pivot rows at the older steps are staged in LDS, kLC steps
+    // per round, all loads of a round in flight together.
     const int jj = tid >> 4, q = tid & 15;
     const int lane = tid & 63;
     const int col = col0 + jj;
     const int64_t p = a.w.piv[nb + q];
-    double acc = 0.0;
-    if (col < steps) {
-      acc = static_cast<double>(X[static_cast<int64_t>(col) * a.ldx + p]);
-      // nb is a multiple of 16: multipliers are fetched 16 steps ahead of their use
-      double lc[kPW], ln[kPW];
-      if (nb > 0) load_l16(a.w.L, N, 0, p, lc);
-      for (int kb = 0; kb < nb; kb += kPW) {
-        if (kb + kPW < nb) load_l16(a.w.L, N, kb + kPW, p, ln);
-#pragma unroll
-        for (int u = 0; u < kPW; ++u) {
-          const double prod = lc[u] * Upan[(kb + u) * kPW + jj];
-          acc = acc - prod;
-        }
-#pragma unroll
-        for (int u = 0; u < kPW; ++u) lc[u] = ln[u];
-      }
-    }
+    double acc = col < steps ? static_cast<double>(X[static_cast<int64_t>(col) * a.ldx + p]) : 0.0;
     double lq[kPW - 1];
 #pragma unroll
     for (int qq = 0; qq < kPW - 1; ++qq)
       lq[qq] = (qq < q && col < steps) ? a.w.L[static_cast<int64_t>(nb + qq) * N + p] : 0.0;
+    for (int kb = 0; kb < nb; kb += kLC) {
+#pragma unroll
+      for (int u = 0; u < kLC / kPW; ++u) {
+        const int k = kb + jj + kPW * u;  // thread (jj, q) stages its own pivot row
+        Lst[(jj + kPW * u) * kPW + q] = k < nb ? a.w.L[static_cast<int64_t>(k) * N + p] : 0.0;
+      }
+      __syncthreads();  // also orders (1) before the first round
+      const int kn = min(kLC, nb - kb);
+      if (col < steps) {
+        for (int kk = 0; kk < kn; ++kk) {
+          const double prod = Lst[kk * kPW + q] * Upan[(kb + kk) * kPW + jj];
+          acc = acc - prod;
+        }
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int qq = 0; qq < kPW - 1; ++qq) {
       const double u = __shfl(acc, (lane & 48) | qq, 64);  // row nb + qq, final by now
@@ -180,35 +185,44 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
   }
   if (!cand) return;
 
-  // (3) candidate rows: the panel entries with all t0 previous updates, in step order
-  const int i = static_cast<int>(blockIdx.x) * kPT + tid;
+  // (3) candidate rows: the panel entries with all t0 previous updates, in step order.
+  // Two threads per row, eight panel columns each; multipliers are fetched two blocks of
+  // 16 steps ahead of their use (t0 is a multiple of 16).
+  constexpr int kHalf = kPW / 2;
+  const int h = tid / kRowsPrep;
+  const int i = static_cast<int>(blockIdx.x) * kRowsPrep + tid % kRowsPrep;
   if (i >= N) return;
-  if (t0 == 0) a.w.chosen[i] = 0;
+  if (t0 == 0 && h == 0) a.w.chosen[i] = 0;
   if ((a.excl && a.excl[i]) || (t0 > 0 && a.w.chosen[i])) return;
   const int pw = min(kPW, steps - t0);
-  double x[kPW];
+  double x[kHalf];
 #pragma unroll
-  for (int jj = 0; jj < kPW; ++jj)
-    x[jj] = jj < pw ? static_cast<double>(X[static_cast<int64_t>(t0 + jj) * a.ldx + i]) : 0.0;
-  // t0 is a multiple of 16: multipliers are fetched 16 steps ahead of their use
-  double lc[kPW], ln[kPW];
-  if (t0 > 0) load_l16(a.w.L, N, 0, i, lc);
+  for (int j2 = 0; j2 < kHalf; ++j2) {
+    const int jj = kHalf * h + j2;
+    x[j2] = jj < pw ? static_cast<double>(X[static_cast<int64_t>(t0 + jj) * a.ldx + i]) : 0.0;
+  }
+  double l0[kPW], l1[kPW], l2[kPW];
+  if (t0 > 0) load_l16(a.w.L, N, 0, i, l0);
+  if (t0 > kPW) load_l16(a.w.L, N, kPW, i, l1);
   for (int kb = 0; kb < t0; kb += kPW) {
-    if (kb + kPW < t0) load_l16(a.w.L, N, kb + kPW, i, ln);
+    if (kb + 2 * kPW < t0) load_l16(a.w.L, N, kb + 2 * kPW, i, l2);
+    const double* up = Upan + kb * kPW + kHalf * h;
 #pragma unroll
     for (int u = 0; u < kPW; ++u) {
-      const double* up = Upan + (kb + u) * kPW;
 #pragma unroll
-      for (int jj = 0; jj < kPW; ++jj) {
-        const double prod = lc[u] * up[jj];
-        x[jj] = x[jj] - prod;
+      for (int j2 = 0; j2 < kHalf; ++j2) {
+        const double prod = l0[u] * up[u * kPW + j2];
+        x[j2] = x[j2] - prod;
       }
     }
 #pragma unroll
-    for (int u = 0; u < kPW; ++u) lc[u] = ln[u];
+    for (int u = 0; u < kPW; ++u) {
+      l0[u] = l1[u];
+      l1[u] = l2[u];
+    }
   }
 #pragma unroll
-  for (int jj = 0; jj < kPW; ++jj) a.w.P[static_cast<int64_t>(jj) * N + i] = x[jj];
+  for (int j2 = 0; j2 < kHalf; ++j2) a.w.P[static_cast<int64_t>(kHalf * h + j2) * N + i] = x[j2];
 }
 
 // ---------------------------------------------------------------------------------
@@ -537,7 +551,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   pa.ldx = ldx;
   pa.N = static_cast<int>(N);
   pa.steps = steps;
-  pa.ncand = static_cast<int>((N + kPT - 1) / kPT);
+  pa.ncand = static_cast<int>((N + kRowsPrep - 1) / kRowsPrep);
   pa.excl = excluded;
   pa.w = wk;
   PanelArgs qa;
@@ -549,7 +563,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
 
   const void* prep = x64 ? reinterpret_cast<const void*>(lupp_prep<double>)
                          : reinterpret_cast<const void*>(lupp_prep<float>);
-  const size_t max_lds = static_cast<size_t>(steps) * kPW * sizeof(double);
+  const size_t max_lds = static_cast<size_t>(steps + kLC) * kPW * sizeof(double);
   if (max_lds > 64 * 1024)
     ICUR_HIP(hipFuncSetAttribute(prep, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(max_lds)));
   const void* panel = reinterpret_cast<const void*>(kShape[sh].fn);
@@ -557,7 +571,7 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
     pa.t0 = t0;
     qa.t0 = t0;
     const int extra = t0 > 0 ? std::max(0, (steps - t0 + kPW - 1) / kPW - 1) : 0;
-    const size_t lds = static_cast<size_t>(t0) * kPW * sizeof(double);
+    const size_t lds = t0 > 0 ? static_cast<size_t>(t0 + kLC) * kPW * sizeof(double) : 0;
     void* pparams[] = {&pa};
     ICUR_HIP(hipLaunchKernel(prep, dim3(pa.ncand + extra), dim3(kPT), pparams, lds, st));
     void* qparams[] = {&qa};

@@ -154,8 +154,16 @@ def test_degenerate_and_edge_cases(icur):
     with pytest.raises(icur.IcurError) as e:
         icur.run(bad, 1e-3, 8)
     assert e.value.status == icur.ERR_NONFINITE
+    # a tolerance the empty approximation already meets (rho starts at 1): no iteration,
+    # and the sketch norm is still checked
+    with pytest.raises(icur.IcurError) as e:
+        icur.run(bad, 1.0, 8)
+    assert e.value.status == icur.ERR_NONFINITE
     # max_rank cap
     A32, _ = W.to_f32(W.rbf(400, 300, 1, h=0.05))
+    out = icur.run(torch.from_numpy(A32).cuda(), 1.0, 8)
+    assert out["rank"] == 0 and out["status"] == "ok" and out["info"]["iterations"] == 0
+    assert out["info"]["sketch_norm"] > 0.0
     out = icur.run(torch.from_numpy(A32).cuda(), 1e-12, 7, max_rank=20)
     assert out["status"] == "maxrank" and out["rank"] == 20
     # exhaustion of a full-rank matrix with a shortened last block (23 = 4*5 + 3)
