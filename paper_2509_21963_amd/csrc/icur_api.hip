@@ -67,6 +67,7 @@ struct DeviceCache {
   // pinned staging area: scalars (byte 0), status words (byte 256) and, from
   // kStageOffset on, the results of a call (infos, I, J and U when they fit)
   void* host_pinned = nullptr;
+  void* host_pinned_dev = nullptr;  // its device address (read-backs are kernel stores)
   std::vector<hipEvent_t> events;
   hipEvent_t sync_event = nullptr;  // marks the end of the work a read-back waits for
   bool spin = true;                 // wait for read-backs by polling (single calls)
@@ -150,12 +151,26 @@ struct Scal {
 };
 
 // Device-event timing of the phases (icur_info).  When off (the batched workers), every
-// call is a no-op and every duration reads 0, saving nine runtime calls per iteration.
+// call is a no-op and every duration reads 0.  Durations are read once, after the call's
+// last wait (add, then flush), so no timing call sits between a read-back and the next
+// launch.
 struct Timer {
   DeviceCache* dc;
   hipStream_t st;
   bool on = true;
   size_t used = 0;
+  struct Span {
+    size_t a, b;
+    double* acc;
+  };
+  std::vector<Span> spans;
+  void add(size_t a, size_t b, double* acc) {
+    if (on) spans.push_back(Span{a, b, acc});
+  }
+  void flush() {
+    for (const Span& sp : spans) *sp.acc += ms(sp.a, sp.b);
+    spans.clear();
+  }
   // An event slot that the caller records itself (or that mark() records now).
   int reserve(size_t* idx) {
     if (!on) {
@@ -209,18 +224,35 @@ int sync_stream(DeviceCache& dc, hipStream_t st) {
   return ICUR_OK;
 }
 
+// Device segments into the pinned staging area, then one wait: by kernel stores into the
+// host-mapped buffer (one launch), else by copies.
+int read_back(DeviceCache& dc, const HostSegs& segs, hipStream_t st) {
+  if (dc.host_pinned_dev) {
+    ICUR_TRY(launch_to_host(segs, dc.host_pinned_dev, st));
+  } else {
+    for (int i = 0; i < segs.n; ++i)
+      ICUR_HIP(hipMemcpyAsync(static_cast<char*>(dc.host_pinned) + segs.seg[i].dst_off, segs.seg[i].src,
+                              static_cast<size_t>(segs.seg[i].bytes), hipMemcpyDeviceToHost, st));
+  }
+  return sync_stream(dc, st);
+}
+
 int read_scal(DeviceCache& dc, const Scal* dev, Scal* host, hipStream_t st) {
   Scal* pin = static_cast<Scal*>(dc.host_pinned);
-  ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(Scal), hipMemcpyDeviceToHost, st));
-  ICUR_TRY(sync_stream(dc, st));
+  HostSegs h{};
+  h.seg[0] = HostSeg{dev, static_cast<int64_t>(sizeof(Scal)), 0};
+  h.n = 1;
+  ICUR_TRY(read_back(dc, h, st));
   *host = *pin;
   return ICUR_OK;
 }
 
 int read_int(DeviceCache& dc, const int* dev, int* host, int count, hipStream_t st) {
   int* pin = reinterpret_cast<int*>(static_cast<char*>(dc.host_pinned) + 256);
-  ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
-  ICUR_TRY(sync_stream(dc, st));
+  HostSegs h{};
+  h.seg[0] = HostSeg{dev, static_cast<int64_t>(sizeof(int)) * count, 256};
+  h.n = 1;
+  ICUR_TRY(read_back(dc, h, st));
   std::memcpy(host, pin, sizeof(int) * count);
   return ICUR_OK;
 }
@@ -230,9 +262,11 @@ int read_int_scal(DeviceCache& dc, const int* dev, int* host, int count, const S
                   hipStream_t st) {
   Scal* spin = static_cast<Scal*>(dc.host_pinned);
   int* pin = reinterpret_cast<int*>(static_cast<char*>(dc.host_pinned) + 256);
-  ICUR_HIP(hipMemcpyAsync(pin, dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
-  ICUR_HIP(hipMemcpyAsync(spin, dscal, sizeof(Scal), hipMemcpyDeviceToHost, st));
-  ICUR_TRY(sync_stream(dc, st));
+  HostSegs h{};
+  h.seg[0] = HostSeg{dev, static_cast<int64_t>(sizeof(int)) * count, 256};
+  h.seg[1] = HostSeg{dscal, static_cast<int64_t>(sizeof(Scal)), 0};
+  h.n = 2;
+  ICUR_TRY(read_back(dc, h, st));
   std::memcpy(host, pin, sizeof(int) * count);
   *hscal = *spin;
   return ICUR_OK;
@@ -242,7 +276,16 @@ int prepare_device(DeviceCache** out, int slot = 0) {
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
   DeviceCache& dc = cache_for(dev.device, slot);
-  if (!dc.host_pinned) ICUR_HIP(hipHostMalloc(&dc.host_pinned, kPinnedBytes, hipHostMallocDefault));
+  if (!dc.host_pinned) {
+    ICUR_HIP(hipHostMalloc(&dc.host_pinned, kPinnedBytes, hipHostMallocDefault));
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, dc.host_pinned, 0) == hipSuccess) {
+      dc.host_pinned_dev = d;
+    } else {
+      (void)hipGetLastError();  // not mapped: read-backs use copies
+      dc.host_pinned_dev = nullptr;
+    }
+  }
   *out = &dc;
   return ICUR_OK;
 }
@@ -547,6 +590,8 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pColMask), n, 0, st));
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pRowMask), m, 0, st));
   ICUR_TRY(tm.mark(&ev_s1));
+  tm.add(ev_s0, ev_s1, &t_info.ms_sketch);
+  tm.add(ev_p0, ev_p1, &t_info.ms_sketch_product);
   t_info.threshold = thr;
   t_info.split_terms = T;
   // ||G A||_F^2 is read back with the first selection's status (one synchronisation
@@ -558,8 +603,6 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   auto take_norm = [&]() -> bool {
     gnorm2 = hs.normsq_x0;
     t_info.sketch_norm = std::sqrt(gnorm2);
-    t_info.ms_sketch = tm.ms(ev_s0, ev_s1);
-    t_info.ms_sketch_product = tm.ms(ev_p0, ev_p1);
     if (!std::isfinite(gnorm2)) {
       set_error("||G A||_F is not finite: A holds Inf or NaN");
       norm_err = ICUR_ERR_NONFINITE;
@@ -568,6 +611,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     if (gnorm2 == 0.0) {
       *rank_out = 0;
       *est_out = 0.0;
+      tm.flush();
       t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
       return true;
     }
@@ -588,6 +632,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     return res64 ? launch_gather_f64(static_cast<const double*>(src), lds, nullptr, rk, cols, ck, trans, dst, ldd, st)
                  : launch_gather_f64(static_cast<const float*>(src), lds, nullptr, rk, cols, ck, trans, dst, ldd, st);
   };
+  size_t iter_start = ev_s1;
   while (rho > thr && r < rmax) {
     const int64_t s = std::min(b, rmax - r);
     ICUR_TRY(grow_to(r + s));
@@ -595,11 +640,12 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     void* Ur = pUr;
     void* Sr = pSr;
     double* W64 = static_cast<double*>(pW64);
-    size_t e0, e1, e2, e3, e4;
+    // e0: the previous iteration's end (nothing is queued in between)
+    size_t e0 = iter_start, e1, e2, e3, e4;
     int parts = 0;
-    ICUR_TRY(tm.mark(&e0));
     // column selection: LUPP on (S^col)^T
     ICUR_TRY(lupp_launch(S, true, c, n, n, static_cast<int>(s), static_cast<const uint8_t*>(pColMask), Jk, lw, st));
+    ICUR_TRY(tm.mark(&e1));
     int lst[2];
     if (gnorm2 < 0.0) {
       ICUR_TRY(read_int_scal(dc, lw.status, lst, 2, dscal, &hs, st));
@@ -612,7 +658,6 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
       return ICUR_ERR_HIP;
     }
     const int64_t nJ = lst[0];
-    ICUR_TRY(tm.mark(&e1));
     if (nJ == 0) {
       status = ICUR_STALLED;
       break;
@@ -638,13 +683,13 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     // row selection: LUPP on S^row
     ICUR_TRY(lupp_launch(Lk, res64, nJ, m, m, static_cast<int>(nJ), static_cast<const uint8_t*>(pRowMask), Ik, lw, st,
                          res64 ? kRowCutFp64 : kRowCutFp32));
+    ICUR_TRY(tm.mark(&e3));
     ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
     if (lst[1]) {
       set_error("selection kernel: grid barrier did not complete");
       return ICUR_ERR_HIP;
     }
     const int64_t nI = lst[0];
-    ICUR_TRY(tm.mark(&e3));
     if (nI == 0) {
       status = ICUR_STALLED;
       break;
@@ -690,9 +735,11 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     const int it = t_info.iterations++;
     if (it < 512) t_info.rho[it] = rho;
     t_info.n_rho = std::min(t_info.iterations, 512);
-    t_info.ms_select += tm.ms(e0, e1) + tm.ms(e2, e3);
-    t_info.ms_residual += tm.ms(e1, e2) + tm.ms(e3, e4);
-    tm.used = ev_s1 + 1;  // recycle the iteration's events
+    tm.add(e0, e1, &t_info.ms_select);
+    tm.add(e2, e3, &t_info.ms_select);
+    tm.add(e1, e2, &t_info.ms_residual);
+    tm.add(e3, e4, &t_info.ms_residual);
+    iter_start = e4;
   }
   if (gnorm2 < 0.0) {  // no iteration ran
     ICUR_TRY(read_scal(dc, dscal, &hs, st));
@@ -704,8 +751,9 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   //      selection order (its diagonal blocks are the pivot blocks N_k of the row
   //      selections), then block triangular solves on the identity
   if (r > 0) {
-    size_t ec0, ec1;
-    ICUR_TRY(tm.mark(&ec0));
+    // the core starts where the last iteration ended, unless the loop stopped part-way
+    size_t ec0 = iter_start, ec1;
+    if (status == ICUR_STALLED) ICUR_TRY(tm.mark(&ec0));
     void *pU, *pM, *pCore;
     const int64_t nb = static_cast<int64_t>(blocks.size());
     ICUR_TRY(ensure(dc, kU, static_cast<size_t>(r) * r * 8, &pU));
@@ -731,11 +779,14 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     const bool staged = info_bytes + 2 * ij_bytes + u_bytes <= kStageBytes;
     std::vector<int> hinfo(nb);
     if (staged) {
-      ICUR_HIP(hipMemcpyAsync(stage, infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
-      ICUR_HIP(hipMemcpyAsync(stage + info_bytes, pIall, ij_bytes, hipMemcpyDeviceToHost, st));
-      ICUR_HIP(hipMemcpyAsync(stage + info_bytes + ij_bytes, pJall, ij_bytes, hipMemcpyDeviceToHost, st));
-      ICUR_HIP(hipMemcpyAsync(stage + info_bytes + 2 * ij_bytes, U, u_bytes, hipMemcpyDeviceToHost, st));
-      ICUR_TRY(sync_stream(dc, st));
+      HostSegs h{};
+      const int64_t so = static_cast<int64_t>(kStageOffset);
+      h.seg[0] = HostSeg{infos, static_cast<int64_t>(nb * sizeof(int)), so};
+      h.seg[1] = HostSeg{pIall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes)};
+      h.seg[2] = HostSeg{pJall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes + ij_bytes)};
+      h.seg[3] = HostSeg{U, static_cast<int64_t>(u_bytes), so + static_cast<int64_t>(info_bytes + 2 * ij_bytes)};
+      h.n = 4;
+      ICUR_TRY(read_back(dc, h, st));
       std::memcpy(hinfo.data(), stage, nb * sizeof(int));
     } else {
       ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -746,7 +797,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
         set_error("core assembly: a pivot block of A(I,J) is exactly singular");
         return ICUR_ERR_HIP;
       }
-    t_info.ms_core = tm.ms(ec0, ec1);
+    tm.add(ec0, ec1, &t_info.ms_core);
     if (staged) {
       std::memcpy(I_out, stage + info_bytes, ij_bytes);
       std::memcpy(J_out, stage + info_bytes + ij_bytes, ij_bytes);
@@ -758,6 +809,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     }
   }
   ICUR_HIP(hipStreamSynchronize(st));
+  tm.flush();
   *rank_out = r;
   *est_out = rho;
   t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -946,6 +998,7 @@ int icur_release(void) {
     }
     if (dc.host_pinned) ICUR_HIP(hipHostFree(dc.host_pinned));
     dc.host_pinned = nullptr;
+    dc.host_pinned_dev = nullptr;
     for (auto e : dc.events) (void)hipEventDestroy(e);
     dc.events.clear();
     if (dc.sync_event) (void)hipEventDestroy(dc.sync_event);

@@ -6,6 +6,8 @@
 // column of a row-major A is a strided gather: each element costs one cache line, which
 // is inherent to the layout; the writes are coalesced.  Rows of A are copied with 16-byte
 // loads when alignment allows.
+#include <algorithm>
+
 #include "icur_internal.h"
 
 namespace icur {
@@ -189,6 +191,34 @@ int launch_commit_block(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, c
   if (k <= 0) return ICUR_OK;
   hipLaunchKernelGGL(commit_block_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st, colmask,
                      rowmask, Jk, Ik, k, Jall, Iall);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+namespace {
+// The read-backs of a call (status words, scalars, results) as stores into host-mapped
+// pinned memory, all segments in one launch; sizes and offsets are multiples of 4 bytes.
+__global__ void to_host_kernel(const HostSegs segs, unsigned* __restrict__ dst) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int s = 0; s < segs.n; ++s) {
+    const unsigned* src = static_cast<const unsigned*>(segs.seg[s].src);
+    unsigned* d = dst + segs.seg[s].dst_off / 4;
+    const int64_t words = segs.seg[s].bytes / 4;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < words; e += stride)
+      d[e] = src[e];
+  }
+}
+}  // namespace
+
+int launch_to_host(const HostSegs& segs, void* host_dev, hipStream_t st) {
+  int64_t words = 0;
+  for (int s = 0; s < segs.n; ++s) {
+    if (segs.seg[s].bytes % 4 != 0 || segs.seg[s].dst_off % 4 != 0) return arg_error("to_host: unaligned segment");
+    words = std::max<int64_t>(words, segs.seg[s].bytes / 4);
+  }
+  if (segs.n < 1 || segs.n > kMaxHostSegs || words == 0) return arg_error("to_host: bad segment list");
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((words + 255) / 256, 256));
+  hipLaunchKernelGGL(to_host_kernel, dim3(blocks), dim3(256), 0, st, segs, static_cast<unsigned*>(host_dev));
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
 }

@@ -185,6 +185,19 @@ int launch_gather_f64(const double* src, int64_t lds, const int64_t* rows, int64
                       const int64_t* cols, int64_t ck, bool trans, double* dst, int64_t ldd,
                       hipStream_t st);
 // colmask[Jk[t]] = rowmask[Ik[t]] = 1 and Jall[t] = Jk[t], Iall[t] = Ik[t] for t < k.
+// Device segments copied into host-mapped pinned memory (host_dev: its device address).
+constexpr int kMaxHostSegs = 4;
+struct HostSeg {
+  const void* src;
+  int64_t bytes;
+  int64_t dst_off;
+};
+struct HostSegs {
+  HostSeg seg[kMaxHostSegs];
+  int n;
+};
+int launch_to_host(const HostSegs& segs, void* host_dev, hipStream_t st);
+
 int launch_commit_block(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, const int64_t* Ik, int64_t k,
                         int64_t* Jall, int64_t* Iall, hipStream_t st);
 int launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
