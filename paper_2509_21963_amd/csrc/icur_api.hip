@@ -68,6 +68,7 @@ struct DeviceCache {
   // kStageOffset on, the results of a call (infos, I, J and U when they fit)
   void* host_pinned = nullptr;
   void* host_pinned_dev = nullptr;  // its device address (read-backs are kernel stores)
+  unsigned flag_seq = 0;            // last value published in the read-back flag
   std::vector<hipEvent_t> events;
   hipEvent_t sync_event = nullptr;  // marks the end of the work a read-back waits for
   bool spin = true;                 // wait for read-backs by polling (single calls)
@@ -75,6 +76,7 @@ struct DeviceCache {
   ~DeviceCache() {}
 };
 
+constexpr size_t kFlagOffset = 1024;  // read-back completion flag in the pinned area
 constexpr size_t kStageOffset = 4096;
 constexpr size_t kStageBytes = size_t(2) << 20;
 constexpr size_t kPinnedBytes = kStageOffset + kStageBytes;
@@ -224,9 +226,39 @@ int sync_stream(DeviceCache& dc, hipStream_t st) {
   return ICUR_OK;
 }
 
-// Device segments into the pinned staging area, then one wait: by kernel stores into the
-// host-mapped buffer (one launch), else by copies.
-int read_back(DeviceCache& dc, const HostSegs& segs, hipStream_t st) {
+// Polls the read-back flag until the kernel has published seq; every 1024 polls the
+// stream is queried, so a failed or drained stream ends the wait.
+int wait_flag(DeviceCache& dc, unsigned seq, hipStream_t st) {
+  volatile unsigned* f = reinterpret_cast<volatile unsigned*>(static_cast<char*>(dc.host_pinned) + kFlagOffset);
+  for (uint64_t polls = 1;; ++polls) {
+    if (*f == seq) break;
+    if ((polls & 1023u) == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        if (*f == seq) break;
+        set_error("read-back: the completion flag was not seen after the stream drained");
+        return ICUR_ERR_HIP;
+      }
+      if (e != hipErrorNotReady) ICUR_HIP(e);
+    }
+    __builtin_ia32_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return ICUR_OK;
+}
+
+// Device segments into the pinned staging area, then one wait.  Small read-backs of a
+// single call are kernel stores into the host-mapped buffer followed by a flag the host
+// polls; the results at the end of a call use a multi-workgroup copy and a stream wait;
+// without a device address for the buffer, copies.
+int read_back(DeviceCache& dc, const HostSegs& segs, hipStream_t st, bool small = true) {
+  if (dc.host_pinned_dev && dc.spin && small) {
+    const unsigned seq = ++dc.flag_seq;
+    ICUR_TRY(launch_to_host_flag(segs, dc.host_pinned_dev,
+                                 reinterpret_cast<unsigned*>(static_cast<char*>(dc.host_pinned_dev) + kFlagOffset), seq,
+                                 st));
+    return wait_flag(dc, seq, st);
+  }
   if (dc.host_pinned_dev) {
     ICUR_TRY(launch_to_host(segs, dc.host_pinned_dev, st));
   } else {
@@ -278,6 +310,8 @@ int prepare_device(DeviceCache** out, int slot = 0) {
   DeviceCache& dc = cache_for(dev.device, slot);
   if (!dc.host_pinned) {
     ICUR_HIP(hipHostMalloc(&dc.host_pinned, kPinnedBytes, hipHostMallocDefault));
+    std::memset(dc.host_pinned, 0, kStageOffset);
+    dc.flag_seq = 0;
     void* d = nullptr;
     if (hipHostGetDevicePointer(&d, dc.host_pinned, 0) == hipSuccess) {
       dc.host_pinned_dev = d;
@@ -786,7 +820,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
       h.seg[2] = HostSeg{pJall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes + ij_bytes)};
       h.seg[3] = HostSeg{U, static_cast<int64_t>(u_bytes), so + static_cast<int64_t>(info_bytes + 2 * ij_bytes)};
       h.n = 4;
-      ICUR_TRY(read_back(dc, h, st));
+      ICUR_TRY(read_back(dc, h, st, false));
       std::memcpy(hinfo.data(), stage, nb * sizeof(int));
     } else {
       ICUR_HIP(hipMemcpyAsync(hinfo.data(), infos, nb * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -208,7 +208,31 @@ __global__ void to_host_kernel(const HostSegs segs, unsigned* __restrict__ dst) 
       d[e] = src[e];
   }
 }
+// Small read-backs: one workgroup copies, then publishes `seq` in a host-visible flag
+// after its stores, so the host can poll the flag instead of waiting for the stream.
+__global__ __launch_bounds__(256) void to_host_flag_kernel(const HostSegs segs, unsigned* __restrict__ dst,
+                                                          unsigned* flag, unsigned seq) {
+  for (int s = 0; s < segs.n; ++s) {
+    const unsigned* src = static_cast<const unsigned*>(segs.seg[s].src);
+    unsigned* d = dst + segs.seg[s].dst_off / 4;
+    const int64_t words = segs.seg[s].bytes / 4;
+    for (int64_t e = threadIdx.x; e < words; e += blockDim.x) d[e] = src[e];
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 }  // namespace
+
+int launch_to_host_flag(const HostSegs& segs, void* host_dev, unsigned* flag_dev, unsigned seq, hipStream_t st) {
+  if (segs.n < 1 || segs.n > kMaxHostSegs) return arg_error("to_host: bad segment list");
+  for (int s = 0; s < segs.n; ++s)
+    if (segs.seg[s].bytes % 4 != 0 || segs.seg[s].dst_off % 4 != 0) return arg_error("to_host: unaligned segment");
+  hipLaunchKernelGGL(to_host_flag_kernel, dim3(1), dim3(256), 0, st, segs, static_cast<unsigned*>(host_dev), flag_dev,
+                     seq);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
 
 int launch_to_host(const HostSegs& segs, void* host_dev, hipStream_t st) {
   int64_t words = 0;

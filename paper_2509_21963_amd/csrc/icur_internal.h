@@ -197,6 +197,8 @@ struct HostSegs {
   int n;
 };
 int launch_to_host(const HostSegs& segs, void* host_dev, hipStream_t st);
+// One workgroup; writes seq to *flag_dev (host-mapped) after the segments are visible.
+int launch_to_host_flag(const HostSegs& segs, void* host_dev, unsigned* flag_dev, unsigned seq, hipStream_t st);
 
 int launch_commit_block(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, const int64_t* Ik, int64_t k,
                         int64_t* Jall, int64_t* Iall, hipStream_t st);
