@@ -334,9 +334,13 @@ constexpr double kSketchChunkFlushBelow = 1e-4;
 // exact rank of A), and inverting that noise in N_k would wreck the residual recurrence.
 // What is dropped is at most this fraction of the block's largest residual entry.
 constexpr double kRowCutFp64 = 0x1.0p-40;
-// FP64 residual products at least this deep and this tall go to the library GEMM
-// (measured: faster for blocks of 128 rows at depth >= 256, slower for blocks of 32).
+// FP64 residual products at least this tall, and this deep, go to the library GEMM
+// (measured: faster for blocks of 128 rows at depth >= 256, slower for blocks of 32; on
+// rows of 16384 or more columns also from depth 64: 47 against 60-90 us for the two
+// 110 x 100 x 40000 products of an iteration).
 constexpr int64_t kLibraryGemmMinK = 256;
+constexpr int64_t kLibraryGemmMinKWide = 64;
+constexpr int64_t kLibraryGemmWideN = 16384;
 constexpr int64_t kLibraryGemmMinM = 96;
 constexpr double kRowCutFp32 = 0x1.0p-16;
 
@@ -532,7 +536,8 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
                      int* parts) -> int {
     // res64: W and B are FP64 and OUT is FP64 (FP64 matrix cores); else W is split into
     // BF16 pieces (or rounded to FP32) and B is FP32.
-    if (res64 && K >= kLibraryGemmMinK && M >= kLibraryGemmMinM &&
+    if (res64 && M >= kLibraryGemmMinM &&
+        (K >= kLibraryGemmMinK || (K >= kLibraryGemmMinKWide && N >= kLibraryGemmWideN)) &&
         ((X == OUT && subtract) || (X == nullptr && !subtract))) {
       // deep products in place (OUT -= W B) or plain: a library FP64 GEMM, then the
       // norm partials of OUT in a pass of their own when asked for; shallow ones stay
