@@ -759,11 +759,29 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     // column residual update S^col <- S^col - S^col(:,J_k) Ur_k, and its norm
     ICUR_TRY(launch_gather_f64(S, n, nullptr, c, Jk, nI, false, W64, nI, st));
     ICUR_TRY(product(W64, c, nI, S, n, Urk, n, n, true, S, n, true, true, &parts));
-    ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_s, st));
-    ICUR_TRY(launch_commit_block(static_cast<uint8_t*>(pColMask), static_cast<uint8_t*>(pRowMask), Jk, Ik, nI,
-                                 static_cast<int64_t*>(pJall) + r, static_cast<int64_t*>(pIall) + r, st));
-    ICUR_TRY(tm.mark(&e4));
-    ICUR_TRY(read_scal(dc, dscal, &hs, st));
+    if (dc.host_pinned_dev) {
+      // norm, commit and the scalar read-back in one launch
+      const bool flag = dc.spin;
+      const unsigned seq = flag ? ++dc.flag_seq : 0u;
+      unsigned* flag_dev =
+          flag ? reinterpret_cast<unsigned*>(static_cast<char*>(dc.host_pinned_dev) + kFlagOffset) : nullptr;
+      ICUR_TRY(launch_iteration_end(dnorm, parts, &dscal->normsq_s, static_cast<uint8_t*>(pColMask),
+                                    static_cast<uint8_t*>(pRowMask), Jk, Ik, nI, static_cast<int64_t*>(pJall) + r,
+                                    static_cast<int64_t*>(pIall) + r, dscal, static_cast<int64_t>(sizeof(Scal)),
+                                    dc.host_pinned_dev, flag_dev, seq, st));
+      ICUR_TRY(tm.mark(&e4));
+      if (flag)
+        ICUR_TRY(wait_flag(dc, seq, st));
+      else
+        ICUR_TRY(sync_stream(dc, st));
+      hs = *static_cast<const Scal*>(dc.host_pinned);
+    } else {
+      ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_s, st));
+      ICUR_TRY(launch_commit_block(static_cast<uint8_t*>(pColMask), static_cast<uint8_t*>(pRowMask), Jk, Ik, nI,
+                                   static_cast<int64_t*>(pJall) + r, static_cast<int64_t*>(pIall) + r, st));
+      ICUR_TRY(tm.mark(&e4));
+      ICUR_TRY(read_scal(dc, dscal, &hs, st));
+    }
     if (hs.info != 0) {
       set_error("the residual block N_k = S(I_k, J_k) is exactly singular");
       return ICUR_ERR_HIP;

@@ -222,7 +222,55 @@ __global__ __launch_bounds__(256) void to_host_flag_kernel(const HostSegs segs, 
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+// End of an iteration in one workgroup: the column-residual norm from its partials (the
+// fixed order of the plain partial reduction: thread t sums partials t, t + 256, ..., then
+// a butterfly within each wave and the four waves in order), the commit of the block's
+// indices, and the scalar record copied to host-mapped memory with an optional flag.
+__global__ __launch_bounds__(256) void iteration_end_kernel(const double* partials, int nparts, double* norm_out,
+                                                            uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk,
+                                                            const int64_t* Ik, int64_t k, int64_t* Jall,
+                                                            int64_t* Iall, const unsigned* rec, int rec_words,
+                                                            unsigned* host_dst, unsigned* flag, unsigned seq) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double v = 0.0;
+  for (int i = tid; i < nparts; i += blockDim.x) v += partials[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  for (int64_t t = tid; t < k; t += blockDim.x) {
+    const int64_t j = Jk[t], i = Ik[t];
+    colmask[j] = 1;
+    rowmask[i] = 1;
+    Jall[t] = j;
+    Iall[t] = i;
+  }
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) sum += red[w];
+    *norm_out = sum;
+    // the record holds norm_out: thread 0 reads its own store back
+    for (int e = 0; e < rec_words; ++e) host_dst[e] = rec[e];
+    if (flag) {
+      __threadfence_system();
+      __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
 }  // namespace
+
+int launch_iteration_end(const double* partials, int nparts, double* norm_out, uint8_t* colmask, uint8_t* rowmask,
+                         const int64_t* Jk, const int64_t* Ik, int64_t k, int64_t* Jall, int64_t* Iall,
+                         const void* rec, int64_t rec_bytes, void* host_dev, unsigned* flag_dev, unsigned seq,
+                         hipStream_t st) {
+  if (rec_bytes % 4 != 0 || rec_bytes > 4096) return arg_error("iteration end: bad record size");
+  if (k < 0 || nparts < 0) return arg_error("iteration end: negative size");
+  hipLaunchKernelGGL(iteration_end_kernel, dim3(1), dim3(256), 0, st, partials, nparts, norm_out, colmask, rowmask,
+                     Jk, Ik, k, Jall, Iall, static_cast<const unsigned*>(rec), static_cast<int>(rec_bytes / 4),
+                     static_cast<unsigned*>(host_dev), flag_dev, seq);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
 
 int launch_to_host_flag(const HostSegs& segs, void* host_dev, unsigned* flag_dev, unsigned seq, hipStream_t st) {
   if (segs.n < 1 || segs.n > kMaxHostSegs) return arg_error("to_host: bad segment list");

@@ -197,6 +197,14 @@ struct HostSegs {
   int n;
 };
 int launch_to_host(const HostSegs& segs, void* host_dev, hipStream_t st);
+// The end of a loop iteration in one launch: *norm_out = the sum of nparts partials (in
+// the order of launch_reduce_partials), the commit of k selected indices (as
+// launch_commit_block), then rec (rec_bytes, holding norm_out) copied to host_dev and,
+// when flag_dev is given, seq published there after the copy is visible.
+int launch_iteration_end(const double* partials, int nparts, double* norm_out, uint8_t* colmask, uint8_t* rowmask,
+                         const int64_t* Jk, const int64_t* Ik, int64_t k, int64_t* Jall, int64_t* Iall,
+                         const void* rec, int64_t rec_bytes, void* host_dev, unsigned* flag_dev, unsigned seq,
+                         hipStream_t st);
 // One workgroup; writes seq to *flag_dev (host-mapped) after the segments are visible.
 int launch_to_host_flag(const HostSegs& segs, void* host_dev, unsigned* flag_dev, unsigned seq, hipStream_t st);
 
