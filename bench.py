@@ -154,7 +154,7 @@ def bench_batched(a):
         "config": {
             "workload": "uneven batch: %d planted FP32 matrices, m,n ~ U{500..8000}, sigma_i = exp(-i/r0), "
                         "r0 ~ U[10,400], tol ~ 10^U[-6,-2], block 32, Gaussian sketch, fp32 form" % a.count,
-            "count": a.count, "elements": elems, "block": b, "workers": a.workers or 8,
+            "count": a.count, "elements": elems, "block": b, "workers": a.workers or 16,
             "plain_loop_s": t_plain, "speedup_vs_plain_loop": t_plain / value,
             "identical_to_plain_loop": bool(same),
             "rank_min": min(ranks), "rank_median": statistics.median(ranks), "rank_max": max(ranks),

@@ -67,7 +67,7 @@ typedef struct icur_opts {
                             matrix cores; -1 = FP32 (plain form) or BF16 pieces (split form),
                             which round N_k^-1 before it multiplies, so the estimate can be
                             off by about cond(N_k) 2^-24: only for well-conditioned blocks */
-  int32_t batch_workers; /* icur_run_batched only: matrices run concurrently, 0 -> 8,
+  int32_t batch_workers; /* icur_run_batched only: matrices run concurrently, 0 -> 16,
                             at most 16; ignored by the single-matrix calls */
 } icur_opts;
 
@@ -130,7 +130,7 @@ int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals
 /*
  * icur_run_batched: Alg. 1 on `count` independent dense FP32 matrices of uneven sizes and
  * tolerances (many small CUR problems at once; each follows Alg. 1 on its own).  The
- * matrices run concurrently, opts->batch_workers (default 8) at a time, each on a worker
+ * matrices run concurrently, opts->batch_workers (default 16) at a time, each on a worker
  * stream of its own with its own cached workspace, largest first; the caller's stream (opts->stream) is waited on
  * before any of them starts.  Each matrix gets exactly the result icur_run would return
  * for it (same kernels, same arithmetic).

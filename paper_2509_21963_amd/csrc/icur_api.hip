@@ -945,7 +945,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   // selection grids of concurrent runs share the CUs, so each is capped at its share;
   // a matrix too large for the share runs afterwards, alone.
   // 8 measured about 25% faster than 4 on the uneven batch, 16 no faster than 8
-  constexpr int kBatchWorkers = 8;
+  constexpr int kBatchWorkers = 16;
   const int S = std::min<int32_t>(count, o.batch_workers > 0 ? o.batch_workers : kBatchWorkers);
   const int gcap = std::max(1, dev.num_cus / S);
   std::vector<int> small, large;
