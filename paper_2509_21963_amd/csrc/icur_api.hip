@@ -944,7 +944,8 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   // ---- workers: batch_workers concurrent runs, each on its own slot and stream.  The
   // selection grids of concurrent runs share the CUs, so each is capped at its share;
   // a matrix too large for the share runs afterwards, alone.
-  // 8 measured about 25% faster than 4 on the uneven batch, 16 no faster than 8
+  // on the uneven batch: 8 about 25% faster than 4, 16 about 6% faster than 8, 24 and 32
+  // no faster than 16
   constexpr int kBatchWorkers = 16;
   const int S = std::min<int32_t>(count, o.batch_workers > 0 ? o.batch_workers : kBatchWorkers);
   const int gcap = std::max(1, dev.num_cus / S);

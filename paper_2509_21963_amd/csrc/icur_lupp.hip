@@ -526,6 +526,8 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
     while (static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT < N) ++sh;
   } else {
     while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * 16 < N) ++sh;
+    // under a workgroup cap (concurrent selections), larger shapes until the grid fits
+    while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * max_groups < N) ++sh;
   }
   const int64_t per_group = static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT;
   if (per_group * max_groups < N) {
