@@ -92,7 +92,7 @@ typedef struct icur_info {
  * icur_run: Alg. 1 on a dense FP32 matrix.
  *   A        device, m x n, row-major, leading dimension lda >= n; read only.
  *   tol      finite, > 0: stop when rho <= tol (times xi when opts->alpha > 0).
- *   block    b, 1 <= b <= min(m, n); c = (11 b) / 10 sketch rows, c <= 4096.
+ *   block    b, 1 <= b <= min(m, n) and b <= 512; c = (11 b) / 10 sketch rows.
  *   sketch_kind, seed: G of icur_sketch_kind drawn from Philox4x32-10 keyed by seed.
  *   opts     may be NULL (all defaults).
  *   I, J     host, capacity max_rank each: selected row / column indices in selection

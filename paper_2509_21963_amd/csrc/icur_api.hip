@@ -395,7 +395,8 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
   const int64_t b = block;
   const int64_t c = (11 * b) / 10;
   if (c > 4096) return arg_error("sketch rows c = floor(1.1 b) above 4096 are not supported");
-  if (b > 1024) return arg_error("block above 1024 is not supported");
+  // the pivot blocks N_k (b x b) are inverted by one workgroup, up to 512 rows
+  if (b > 512) return arg_error("block above 512 is not supported");
   if (kind == ICUR_SKETCH_SPARSE_SIGN && c > 255) return arg_error("sparse-sign sketch needs c <= 255");
   if (sparse && c > 256) return arg_error("the CSR sketch needs c = floor(1.1 b) <= 256");
   if (o->zeta < 0 || o->zeta > 8) return arg_error("zeta must be at most 8");

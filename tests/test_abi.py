@@ -86,6 +86,9 @@ def test_run_rejects_bad_options():
     # sparse-sign needs c <= 255
     st, _ = _run_args(lib, m=300, n=300, lda=300, block=240, kind=1)
     assert st == icur.ERR_ARG
+    # pivot blocks are inverted by one workgroup: b <= 512, rejected before device work
+    st, rank = _run_args(lib, m=1000, n=1000, lda=1000, block=513)
+    assert st == icur.ERR_ARG and rank == -1
 
 
 def test_step_entry_points_reject_bad_shapes():
