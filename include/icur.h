@@ -262,6 +262,32 @@ int icur_gather(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t
 int icur_core_update(double* U, int64_t ldu, int64_t r, int64_t k, const double* Y,
                      const double* A21, const double* A22, double* rcond, void* stream);
 
+/* ------------------------------------------------------------------------------------
+ * Entry point that allocates nothing.
+ * ---------------------------------------------------------------------------------- */
+
+/*
+ * icur_lupp_noalloc: icur_lupp for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, arithmetic, kernels and results as icur_lupp; its workspace is a fixed
+ * 48 MiB device array inside the library (one copy per device, held until the process
+ * ends) instead of the allocated workspace cache, and the call makes no device or
+ * pinned-host allocation.
+ *   Limits: steps <= 256 and lupp_workspace(steps, N) <= 48 MiB, where the workspace is
+ *   about 8 (steps + 16) N bytes plus 80 KB (b = 100 pivots over N = 40000 candidates
+ *   takes 37.3 MB).  Larger requests return ICUR_ERR_ARG with a message.
+ *   Concurrency: every call on one device uses that device's one array, so calls that
+ *   overlap on one device (several host threads, or several streams) race and give
+ *   wrong pivots; serialise them.  Nothing needs clearing between calls: each call
+ *   rewrites every word it later reads.
+ *   Set-up: icur_init_noalloc() looks up the array's device address on the current
+ *   device (call it once per device, with that device current, before any capture);
+ *   icur_lupp_noalloc does the same look-up itself on its first call on a device.
+ */
+int icur_init_noalloc(void);
+int icur_lupp_noalloc(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
+                      const uint8_t* excluded, int64_t* piv, int32_t* npiv, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,7 +52,7 @@ class Info(ctypes.Structure):
 _lib = None
 EXPORTS = ["icur_run", "icur_run_csr", "icur_run_batched", "icur_last_info", "icur_last_error", "icur_release",
            "icur_make_sketch", "icur_sketch", "icur_lupp", "icur_residual", "icur_gather",
-           "icur_core_update"]
+           "icur_core_update", "icur_init_noalloc", "icur_lupp_noalloc"]
 
 
 def load(path=LIB_PATH):
@@ -79,6 +79,8 @@ def load(path=LIB_PATH):
                                   ctypes.POINTER(D), P]
     lib.icur_gather.argtypes = [P, I64, I64, I64, P, P, I64, P, I64, P, I64, P]
     lib.icur_core_update.argtypes = [P, I64, I64, I64, P, P, P, ctypes.POINTER(D), P]
+    lib.icur_init_noalloc.argtypes = []
+    lib.icur_lupp_noalloc.argtypes = [P, I64, I64, I64, I32, P, P, ctypes.POINTER(I32), P]
     for name in EXPORTS:
         if name not in ("icur_last_error",):
             getattr(lib, name).restype = ctypes.c_int
@@ -273,6 +275,29 @@ def lupp(X, steps, excluded=None):
     _check(lib.icur_lupp(_ptr(X), K, N, X.stride(0), steps, _ptr(excluded), _ptr(piv),
                          ctypes.byref(npiv), _stream()))
     return piv[:npiv.value].cpu().numpy()
+
+
+def lupp_noalloc(X, steps, piv, excluded=None):
+    """icur_lupp_noalloc on the K x N FP32 device tensor X into the caller's int64 device
+    tensor piv (capacity >= steps): the library allocates nothing.  Returns the pivot
+    count."""
+    import torch
+    lib = load()
+    _require(X, torch.float32, "X")
+    K, N = X.shape
+    if piv.dtype != torch.int64 or piv.device.type != "cuda" or piv.numel() < steps:
+        raise ValueError("piv must be an int64 device tensor with at least `steps` entries")
+    if excluded is not None and (excluded.dtype != torch.uint8 or excluded.numel() != N):
+        raise ValueError("excluded must be a uint8 device tensor of length N")
+    npiv = ctypes.c_int32(0)
+    _check(lib.icur_lupp_noalloc(_ptr(X), K, N, X.stride(0), steps, _ptr(excluded), _ptr(piv),
+                                 ctypes.byref(npiv), _stream()))
+    return npiv.value
+
+
+def init_noalloc():
+    """icur_init_noalloc: look up the fixed scratch area on the current device."""
+    _check(load().icur_init_noalloc())
 
 
 def residual(X, W, B, terms):
