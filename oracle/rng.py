@@ -14,10 +14,16 @@ implemented, on the GPU) is:
 * sparse-sign entries: zeta distinct rows per column of G drawn by Floyd's sampling
   algorithm (Bentley and Floyd, "A sample of brilliance", CACM 1987), each with a
   random sign.  Scale 1.
+* subsampled randomized trigonometric transform (SRTT, named in §3.4 for very large m):
+  G = sqrt(m/c) R F D with D a diagonal of random signs, F the orthonormal DCT-II of
+  length m, and R keeping c distinct rows of F D drawn by Floyd's algorithm and listed
+  in increasing order.  With this scale E ||G x||^2 = ||x||^2.
 
 Counter layout (shared definition, implemented separately on each side):
   Gaussian entry G[r, i]     : ctr = (lo32(i), hi32(i), r, 0x47415553), key = (lo32(seed), hi32(seed))
   sparse-sign draw t, col i  : ctr = (lo32(i), hi32(i), t, 0x53505253), key = (lo32(seed), hi32(seed))
+  SRTT sign d_i              : ctr = (lo32(i), hi32(i), 0, 0x53525444), bit 0 of x0 set = -1
+  SRTT row draw t            : ctr = (t, 0, 0, 0x53525452), v = (x1 * 2^32 + x0) mod (j + 1)
 """
 import numpy as np
 
@@ -29,6 +35,8 @@ MASK32 = np.uint64(0xFFFFFFFF)
 
 TAG_GAUSS = 0x47415553
 TAG_SIGN = 0x53505253
+TAG_SRTT_SIGN = 0x53525444
+TAG_SRTT_ROWS = 0x53525452
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):
@@ -130,10 +138,64 @@ def sparse_sign_G(seed, c, m, zeta=8):
     return G
 
 
+def srtt_signs(seed, m):
+    """Diagonal of D: d_i = -1 when bit 0 of the Philox word x0 for column i is set."""
+    k0, k1 = _seed_key(seed)
+    i = np.arange(m, dtype=np.uint64)
+    x0, _, _, _ = philox4x32_10(i & MASK32, i >> np.uint64(32), np.zeros(m, np.uint64),
+                                np.full(m, TAG_SRTT_SIGN, np.uint64), k0, k1)
+    return np.where((x0 & np.uint32(1)) == 0, 1.0, -1.0)
+
+
+def srtt_rows(seed, c, m):
+    """The c distinct kept rows of F D in increasing order (Floyd's algorithm: for
+    t = 0 .. c-1 with j = m - c + t draw v uniform on [0, j] from the 64-bit Philox value
+    x1 * 2^32 + x0 modulo j + 1; insert v unless already chosen, else insert j)."""
+    if c > m:
+        raise ValueError("SRTT needs c <= m")
+    k0, k1 = _seed_key(seed)
+    chosen = set()
+    for t in range(c):
+        j = m - c + t
+        x0, x1, _, _ = philox4x32_10(np.uint64(t), np.uint64(0), np.uint64(0),
+                                     np.uint64(TAG_SRTT_ROWS), k0, k1)
+        v = ((int(x1) << 32) | int(x0)) % (j + 1)
+        chosen.add(j if v in chosen else v)
+    return np.array(sorted(chosen), dtype=np.int64)
+
+
+def srtt_G(seed, c, m):
+    """Dense c x m SRTT operator sqrt(m/c) R F D (FP64), from the DCT-II definition
+    F[r, i] = s_r cos(pi r (2 i + 1) / (2 m)), s_0 = sqrt(1/m), s_r = sqrt(2/m).  The
+    angle is reduced exactly as q = r (2 i + 1) mod 4 m before the cosine."""
+    rows = srtt_rows(seed, c, m)
+    d = srtt_signs(seed, m)
+    i = np.arange(m, dtype=np.int64)
+    q = (rows[:, None] * (2 * i[None, :] + 1)) % (4 * m)
+    F = np.cos(np.pi * q.astype(np.float64) / (2.0 * m))
+    scale = np.where(rows == 0, np.sqrt(1.0 / m), np.sqrt(2.0 / m)) * np.sqrt(m / c)
+    return F * scale[:, None] * d[None, :]
+
+
 def make_G(seed, c, m, kind, zeta=8):
-    """The recycled sketch operator G (c x m).  kind 0: Gaussian, 1: sparse-sign."""
+    """The recycled sketch operator G (c x m).  kind 0: Gaussian, 1: sparse-sign,
+    2: SRTT."""
     if kind == 0:
         return gaussian_G(seed, c, m)
     if kind == 1:
         return sparse_sign_G(seed, c, m, zeta)
+    if kind == 2:
+        return srtt_G(seed, c, m)
+    raise ValueError("unknown sketch kind %r" % (kind,))
+
+
+def g_scale(kind, c, zeta=8):
+    """s with E ||G x||^2 = s^2 ||x||^2 for the operator make_G returns: sqrt(c) for the
+    unscaled Gaussian, sqrt(min(zeta, c)) for the sparse-sign operator, 1 for SRTT."""
+    if kind == 0:
+        return float(np.sqrt(c))
+    if kind == 1:
+        return float(np.sqrt(min(int(zeta), int(c))))
+    if kind == 2:
+        return 1.0
     raise ValueError("unknown sketch kind %r" % (kind,))

@@ -104,4 +104,4 @@ def test_make_G_dispatch():
     assert np.array_equal(make_G(1, 4, 9, 0), gaussian_G(1, 4, 9))
     assert np.array_equal(make_G(1, 4, 9, 1), sparse_sign_G(1, 4, 9))
     with pytest.raises(ValueError):
-        make_G(1, 4, 9, 2)
+        make_G(1, 4, 9, 3)
