@@ -58,7 +58,11 @@ typedef struct icur_opts {
   int32_t zeta;         /* nonzeros per column of a sparse-sign G; 0 -> 8 (clamped to c) */
   int64_t max_rank;     /* cap on |J|; 0 -> min(m, n) */
   void*   stream;       /* hipStream_t or NULL */
-  double  alpha;        /* risk-aware stopping (§3.3, Corollary): 0 = off, else in (0,1) */
+  double  alpha;        /* risk-aware stopping (§3.3, Corollary): 0 = off, else in (0,1);
+                           Gaussian sketch only (the Corollary's hypothesis).  With
+                           ICUR_DENOM_A the stop rho <= xi tol bounds the true error by
+                           (1 + delta) tol with probability >= 1 - alpha; with the default
+                           denominator xi is applied to rho as a heuristic */
   double  delta;        /* allowed deviation, >= 0 (used when alpha > 0) */
   int32_t split_terms;  /* BF16_SPLIT only: pieces per FP32 operand, 0 = from tol, 1..3 */
   int32_t sketch_fp32;  /* FP32 form only: 1 = form G A on FP32 matrix cores; 0 (default) =
@@ -69,7 +73,23 @@ typedef struct icur_opts {
                             off by about cond(N_k) 2^-24: only for well-conditioned blocks */
   int32_t batch_workers; /* icur_run_batched only: matrices run concurrently, 0 -> 16,
                             at most 16; ignored by the single-matrix calls */
+  int32_t denominator;  /* estimate's denominator: ICUR_DENOM_GA (0, default, Alg. 1) or
+                           ICUR_DENOM_A (1): rho = ||S^col||_F / (s_G ||A||_F), the quantity
+                           the §3.3 Corollary bounds (s_G^2 = c for the Gaussian G, min(zeta,c)
+                           for the sparse-sign G); costs one extra read of A */
+  int32_t selection;    /* index selection of both steps: ICUR_SELECT_LUPP (0, default) or
+                           ICUR_SELECT_QRCP (1), Alg. 1's alternative (§5.3) */
 } icur_opts;
+
+enum icur_selection {
+  ICUR_SELECT_LUPP = 0,  /* LU with partial pivoting (§3.2.1, §3.2.2) */
+  ICUR_SELECT_QRCP = 1   /* QR with column pivoting (Alg. 1; §5.3) */
+};
+
+enum icur_denominator {
+  ICUR_DENOM_GA = 0,  /* rho = ||S^col||_F / ||G A||_F (Alg. 1); rho starts at 1 */
+  ICUR_DENOM_A = 1    /* rho = ||S^col||_F / (s_G ||A||_F) (§3.3 Corollary; §5 footnote) */
+};
 
 /* Per-call statistics of the calling thread's last icur_run*/
 typedef struct icur_info {
@@ -83,9 +103,11 @@ typedef struct icur_info {
   double  ms_residual;        /* gathers, N_k^-1 and the residual-form products */
   double  ms_core;            /* FP64 assembly of U = A(I,J)^-1 after the loop */
   double  ms_sketch_product;  /* the G A product kernel(s) alone (device events) */
-  int32_t n_rho;              /* entries written to rho[] (<= 512) */
+  int32_t n_rho;              /* entries written to rho[] and block_sizes[] (<= 512) */
   int32_t pad;
   double  rho[512];           /* rho after each iteration */
+  int32_t block_sizes[512];   /* indices added by each iteration (b, or fewer when a
+                                 block is cut short); I and J are these blocks in order */
 } icur_info;
 
 /*
@@ -217,6 +239,18 @@ int icur_lupp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
               const uint8_t* excluded, int64_t* piv, int32_t* npiv, void* stream);
 
 /*
+ * icur_qrcp: pivot order of QR with column pivoting (Alg. 1's alternative selection;
+ * §5.3) applied to X, whose N columns are the candidates (the same candidates as
+ * icur_lupp: T = X^T has one row per candidate).  Step t picks the candidate whose
+ * component orthogonal to the ones already chosen has the largest 2-norm (ties to the
+ * lowest index); FP64, residual vectors orthogonalised explicitly (no norm downdating).
+ *   X, K, N, ldx, steps, excluded, piv, npiv: as icur_lupp (npiv < steps when every
+ *   remaining candidate has an exactly zero residual).  K <= 4096, N < 2^31.
+ */
+int icur_qrcp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
+              const uint8_t* excluded, int64_t* piv, int32_t* npiv, void* stream);
+
+/*
  * icur_residual: OUT = X - W B (the column residual G A - (G C) U R of Alg. 1 with
  * W = (G C) U and B = R, and the row residual A(:,J_k)^T - (U A(I,J_k))^T C^T with
  * W = Y^T and B = C^T), plus ||OUT||_F^2 in FP64.
@@ -233,6 +267,24 @@ int icur_lupp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
 int icur_residual(const float* X, int64_t ldx, const double* W, int64_t ldw, const float* B,
                   int64_t ldb, int64_t M, int64_t K, int64_t N, int32_t terms, float* OUT,
                   int64_t ldo, double* normsq, void* stream);
+
+/*
+ * icur_residual_f64: the residual-form products of the loop in FP64, routed exactly as
+ * icur_run routes them (the recurrence of §4.2: the row residual S^row = A(:,J_k) -
+ * Lc Ur(:,J_k), the residual at the new rows, Ur_k = N_k^{-1} S(I_k,:) and the column
+ * residual S^col <- S^col - S^col(:,J_k) Ur_k).
+ *   X        device, M x N FP64, leading dimension ldx: OUT = X - W B; X may equal OUT
+ *            (in place).  NULL: OUT = W B.
+ *   W        device, M x K FP64 (ldw); B device, K x N FP64 (ldb); OUT device, M x N
+ *            FP64 (ldo).
+ *   normsq   host, may be NULL: ||OUT||_F^2 (FP64 partial sums).
+ * Products of at least 96 rows at depth >= 256 (>= 64 on rows of >= 16384 columns), in
+ * place or plain, run on the library FP64 GEMM; all others on the short-M FP64
+ * matrix-core kernel.  M <= 4096; K may be 0.
+ */
+int icur_residual_f64(const double* X, int64_t ldx, const double* W, int64_t ldw, const double* B,
+                      int64_t ldb, int64_t M, int64_t K, int64_t N, double* OUT, int64_t ldo,
+                      double* normsq, void* stream);
 
 /*
  * icur_gather: the CUR factor gathers of Alg. 1 (C = A(:,J), R = A(I,:)).

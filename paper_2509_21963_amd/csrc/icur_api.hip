@@ -13,6 +13,7 @@
 #include <thread>
 #include <vector>
 
+#include "icur_batched.h"
 #include "icur_internal.h"
 #include "icur_wide_kernel.h"
 
@@ -50,7 +51,7 @@ namespace {
 enum Slot {
   kG, kRowsPat, kSignsPat, kX0, kS, kSrow, kCt, kR, kU, kY, kA12, kA21, kA22, kYt, kX0J, kW64,
   kWp, kColMask, kRowMask, kJk, kIk, kJall, kIall, kLupp, kGemmWs, kNormPart, kScal, kCoreWs,
-  kStepA, kStepB, kCsc, kNumSlots
+  kStepA, kStepB, kCsc, kQrcp, kNumSlots
 };
 
 struct Buf {
@@ -150,6 +151,7 @@ struct Scal {
   double norms[2];
   int info;
   int pad;
+  double normsq_a;  // ||A||_F^2 (the ||A||_F denominator only)
 };
 
 // Device-event timing of the phases (icur_info).  When off (the batched workers), every
@@ -324,11 +326,6 @@ int prepare_device(DeviceCache** out, int slot = 0) {
   return ICUR_OK;
 }
 
-// Sketch accumulation: FP32 sums over 128 rows of A give X0 a relative noise near
-// sqrt(128) 2^-24; the column residual subtracts X0(:,J) times interpolation coefficients
-// whose norm reaches tens on ill-conditioned crosses, which puts a floor near 1e-5 under
-// rho.  Below this tolerance the sums are widened to FP64 after every 32 rows.
-constexpr double kSketchChunkFlushBelow = 1e-4;
 // Row selection ends at a pivot below this fraction of its first pivot: the Schur
 // complement is then rounding noise of the factors' precision (a block straddling the
 // exact rank of A), and inverting that noise in N_k would wreck the residual recurrence.
@@ -343,16 +340,6 @@ constexpr int64_t kLibraryGemmMinKWide = 64;
 constexpr int64_t kLibraryGemmWideN = 16384;
 constexpr int64_t kLibraryGemmMinM = 96;
 constexpr double kRowCutFp32 = 0x1.0p-16;
-
-// BF16 pieces per FP32 operand for a tolerance.  One piece rounds with relative error
-// up to 2^-8, two with 2^-16, three reproduce FP32.  The sketched residual's noise
-// floor is this error amplified by the interpolation coefficients of the cross, so the
-// count leaves a wide margin: one piece only for very loose tolerances.
-int terms_for_tol(double tol) {
-  if (tol >= 1e-1) return 1;
-  if (tol >= 5e-4) return 2;
-  return 3;
-}
 
 double risk_factor(double alpha, double delta, int64_t c, int* status) {
   *status = ICUR_OK;
@@ -405,9 +392,112 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
   if (o->residual_fp64 < -1 || o->residual_fp64 > 1) return arg_error("residual_fp64 must be -1, 0 or 1");
   if (o->max_rank < 0) return arg_error("max_rank must be >= 0");
   if (o->batch_workers < 0 || o->batch_workers > 16) return arg_error("batch_workers must be 0..16");
+  if (o->denominator != ICUR_DENOM_GA && o->denominator != ICUR_DENOM_A) return arg_error("unknown denominator");
+  if (o->selection != ICUR_SELECT_LUPP && o->selection != ICUR_SELECT_QRCP) return arg_error("unknown selection");
+  // the Corollary of §3.3 is stated for a Gaussian G
+  if (o->alpha != 0.0 && kind != ICUR_SKETCH_GAUSSIAN)
+    return arg_error("risk-aware stopping needs the Gaussian sketch (the §3.3 Corollary's hypothesis)");
   int st_risk = ICUR_OK;
   (void)risk_factor(o->alpha, o->delta, c, &st_risk);
   return st_risk;
+}
+
+}  // namespace
+
+// BF16 pieces per FP32 operand for a tolerance.  One piece rounds with relative error
+// up to 2^-8, two with 2^-16, three reproduce FP32.  The sketched residual's noise
+// floor is this error amplified by the interpolation coefficients of the cross, so the
+// count leaves a wide margin: one piece only for very loose tolerances.
+int terms_for_tol(double tol) {
+  if (tol >= 1e-1) return 1;
+  if (tol >= 5e-4) return 2;
+  return 3;
+}
+
+// G (c x m BF16, leading dimension ldg) drawn from (kind, seed, zeta), X0 = G A into S
+// (c x n FP64) and ||X0||_F^2 into *normsq_dev: the sketch kernel when the shape allows
+// (A split into `terms` BF16 pieces), else the general product.  ev_begin / ev_end (may
+// be null) bracket the product kernel.
+int form_sketch(int kind, uint64_t seed, int64_t c, int64_t m, int64_t n, const float* A, int64_t lda, int zeta,
+                int terms, bool precise, uint16_t* G, int64_t ldg, double* S, double* partials, void* ws,
+                size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
+  if (kind == ICUR_SKETCH_GAUSSIAN)
+    ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
+  else
+    ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, ldg, st));
+  int parts = 0;
+  int sk = ICUR_ERR_UNSUPPORTED;
+  if (terms > 0)
+    sk = sketch_product(G, ldg, c, A, m, n, lda, terms, precise, S, n, partials, &parts, ws, ws_bytes, st, ev_begin,
+                        ev_end);
+  if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
+  if (sk == ICUR_ERR_UNSUPPORTED) {
+    if (ev_begin) ICUR_HIP(hipEventRecord(ev_begin, st));
+    WideGemm g{};
+    g.W = G;
+    g.ldw = ldg;
+    g.wterms = terms == 0 ? 0 : 1;
+    g.w_bf16 = true;
+    g.B = A;
+    g.ldb = lda;
+    g.bterms = terms;
+    g.M = c;
+    g.K = m;
+    g.N = n;
+    g.subtract = false;
+    g.out64 = true;
+    g.OUT = S;
+    g.ldo = n;
+    g.norm_partials = partials;
+    g.nparts = &parts;
+    ICUR_TRY(wide_gemm(g, ws, ws_bytes, st));
+    if (ev_end) ICUR_HIP(hipEventRecord(ev_end, st));
+  }
+  return launch_reduce_partials(partials, parts, normsq_dev, st);
+}
+
+namespace {
+
+// OUT = X - W B (subtract) or W B in FP64 (W is M x K with leading dimension ldw, B is
+// K x N, X and OUT M x N), routed as the loop routes its residual products: products of
+// at least kLibraryGemmMinM rows at depth >= kLibraryGemmMinK (or >= kLibraryGemmMinKWide
+// on rows of >= kLibraryGemmWideN columns), in place (X == OUT) or plain (X null), on the
+// library FP64 GEMM, with the norm partials from a separate pass; all others on the
+// short-M FP64 matrix-core kernel, which fuses the partials.  norm_partials may be null.
+int product_f64(const double* W, int64_t ldw, int64_t M, int64_t K, const double* X, int64_t ldx, const double* B,
+                int64_t ldb, int64_t N, bool subtract, double* OUT, int64_t ldo, double* norm_partials, int* parts,
+                void* gemm_ws, size_t gemm_ws_bytes, hipStream_t st) {
+  if (M >= kLibraryGemmMinM && (K >= kLibraryGemmMinK || (K >= kLibraryGemmMinKWide && N >= kLibraryGemmWideN)) &&
+      ((X == OUT && subtract) || (X == nullptr && !subtract))) {
+    ICUR_TRY(dgemm(M, N, K, subtract ? -1.0 : 1.0, W, ldw, 1, B, ldb, 1, subtract ? 1.0 : 0.0, OUT, ldo, st));
+    if (norm_partials) {
+      const int blocks = static_cast<int>(std::min<int64_t>((M * N + 255) / 256, 1024));
+      ICUR_TRY(wide::launch_reduce_f64(nullptr, 0, M, N, OUT, ldo, 1, OUT, ldo, norm_partials, blocks, st));
+      *parts = blocks;
+    } else {
+      *parts = 0;
+    }
+    return ICUR_OK;
+  }
+  WideGemm g{};
+  g.X = X;
+  g.ldx = ldx;
+  g.W = W;
+  g.ldw = ldw;
+  g.wterms = -1;
+  g.B = B;
+  g.ldb = ldb;
+  g.bterms = -1;
+  g.M = M;
+  g.K = K;
+  g.N = N;
+  g.subtract = subtract;
+  g.out64 = true;
+  g.OUT = OUT;
+  g.ldo = ldo;
+  g.norm_partials = norm_partials;
+  g.nparts = parts;
+  return wide_gemm(g, gemm_ws, gemm_ws_bytes, st);
 }
 
 // cache_slot: the workspace to use (0 for single calls); lupp_groups > 0 caps the
@@ -432,6 +522,9 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   const double xi = risk_factor(o.alpha, o.delta, c, &st_risk);
   if (st_risk != ICUR_OK) return st_risk;
   const double thr = xi * tol;
+  const bool denom_a = (o.denominator == ICUR_DENOM_A);
+  // s_G^2: E ||G x||^2 = s_G^2 ||x||^2 for the unscaled operators
+  const double sg2 = kind == ICUR_SKETCH_GAUSSIAN ? static_cast<double>(c) : static_cast<double>(std::min<int64_t>(zeta, c));
   const bool split = (o.precision == ICUR_BF16_SPLIT);
   const int T = split ? (o.split_terms ? o.split_terms : terms_for_tol(tol)) : 0;
   // sketch pieces: the plain form forms every product exactly (three pieces of A times a
@@ -490,7 +583,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   gemm_ws = std::max(gemm_ws, wide_gemm_workspace_bytes(b, BIGK, n, dev.num_cus));
   gemm_ws = std::max(gemm_ws, sketch_workspace_bytes(c, m, n, dev.num_cus));
   ICUR_TRY(ensure(dc, kGemmWs, gemm_ws, &pGemm));
-  const int nparts_cap = std::max(std::max(std::max(max_norm_partials(c, n), max_norm_partials(b, m)),
+  const int nparts_cap = std::max(std::max(std::max(std::max(max_norm_partials(c, n), max_norm_partials(b, m)), kSumsqMaxParts),
                                            sketch_max_norm_partials(c, n)),
                                   csr_max_norm_partials(n));
   ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(nparts_cap) * 8, &pNorm));
@@ -498,6 +591,18 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   LuppWork lw;
   lupp_bind_workspace(pLupp, b, std::max(m, n), &lw);
   lw.max_groups = lupp_groups;
+  const bool qrcp = (o.selection == ICUR_SELECT_QRCP);
+  void* pQr = nullptr;
+  if (qrcp)
+    ICUR_TRY(ensure(dc, kQrcp, std::max(qrcp_workspace_bytes(c, n, 4 * dev.num_cus), qrcp_workspace_bytes(b, m, 4 * dev.num_cus)),
+                    &pQr));
+  // the selection of Alg. 1: LUPP (default) or QRCP, same status words
+  auto select = [&](const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps, const uint8_t* excl,
+                    int64_t* piv, double rel_cut) -> int {
+    if (qrcp)
+      return qrcp_launch(X, x64, K, N, ldx, steps, excl, piv, lw.status, pQr, dc.buf[kQrcp].bytes, st, rel_cut);
+    return lupp_launch(X, x64, K, N, ldx, steps, excl, piv, lw, st, rel_cut);
+  };
   Scal* dscal = static_cast<Scal*>(pScal);
   double* dnorm = static_cast<double*>(pNorm);
   double* Nblk = static_cast<double*>(pN);                 // b x b, then its inverse
@@ -537,38 +642,25 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
                      int* parts) -> int {
     // res64: W and B are FP64 and OUT is FP64 (FP64 matrix cores); else W is split into
     // BF16 pieces (or rounded to FP32) and B is FP32.
-    if (res64 && M >= kLibraryGemmMinM &&
-        (K >= kLibraryGemmMinK || (K >= kLibraryGemmMinKWide && N >= kLibraryGemmWideN)) &&
-        ((X == OUT && subtract) || (X == nullptr && !subtract))) {
-      // deep products in place (OUT -= W B) or plain: a library FP64 GEMM, then the
-      // norm partials of OUT in a pass of their own when asked for; shallow ones stay
-      // on the short-M kernel, which fuses the norm and has less launch overhead
-      ICUR_TRY(dgemm(M, N, K, subtract ? -1.0 : 1.0, W64, K, 1, static_cast<const double*>(B), ldb, 1,
-                     subtract ? 1.0 : 0.0, static_cast<double*>(OUT), ldo, st));
-      if (norm) {
-        const int blocks = static_cast<int>(std::min<int64_t>((M * N + 255) / 256, 1024));
-        ICUR_TRY(wide::launch_reduce_f64(nullptr, 0, M, N, OUT, ldo, 1, OUT, ldo, dnorm, blocks, st));
-        *parts = blocks;
-      } else {
-        *parts = 0;
-      }
-      return ICUR_OK;
-    }
-    if (K > 0 && !res64) ICUR_TRY(launch_split_f64(W64, M, K, K, false, T, pWp, K, M * K, st));
+    if (res64)
+      return product_f64(W64, K, M, K, static_cast<const double*>(X), ldx, static_cast<const double*>(B), ldb, N,
+                         subtract, static_cast<double*>(OUT), ldo, norm ? dnorm : nullptr, parts, pGemm,
+                         dc.buf[kGemmWs].bytes, st);
+    if (K > 0) ICUR_TRY(launch_split_f64(W64, M, K, K, false, T, pWp, K, M * K, st));
     WideGemm g{};
     g.X = X;
     g.ldx = ldx;
-    g.W = res64 ? static_cast<const void*>(W64) : pWp;
+    g.W = pWp;
     g.ldw = K;
-    g.wterms = res64 ? -1 : T;
+    g.wterms = T;
     g.B = B;
     g.ldb = ldb;
-    g.bterms = res64 ? -1 : T;
+    g.bterms = T;
     g.M = M;
     g.K = K;
     g.N = N;
     g.subtract = subtract;
-    g.out64 = out64 || res64;
+    g.out64 = out64;
     g.OUT = OUT;
     g.ldo = ldo;
     g.norm_partials = norm ? dnorm : nullptr;
@@ -589,43 +681,21 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     ICUR_TRY(tm.mark(&ev_p1));
     ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
   } else {
-    if (kind == ICUR_SKETCH_GAUSSIAN)
-      ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
-    else
-      ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, ldg, st));
-    int parts = 0;
     // ev_p0 / ev_p1 bracket the sketch kernel itself (the first 160-row slice of G when
     // c > 160), not its split-K reduce; the general product is bracketed whole
     ICUR_TRY(tm.reserve(&ev_p0));
     ICUR_TRY(tm.reserve(&ev_p1));
-    int sk = ICUR_ERR_UNSUPPORTED;
-    if (sketch_terms > 0)
-      sk = sketch_product(G, ldg, c, A, m, n, lda, sketch_terms, tol < kSketchChunkFlushBelow, S, n, dnorm,
-                          &parts, pGemm, dc.buf[kGemmWs].bytes, st, tm.event(ev_p0), tm.event(ev_p1));
-    if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
-    if (sk == ICUR_ERR_UNSUPPORTED) ICUR_TRY(tm.record(ev_p0));
-    WideGemm g{};
-    g.W = G;
-    g.ldw = ldg;
-    g.wterms = sketch_terms == 0 ? 0 : 1;
-    g.w_bf16 = true;
-    g.B = A;
-    g.ldb = lda;
-    g.bterms = sketch_terms;
-    g.M = c;
-    g.K = m;
-    g.N = n;
-    g.subtract = false;
-    g.out64 = true;
-    g.OUT = S;
-    g.ldo = n;
-    g.norm_partials = dnorm;
-    g.nparts = &parts;
-    if (sk == ICUR_ERR_UNSUPPORTED) {
-      ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
-      ICUR_TRY(tm.record(ev_p1));
-    }
-    ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_x0, st));
+    ICUR_TRY(form_sketch(kind, seed, c, m, n, A, lda, zeta, sketch_terms, tol < kSketchChunkFlushBelow, G, ldg, S,
+                         dnorm, pGemm, dc.buf[kGemmWs].bytes, &dscal->normsq_x0, st, tm.event(ev_p0),
+                         tm.event(ev_p1)));
+  }
+  if (denom_a) {
+    int parts = 0;
+    if (sparse)
+      ICUR_TRY(launch_sumsq_f32(src.csr->vals, 1, src.csr->nnz, std::max<int64_t>(src.csr->nnz, 1), dnorm, &parts, st));
+    else
+      ICUR_TRY(launch_sumsq_f32(A, m, n, lda, dnorm, &parts, st));
+    ICUR_TRY(launch_reduce_partials(dnorm, parts, &dscal->normsq_a, st));
   }
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pColMask), n, 0, st));
   ICUR_TRY(launch_fill_u8(static_cast<uint8_t*>(pRowMask), m, 0, st));
@@ -639,6 +709,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   // Returns 1 when the call ends here (rank 0, or an error in *err).
   Scal hs;
   double gnorm2 = -1.0;
+  double denom2 = -1.0;  // the estimate's squared denominator: ||G A||_F^2 or s_G^2 ||A||_F^2
   int norm_err = ICUR_OK;
   auto take_norm = [&]() -> bool {
     gnorm2 = hs.normsq_x0;
@@ -648,9 +719,13 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
       norm_err = ICUR_ERR_NONFINITE;
       return true;
     }
-    if (gnorm2 == 0.0) {
+    denom2 = denom_a ? sg2 * hs.normsq_a : gnorm2;
+    // with the ||A||_F denominator the empty approximation already has rho < 1, and may
+    // meet the tolerance without any index
+    const double rho0 = gnorm2 == 0.0 ? 0.0 : std::sqrt(gnorm2 / denom2);
+    if (gnorm2 == 0.0 || (denom_a && rho0 <= thr)) {
       *rank_out = 0;
-      *est_out = 0.0;
+      *est_out = rho0;
       tm.flush();
       t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
       return true;
@@ -684,7 +759,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     size_t e0 = iter_start, e1, e2, e3, e4;
     int parts = 0;
     // column selection: LUPP on (S^col)^T
-    ICUR_TRY(lupp_launch(S, true, c, n, n, static_cast<int>(s), static_cast<const uint8_t*>(pColMask), Jk, lw, st));
+    ICUR_TRY(select(S, true, c, n, n, static_cast<int>(s), static_cast<const uint8_t*>(pColMask), Jk, 0.0));
     ICUR_TRY(tm.mark(&e1));
     int lst[2];
     if (gnorm2 < 0.0) {
@@ -721,8 +796,8 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     }
     ICUR_TRY(tm.mark(&e2));
     // row selection: LUPP on S^row
-    ICUR_TRY(lupp_launch(Lk, res64, nJ, m, m, static_cast<int>(nJ), static_cast<const uint8_t*>(pRowMask), Ik, lw, st,
-                         res64 ? kRowCutFp64 : kRowCutFp32));
+    ICUR_TRY(select(Lk, res64, nJ, m, m, static_cast<int>(nJ), static_cast<const uint8_t*>(pRowMask), Ik,
+                    res64 ? kRowCutFp64 : kRowCutFp32));
     ICUR_TRY(tm.mark(&e3));
     ICUR_TRY(read_int(dc, lw.status, lst, 2, st));
     if (lst[1]) {
@@ -789,9 +864,12 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     }
     r += nI;
     blocks.push_back(nI);
-    rho = std::sqrt(hs.normsq_s / gnorm2);
+    rho = std::sqrt(hs.normsq_s / denom2);
     const int it = t_info.iterations++;
-    if (it < 512) t_info.rho[it] = rho;
+    if (it < 512) {
+      t_info.rho[it] = rho;
+      t_info.block_sizes[it] = static_cast<int32_t>(nI);
+    }
     t_info.n_rho = std::min(t_info.iterations, 512);
     tm.add(e0, e1, &t_info.ms_select);
     tm.add(e2, e3, &t_info.ms_select);
@@ -947,12 +1025,56 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   // a matrix too large for the share runs afterwards, alone.
   // on the uneven batch: 8 about 25% faster than 4, 16 about 6% faster than 8, 24 and 32
   // no faster than 16
+  // ---- grouped form (default): every matrix that fits one selection workgroup and uses
+  // FP64 residual factors advances together with the others, one launch per step
+  std::vector<std::string> errs(static_cast<size_t>(count), "not run: no worker thread could select the device");
+  std::vector<int> grouped, rest;
+  const bool group_ok = o.batch_workers == 0 && block <= kGMaxSteps && o.residual_fp64 >= 0 &&
+                        o.selection == ICUR_SELECT_LUPP;
+  for (int32_t i = 0; i < count; ++i)
+    (group_ok && std::max(m[i], n[i]) <= kGMaxN ? grouped : rest).push_back(i);
+  int64_t total_iters = 0;
+  if (!grouped.empty()) {
+    int st_risk = ICUR_OK;
+    BatchedCall bc{};
+    bc.count = count;
+    bc.A = A;
+    bc.m = m;
+    bc.n = n;
+    bc.lda = lda;
+    bc.tol = tol;
+    bc.block = block;
+    bc.kind = sketch_kind;
+    bc.seed = seed;
+    bc.opts = &o;
+    bc.xi = risk_factor(o.alpha, o.delta, (11 * static_cast<int64_t>(block)) / 10, &st_risk);
+    bc.row_cut = kRowCutFp64;
+    bc.I_pool = I_pool;
+    bc.J_pool = J_pool;
+    bc.U_pool = U_pool;
+    bc.cap_offsets = cap_offsets;
+    bc.uoff = uoff.data();
+    bc.rank = rank;
+    bc.est = est_err;
+    bc.status = status;
+    bc.errs = errs.data();
+    for (int i : grouped) status[i] = ICUR_ERR_HIP;
+    const int gst = run_batched_grouped(grouped, bc, caller);
+    if (gst < 0) {
+      for (int i : grouped) {
+        status[i] = gst;
+        errs[i] = t_error;
+      }
+    }
+    total_iters += bc.iterations;
+  }
+
   constexpr int kBatchWorkers = 16;
-  const int S = std::min<int32_t>(count, o.batch_workers > 0 ? o.batch_workers : kBatchWorkers);
+  const int S = std::max(1, std::min<int32_t>(static_cast<int32_t>(rest.size()),
+                                              o.batch_workers > 0 ? o.batch_workers : kBatchWorkers));
   const int gcap = std::max(1, dev.num_cus / S);
   std::vector<int> small, large;
-  for (int32_t i = 0; i < count; ++i)
-    (std::max(m[i], n[i]) <= lupp_max_candidates(gcap) ? small : large).push_back(i);
+  for (int i : rest) (std::max(m[i], n[i]) <= lupp_max_candidates(gcap) ? small : large).push_back(i);
   auto by_size = [&](int x, int y) { return m[x] * n[x] > m[y] * n[y] || (m[x] * n[x] == m[y] * n[y] && x < y); };
   std::sort(small.begin(), small.end(), by_size);
   std::sort(large.begin(), large.end(), by_size);
@@ -970,9 +1092,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   for (int s = 0; s < S; ++s) ICUR_HIP(hipStreamWaitEvent(streams[s], ready, 0));
 
   // a matrix stays marked as not run unless a worker reaches it
-  std::vector<std::string> errs(static_cast<size_t>(count), "not run: no worker thread could select the device");
-  for (int32_t i = 0; i < count; ++i) status[i] = ICUR_ERR_HIP;
-  int64_t total_iters = 0;
+  for (int i : rest) status[i] = ICUR_ERR_HIP;
   std::mutex iters_mu;
   auto run_one = [&](int i, int s, int groups) {
     icur_opts oo = o;
@@ -1176,6 +1296,32 @@ int icur_lupp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps,
   return ICUR_OK;
 }
 
+int icur_qrcp(const float* X, int64_t K, int64_t N, int64_t ldx, int32_t steps, const uint8_t* excluded, int64_t* piv,
+              int32_t* npiv, void* stream) {
+  t_error.clear();
+  if (!X || !piv || !npiv) return arg_error("null pointer");
+  if (K < 1 || N < 1 || ldx < N) return arg_error("invalid shape");
+  if (steps < 1 || steps > K) return arg_error("need 1 <= steps <= K");
+  if (K > 4096) return arg_error("K above 4096 is not supported");
+  if (N > 0x7fffffffLL) return arg_error("N must be below 2^31");
+  DeviceCache* dcp;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  hipStream_t st = as_stream(stream);
+  void *pQ, *pS;
+  ICUR_TRY(ensure(dc, kQrcp, qrcp_workspace_bytes(K, N, 4 * dev.num_cus), &pQ));
+  ICUR_TRY(ensure(dc, kScal, 256, &pS));
+  int* status = static_cast<int*>(pS);
+  ICUR_TRY(qrcp_launch(X, false, K, N, ldx, steps, excluded, piv, status, pQ, dc.buf[kQrcp].bytes, st));
+  int lst[1];
+  ICUR_TRY(read_int(dc, status, lst, 1, st));
+  *npiv = lst[0];
+  return ICUR_OK;
+}
+
 int icur_residual(const float* X, int64_t ldx, const double* W, int64_t ldw, const float* B,
                   int64_t ldb, int64_t M, int64_t K, int64_t N, int32_t terms, float* OUT,
                   int64_t ldo, double* normsq, void* stream) {
@@ -1219,6 +1365,38 @@ int icur_residual(const float* X, int64_t ldx, const double* W, int64_t ldw, con
   int parts = 0;
   g.nparts = &parts;
   ICUR_TRY(wide_gemm(g, pGemm, dc.buf[kGemmWs].bytes, st));
+  Scal* ds = static_cast<Scal*>(pScal);
+  ICUR_TRY(launch_reduce_partials(static_cast<double*>(pNorm), parts, &ds->normsq_s, st));
+  Scal hs;
+  ICUR_TRY(read_scal(dc, ds, &hs, st));
+  if (normsq) *normsq = hs.normsq_s;
+  return ICUR_OK;
+}
+
+int icur_residual_f64(const double* X, int64_t ldx, const double* W, int64_t ldw, const double* B, int64_t ldb,
+                      int64_t M, int64_t K, int64_t N, double* OUT, int64_t ldo, double* normsq, void* stream) {
+  t_error.clear();
+  if (!OUT || (K > 0 && (!W || !B))) return arg_error("null pointer");
+  if (M < 1 || N < 1 || K < 0) return arg_error("invalid shape");
+  if (M > 4096) return arg_error("M above 4096 is not supported");
+  if (ldo < N || (X && ldx < N) || (K > 0 && (ldw < K || ldb < N))) return arg_error("invalid leading dimension");
+  DeviceCache* dcp;
+  ICUR_TRY(prepare_device(&dcp));
+  DeviceCache& dc = *dcp;
+  std::lock_guard<std::mutex> lock(dc.mu);
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  hipStream_t st = as_stream(stream);
+  void *pGemm, *pNorm, *pScal;
+  ICUR_TRY(ensure(dc, kGemmWs, wide_gemm_workspace_bytes(M, K, N, dev.num_cus), &pGemm));
+  ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(std::max(max_norm_partials(M, N), 1024)) * 8, &pNorm));
+  ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  int parts = 0;
+  // X == OUT or X null with K > 0 take the library route when the shape qualifies; a
+  // separate X is subtracted by the short-M kernel
+  const bool plain = (X == nullptr);
+  ICUR_TRY(product_f64(W, ldw, M, K, X, ldx, B, ldb, N, !plain, OUT, ldo, static_cast<double*>(pNorm), &parts, pGemm,
+                       dc.buf[kGemmWs].bytes, st));
   Scal* ds = static_cast<Scal*>(pScal);
   ICUR_TRY(launch_reduce_partials(static_cast<double*>(pNorm), parts, &ds->normsq_s, st));
   Scal hs;

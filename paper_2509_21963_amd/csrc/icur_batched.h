@@ -1,0 +1,120 @@
+// Grouped kernels of the batched form: many independent matrices advanced together, one
+// launch per step of Alg. 1 for all of them (icur_group_*.hip), driven by
+// icur_batched.hip.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "icur_internal.h"
+
+namespace icur {
+
+// ----- limits of the grouped path
+constexpr int kGMaxN = 8192;     // candidates per selection (one workgroup holds them all)
+constexpr int kGMaxSteps = 64;   // pivots per selection (so block <= 64, c <= 70)
+
+// One LUPP selection: pivots of T = X^T (N candidates x K >= *steps columns), FP64,
+// textbook right-looking rounding (the pivots of icur_lupp on the same values).
+struct GroupLuppJob {
+  const double* X;        // K x N, leading dimension ldx: X[t * ldx + i] = T[i][t]
+  int64_t ldx;
+  int N;                  // candidates, <= kGMaxN
+  int pad;
+  const int* steps;       // device: pivots wanted (<= kGMaxSteps); 0 skips the job
+  const uint8_t* excl;    // N flags or null
+  double* L;              // scratch, *steps x N doubles
+  int64_t* piv;           // out: pivot indices in order
+  int* npiv;              // out: pivots found
+  double rel_cut;         // > 0: stop at a pivot <= rel_cut * |first pivot|
+};
+int launch_group_lupp(const GroupLuppJob* jobs_dev, int njobs, hipStream_t st);
+
+// ----- per-matrix state of the batched loop (device array, one entry per matrix)
+struct BatchMat {
+  // input and fixed buffers
+  const float* A;
+  int64_t lda;
+  int m, n;
+  double* S;          // c x n: X0, then the sketched column residual
+  double* Lsel;       // b x max(m, n): selection multipliers
+  double* Sr;         // b x n: residual at the new rows, A(I_k,:) - Lc(I_k,:) Ur
+  double* Wc;         // c x b: S(:, J_k)
+  double* Nk;         // b x b: pivot block N_k = S(I_k, J_k), inverted in place
+  double* normp;      // norm partials of the column-residual update
+  uint8_t* colmask;   // n
+  uint8_t* rowmask;   // m
+  int64_t* Jk;        // b
+  int64_t* Ik;        // b
+  // rank-sized buffers (capacity cap, grown by the host between iterations)
+  double* LcT;        // cap x m: column factors (row t = S^{(k-1)}(:, J_k[t])^T)
+  double* Ur;         // cap x n: row factors (N_k^{-1} S^{(k-1)}(I_k, :))
+  double* U;          // cap x cap: the core A(I,J)^{-1}, leading dimension cap
+  double* Wa;         // b x cap: Ur(:, J_k)^T, then Lc(I_k, :)
+  double* AIJk;       // cap x b: A(I, J_k)
+  double* AIkJ;       // b x cap: A(I_k, J)
+  double* Y;          // cap x b: U A(I, J_k)
+  double* Z;          // b x cap: A(I_k, J) U
+  double* V;          // cap x b: Y N_k^{-1}
+  int64_t* Jall;      // cap
+  int64_t* Iall;      // cap
+  int cap;
+  int rmax;           // rank bound, min(m, n, max_rank)
+  // loop state
+  int r;              // indices selected so far
+  int s;              // column pivots wanted this iteration; 0 = finished
+  int nJ, nI;         // pivots found by this iteration's selections
+  int info;           // nonzero: N_k exactly singular
+  int status;         // ICUR_OK, ICUR_MAXRANK or ICUR_STALLED once finished
+  int iters;
+  double denom2;      // squared denominator of rho
+  double thr;         // stopping threshold xi * tol
+  double rho;
+  int nparts;         // norm partials written by the last update
+  int pad;
+};
+
+// The column (rows = false) or row selection of every unfinished matrix, one workgroup
+// each: writes Jk / nJ or Ik / nI.
+int launch_batch_lupp(BatchMat* mats_dev, int count, bool rows, double rel_cut, hipStream_t st);
+
+// Per-matrix record copied to host-mapped memory at the end of every iteration.
+struct BatchRec {
+  int r, s, status, info, iters, pad;
+  double rho;
+};
+
+// Arguments of one icur_run_batched call as the grouped driver sees them (host arrays
+// indexed by matrix; checked by the caller).
+struct BatchedCall {
+  int count;
+  const float* const* A;
+  const int64_t* m;
+  const int64_t* n;
+  const int64_t* lda;
+  const double* tol;
+  int block;
+  int kind;
+  const uint64_t* seed;
+  const icur_opts* opts;  // defaults applied
+  double xi;              // risk-aware factor (1 when off)
+  double row_cut;         // relative cut of the row selection
+  int64_t* I_pool;
+  int64_t* J_pool;
+  double* U_pool;
+  const int64_t* cap_offsets;
+  const int64_t* uoff;    // start of each matrix's core in U_pool
+  int64_t* rank;
+  double* est;
+  int32_t* status;
+  std::string* errs;      // per-matrix messages of failed matrices
+  int iterations;         // out: grouped iterations run
+};
+
+// Alg. 1 on the matrices listed in `which` (each with max(m, n) <= kGMaxN, block <=
+// kGMaxSteps), all advanced together; results into the call's pools.  Per-matrix
+// failures go to status / errs; the return value is an error only when the whole group
+// could not run.
+int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream_t st);
+
+}  // namespace icur

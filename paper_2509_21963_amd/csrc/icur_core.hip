@@ -20,6 +20,7 @@
 #include <rocblas/rocblas.h>
 
 #include "icur_internal.h"
+#include "icur_gj.h"
 #include "icur_wave.h"
 
 namespace icur {
@@ -382,82 +383,10 @@ __global__ __launch_bounds__(256) void gj_inverse_tile_kernel(double* __restrict
   if (tid == 0) *info = 0;
 }
 
-// The same inverse for a block whose rows are already in partial-pivoting order: the
-// pivot block N_k of a row selection (rows I_k in selection order, columns J_k) is the
-// leading part of an LU with partial pivoting, so eliminating on the diagonal in order
-// keeps every multiplier within 1 and needs no pivot search.  Per step the tile column
-// and the tile row holding column and row j publish them, one barrier, then the update.
-// A zero pivot reports info = 1.
+// The in-order Gauss-Jordan inverse (icur_gj.h) for one block.
 __global__ __launch_bounds__(256) void gj_inverse_inorder_kernel(double* __restrict__ Ng, int k,
                                                                  int* __restrict__ info) {
-  __shared__ double colj[2][128];
-  __shared__ double prow[2][128];
-  const int tid = threadIdx.x;
-  const int tr = tid >> 4, tc = tid & 15;
-  const int r0 = 8 * tr, c0 = 8 * tc;
-  double a[8][8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const int r = r0 + i, c = c0 + jj;
-      a[i][jj] = (r < k && c < k) ? Ng[r * k + c] : 0.0;
-    }
-  for (int j0 = 0; j0 < k; j0 += 8) {
-    const int tj = j0 >> 3;
-    bool fail = false;
-    tile_static_for<8>([&](auto jcc) __attribute__((always_inline)) {
-      constexpr int jc = decltype(jcc)::value;
-      const int j = j0 + jc;
-      if (fail || j >= k) return;
-      const int b = j & 1;
-      if (tc == tj) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) colj[b][r0 + i] = a[i][jc];
-      }
-      if (tr == tj) {
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) prow[b][c0 + jj] = a[jc][jj];
-      }
-      __syncthreads();
-      const double piv = colj[b][j];
-      if (piv == 0.0) {  // uniform: every thread read the same word
-        fail = true;
-        return;
-      }
-      const double rinv = 1.0 / piv;
-      double pr[8], f[8];
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) pr[jj] = prow[b][c0 + jj] * rinv;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) f[i] = colj[b][r0 + i];
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) a[i][jj] = a[i][jj] - f[i] * pr[jj];
-      if (tc == tj) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) a[i][jc] = -f[i] * rinv;
-      }
-      if (tr == tj) {
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) a[jc][jj] = pr[jj];
-        if (tc == tj) a[jc][jc] = rinv;
-      }
-    });
-    if (fail) {
-      if (tid == 0) *info = 1;
-      return;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const int r = r0 + i, c = c0 + jj;
-      if (r < k && c < k) Ng[r * k + c] = a[i][jj];
-    }
-  if (tid == 0) *info = 0;
+  gj_inorder_tile(Ng, k, info);
 }
 
 }  // namespace

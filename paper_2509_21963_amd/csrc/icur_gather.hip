@@ -295,6 +295,44 @@ int launch_to_host(const HostSegs& segs, void* host_dev, hipStream_t st) {
   return ICUR_OK;
 }
 
+namespace {
+// Per-workgroup FP64 partial sums of a^2 over an m x n FP32 matrix (leading dimension
+// lda): workgroup g takes rows g, g + G, ...; threads stride the row with 4-element
+// loads where the row is aligned.  One partial per workgroup, in a fixed order.
+__global__ __launch_bounds__(256) void sumsq_f32_kernel(const float* __restrict__ A, int64_t m, int64_t n,
+                                                        int64_t lda, double* __restrict__ partials) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const float* row = A + i * lda;
+    const int64_t head = (reinterpret_cast<uintptr_t>(row) & 15) ? std::min<int64_t>(n, (16 - (reinterpret_cast<uintptr_t>(row) & 15)) / 4) : 0;
+    for (int64_t j = threadIdx.x; j < head; j += blockDim.x) acc += static_cast<double>(row[j]) * row[j];
+    const int64_t nv = (n - head) / 4;
+    const float4* v4 = reinterpret_cast<const float4*>(row + head);
+    for (int64_t j = threadIdx.x; j < nv; j += blockDim.x) {
+      const float4 v = v4[j];
+      acc += static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y + static_cast<double>(v.z) * v.z +
+             static_cast<double>(v.w) * v.w;
+    }
+    for (int64_t j = head + nv * 4 + threadIdx.x; j < n; j += blockDim.x) acc += static_cast<double>(row[j]) * row[j];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+}  // namespace
+
+int launch_sumsq_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* partials, int* nparts,
+                     hipStream_t st) {
+  if (m < 0 || n < 0 || (m > 0 && lda < n)) return arg_error("sum of squares: bad shape");
+  const int blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(m, kSumsqMaxParts)));
+  hipLaunchKernelGGL(sumsq_f32_kernel, dim3(blocks), dim3(256), 0, st, A, m, n, lda, partials);
+  ICUR_HIP(hipGetLastError());
+  *nparts = blocks;
+  return ICUR_OK;
+}
+
 int launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st) {
   if (n <= 0) return ICUR_OK;
   hipLaunchKernelGGL(fill_u8_kernel, dim3(blocks_for(n)), dim3(256), 0, st, p, n, v);

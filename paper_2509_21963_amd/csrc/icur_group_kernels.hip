@@ -1,0 +1,480 @@
+// Grouped kernels of the batched loop: every step of Alg. 1 for all unfinished matrices in
+// one launch.  A plan kernel turns the matrices' current state (rank r, pivots found nJ,
+// nI) into lists of products and gathers; persistent kernels walk those lists, so their
+// launch configuration never depends on the data (the same launches every iteration).
+//
+// Products are OUT(M x N) = beta X + alpha W(M x K) B(K x N) in FP64 on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64): tiles of 32 rows x 128 columns, the whole depth K per
+// tile in 32-deep chunks (W staged through LDS, B straight to registers), so the result
+// of every element is a fixed-order FP64 sum that does not depend on the grouping.
+#include <algorithm>
+#include <climits>
+
+#include "icur_batched.h"
+#include "icur_gj.h"
+
+namespace icur {
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPT = 256;           // threads of the product and gather kernels
+constexpr int kRowsT = 32;         // product tile rows (two 16-row MFMA tiles)
+constexpr int kColsT = 128;        // product tile columns (four waves x two 16-column tiles)
+constexpr int kKC = 32;            // K chunk
+constexpr int kGatherCols = 256;   // gather tile: one row x 256 columns
+
+struct GemmOp {
+  const double* X;  // may be null (beta = 0)
+  int64_t ldx;
+  const double* W;
+  int64_t ldw;
+  const double* B;
+  int64_t ldb;
+  double* OUT;
+  int64_t ldo;
+  int M, K, N, tiles_n;
+  double alpha;
+  double* normp;    // per-tile sums of OUT^2 (indexed by the op's local tile), or null
+  int tile0, pad;   // pad: the op's tile count while the plan is built
+};
+
+struct GatherOp {
+  const void* src;  // FP32 when f32, else FP64
+  int64_t rs, cs;   // src element strides per row index / column index
+  const int64_t* ridx;
+  const int64_t* cidx;
+  double* dst;
+  int64_t ldd;
+  int rows, cols, tiles_c, f32;
+  double scale;
+  int tile0, pad;   // pad: the op's tile count while the plan is built
+};
+
+// Stage lists of one iteration.  Phase 0 (after the column selection): gathers GA and
+// the row-residual product P1.  Phase 1 (after the row selection): gathers GB, products
+// P2 (with the core's Y and Z), P3 (with V), P4 (with the core update), copies GC.
+enum Stage { kGA, kP1, kGB, kP2, kP3, kP4, kGC, kNumStages };
+constexpr int kOpsPerMat = 6;
+
+struct Plan {
+  GemmOp* gemm[kNumStages];
+  GatherOp* gather[kNumStages];
+  int* nops;    // per stage
+  int* ntiles;  // per stage
+};
+
+__device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Ops occupy fixed slots (matrix i, slot k -> entry i * kOpsPerMat + k); an unused slot has
+// no tiles.  tile0 is filled in afterwards by a scan over the entries.
+__device__ __forceinline__ void set_gemm(GemmOp* ops, int i, int k, const double* X, int64_t ldx, const double* W,
+                                         int64_t ldw, const double* B, int64_t ldb, double* OUT, int64_t ldo, int M,
+                                         int K, int N, double alpha, double* normp) {
+  GemmOp& o = ops[i * kOpsPerMat + k];
+  o.X = X;
+  o.ldx = ldx;
+  o.W = W;
+  o.ldw = ldw;
+  o.B = B;
+  o.ldb = ldb;
+  o.OUT = OUT;
+  o.ldo = ldo;
+  o.M = M;
+  o.K = K;
+  o.N = N;
+  o.tiles_n = (M > 0 && N > 0) ? ceil_div(N, kColsT) : 0;
+  o.alpha = alpha;
+  o.normp = normp;
+  o.pad = (M > 0 && N > 0) ? ceil_div(M, kRowsT) * o.tiles_n : 0;  // tiles (until the scan)
+}
+
+__device__ __forceinline__ void set_gather(GatherOp* ops, int i, int k, const void* src, bool f32, int64_t rs,
+                                           int64_t cs, const int64_t* ridx, const int64_t* cidx, double* dst,
+                                           int64_t ldd, int rows, int cols, double scale) {
+  GatherOp& o = ops[i * kOpsPerMat + k];
+  o.src = src;
+  o.f32 = f32 ? 1 : 0;
+  o.rs = rs;
+  o.cs = cs;
+  o.ridx = ridx;
+  o.cidx = cidx;
+  o.dst = dst;
+  o.ldd = ldd;
+  o.rows = rows;
+  o.cols = cols;
+  o.tiles_c = (rows > 0 && cols > 0) ? ceil_div(cols, kGatherCols) : 0;
+  o.scale = scale;
+  o.pad = rows > 0 ? rows * o.tiles_c : 0;
+}
+
+// Exclusive scan of the per-slot tile counts (held in .pad) into .tile0, and the total.
+template <typename OP>
+__device__ void scan_tiles(OP* ops, int n, int* total, int* nops, int* warp_sums) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int carry = 0;
+  for (int base = 0; base < n; base += nt) {
+    const int e = base + tid;
+    const int v = e < n ? ops[e].pad : 0;
+    // inclusive scan within the workgroup: waves by shuffles, then the wave totals
+    int x = v;
+    const int lane = tid & 63, w = tid >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) warp_sums[w] = x;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < w; ++q) before += warp_sums[q];
+    int chunk_total = 0;
+    for (int q = 0; q < nt / 64; ++q) chunk_total += warp_sums[q];
+    if (e < n) ops[e].tile0 = carry + before + x - v;
+    carry += chunk_total;
+  }
+  if (tid == 0) {
+    *total = carry;
+    *nops = n;
+  }
+}
+
+// The lists of a phase, from every matrix's state.  Phase 0 (after the column selection):
+// GA, P1.  Phase 1 (after the row selection): GB, P2, P3, P4, GC.
+__global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats, int count, int c, int phase,
+                                                    Plan plan) {
+  __shared__ int warp_sums[16];
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    BatchMat& bm = mats[i];
+    const bool on = bm.s != 0;
+    const int r = bm.r, m = bm.m, n = bm.n, cap = bm.cap;
+    if (phase == 0) {
+      const int nJ = on ? bm.nJ : 0;
+      double* Lk = bm.LcT + static_cast<int64_t>(r) * m;
+      // GA: A(:, J_k)^T -> the next rows of LcT; Ur(:, J_k)^T -> Wa
+      set_gather(plan.gather[kGA], i, 0, bm.A, true, 1, bm.lda, bm.Jk, nullptr, Lk, m, nJ, m, 1.0);
+      set_gather(plan.gather[kGA], i, 1, bm.Ur, false, 1, n, bm.Jk, nullptr, bm.Wa, cap, nJ, r, 1.0);
+      for (int k = 2; k < kOpsPerMat; ++k) set_gather(plan.gather[kGA], i, k, nullptr, false, 0, 0, nullptr, nullptr, nullptr, 0, 0, 0, 0.0);
+      // P1: row residual S^row = A(:, J_k) - Lc Ur(:, J_k), stored transposed
+      set_gemm(plan.gemm[kP1], i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr);
+      for (int k = 1; k < kOpsPerMat; ++k) set_gemm(plan.gemm[kP1], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
+    } else {
+      const int nI = on ? bm.nI : 0;
+      const int nR = nI > 0 ? r : 0;  // the core's old block takes part from the second block on
+      const double* Lk = bm.LcT + static_cast<int64_t>(r) * m;
+      double* Urk = bm.Ur + static_cast<int64_t>(r) * n;
+      double* U = bm.U;
+      // GB: N_k = S(I_k, J_k); A(I_k, :); Lc(I_k, :); S(:, J_k); A(I, J_k); A(I_k, J)
+      set_gather(plan.gather[kGB], i, 0, Lk, false, 1, m, bm.Ik, nullptr, bm.Nk, nI, nI, nI, 1.0);
+      set_gather(plan.gather[kGB], i, 1, bm.A, true, bm.lda, 1, bm.Ik, nullptr, bm.Sr, n, nI, n, 1.0);
+      set_gather(plan.gather[kGB], i, 2, bm.LcT, false, 1, m, bm.Ik, nullptr, bm.Wa, cap, nI, nR, 1.0);
+      set_gather(plan.gather[kGB], i, 3, bm.S, false, n, 1, nullptr, bm.Jk, bm.Wc, nI, nI > 0 ? c : 0, nI, 1.0);
+      set_gather(plan.gather[kGB], i, 4, bm.A, true, bm.lda, 1, bm.Iall, bm.Jk, bm.AIJk, nI, nR, nI, 1.0);
+      set_gather(plan.gather[kGB], i, 5, bm.A, true, bm.lda, 1, bm.Ik, bm.Jall, bm.AIkJ, cap, nI, nR, 1.0);
+      // P2: residual at the new rows Sr -= Lc(I_k,:) Ur; the core's Y = U A(I,J_k), Z = A(I_k,J) U
+      set_gemm(plan.gemm[kP2], i, 0, bm.Sr, n, bm.Wa, cap, bm.Ur, n, bm.Sr, n, nR > 0 ? nI : 0, r, n, -1.0, nullptr);
+      set_gemm(plan.gemm[kP2], i, 1, nullptr, 0, U, cap, bm.AIJk, nI, bm.Y, nI, nR, r, nI, 1.0, nullptr);
+      set_gemm(plan.gemm[kP2], i, 2, nullptr, 0, bm.AIkJ, cap, U, cap, bm.Z, cap, nR > 0 ? nI : 0, r, r, 1.0, nullptr);
+      // P3: new row factors Ur_k = N_k^{-1} Sr; V = Y N_k^{-1}
+      set_gemm(plan.gemm[kP3], i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr);
+      set_gemm(plan.gemm[kP3], i, 1, nullptr, 0, bm.Y, nI, bm.Nk, nI, bm.V, nI, nR, nI, nI, 1.0, nullptr);
+      // P4: column residual S -= S(:, J_k) Ur_k (with its norm partials); the core's U += V Z
+      // and its new block row -N_k^{-1} Z
+      set_gemm(plan.gemm[kP4], i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp);
+      set_gemm(plan.gemm[kP4], i, 1, U, cap, bm.V, nI, bm.Z, cap, U, cap, nR, nI, r, 1.0, nullptr);
+      set_gemm(plan.gemm[kP4], i, 2, nullptr, 0, bm.Nk, nI, bm.Z, cap, U + static_cast<int64_t>(r) * cap, cap,
+               nR > 0 ? nI : 0, nI, r, -1.0, nullptr);
+      bm.nparts = plan.gemm[kP4][i * kOpsPerMat].pad;
+      // GC: the core's new block column -V, and N_k^{-1} in the corner
+      set_gather(plan.gather[kGC], i, 0, bm.V, false, nI, 1, nullptr, nullptr, U + r, cap, nR, nI, -1.0);
+      set_gather(plan.gather[kGC], i, 1, bm.Nk, false, nI, 1, nullptr, nullptr, U + static_cast<int64_t>(r) * cap + r,
+                 cap, nI, nI, 1.0);
+      for (int k = 2; k < kOpsPerMat; ++k) set_gather(plan.gather[kGC], i, k, nullptr, false, 0, 0, nullptr, nullptr, nullptr, 0, 0, 0, 0.0);
+      for (int k = 3; k < kOpsPerMat; ++k) {
+        set_gemm(plan.gemm[kP2], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
+        set_gemm(plan.gemm[kP4], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
+      }
+      for (int k = 2; k < kOpsPerMat; ++k)
+        set_gemm(plan.gemm[kP3], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
+    }
+  }
+  __syncthreads();
+  const int n = count * kOpsPerMat;
+  if (phase == 0) {
+    scan_tiles(plan.gather[kGA], n, plan.ntiles + kGA, plan.nops + kGA, warp_sums);
+    scan_tiles(plan.gemm[kP1], n, plan.ntiles + kP1, plan.nops + kP1, warp_sums);
+  } else {
+    scan_tiles(plan.gather[kGB], n, plan.ntiles + kGB, plan.nops + kGB, warp_sums);
+    scan_tiles(plan.gemm[kP2], n, plan.ntiles + kP2, plan.nops + kP2, warp_sums);
+    scan_tiles(plan.gemm[kP3], n, plan.ntiles + kP3, plan.nops + kP3, warp_sums);
+    scan_tiles(plan.gemm[kP4], n, plan.ntiles + kP4, plan.nops + kP4, warp_sums);
+    scan_tiles(plan.gather[kGC], n, plan.ntiles + kGC, plan.nops + kGC, warp_sums);
+  }
+}
+
+template <typename OP>
+__device__ __forceinline__ int find_op(const OP* ops, int nops, int tile) {
+  int lo = 0, hi = nops - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ops[mid].tile0 <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// dst[i][j] = scale * src[ridx[i] rs + cidx[j] cs] (identity where an index list is null)
+__global__ __launch_bounds__(kPT) void gather_kernel(const GatherOp* __restrict__ ops, const int* __restrict__ pnops,
+                                                     const int* __restrict__ pntiles) {
+  const int nops = *pnops, ntiles = *pntiles;
+  for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
+    const GatherOp& o = ops[find_op(ops, nops, g)];
+    const int lt = g - o.tile0;
+    const int i = lt / o.tiles_c;
+    const int j = (lt % o.tiles_c) * kGatherCols + threadIdx.x;
+    const int64_t ri = o.ridx ? o.ridx[i] : i;
+    double* d = o.dst + static_cast<int64_t>(i) * o.ldd;
+    for (int jj = j; jj < min(o.cols, j + kGatherCols); jj += kPT) {
+      const int64_t cj = o.cidx ? o.cidx[jj] : jj;
+      const int64_t e = ri * o.rs + cj * o.cs;
+      const double v = o.f32 ? static_cast<double>(static_cast<const float*>(o.src)[e])
+                             : static_cast<const double*>(o.src)[e];
+      d[jj] = o.scale * v;
+    }
+  }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kPT / 64; ++w) s += red[w];
+  return s;
+}
+
+// Persistent FP64 product over a list of ops.  Lane (lr, lg) of wave w: MFMA A operand
+// W[row lr][k 4j + lg], B operand B[k 4j + lg][column lr], accumulator slot v = row
+// 4 v + lg, column lr; the wave owns columns 32 w .. 32 w + 31 of the tile.
+__global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
+                                                   const int* __restrict__ pntiles) {
+  constexpr int kStride = kRowsT + 2;  // LDS row stride of the transposed W chunk
+  __shared__ double wl[kKC * kStride];
+  __shared__ double red[kPT / 64];
+  const int nops = *pnops, ntiles = *pntiles;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
+    const GemmOp& o = ops[find_op(ops, nops, g)];
+    const int lt = g - o.tile0;
+    const int m0 = (lt / o.tiles_n) * kRowsT;
+    const int n0 = (lt % o.tiles_n) * kColsT + wave * 32;
+    int col[2];
+    bool cok[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      col[s] = n0 + 16 * s + lr;
+      cok[s] = col[s] < o.N;
+      if (!cok[s]) col[s] = 0;
+    }
+    doublex4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) acc[t][s] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double b[8][2];
+    auto load_b = [&](int k0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + 4 * j + lg;
+        const bool kok = k < o.K;
+        const double* row = o.B + static_cast<int64_t>(kok ? k : 0) * o.ldb;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) b[j][s] = (kok && cok[s]) ? row[col[s]] : 0.0;
+      }
+    };
+    if (o.K > 0) load_b(0);
+    for (int k0 = 0; k0 < o.K; k0 += kKC) {
+      __syncthreads();  // the previous chunk's W reads are done
+      for (int e = threadIdx.x; e < kRowsT * kKC; e += kPT) {
+        const int row = e / kKC, kk = e % kKC;
+        const int gr = m0 + row, gk = k0 + kk;
+        wl[kk * kStride + row] = (gr < o.M && gk < o.K) ? o.W[static_cast<int64_t>(gr) * o.ldw + gk] : 0.0;
+      }
+      __syncthreads();
+      double bc[8][2];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) bc[j][s] = b[j][s];
+      if (k0 + kKC < o.K) load_b(k0 + kKC);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        double a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = wl[(4 * j + lg) * kStride + t * 16 + lr];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[t][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bc[j][s], acc[t][s], 0, 0, 0);
+      }
+    }
+    double sq = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + t * 16 + 4 * v + lg;
+        if (row >= o.M) continue;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          if (!cok[s]) continue;
+          double out = o.alpha * acc[t][s][v];
+          if (o.X) out = o.X[static_cast<int64_t>(row) * o.ldx + col[s]] + out;
+          o.OUT[static_cast<int64_t>(row) * o.ldo + col[s]] = out;
+          sq += out * out;
+        }
+      }
+    if (o.normp) {
+      const double tot = block_sum(sq, red);
+      if (threadIdx.x == 0) o.normp[lt] = tot;
+    }
+  }
+}
+
+// Pivot blocks N_k of every unfinished matrix inverted in place (rows already in
+// partial-pivoting order), one workgroup each.
+__global__ __launch_bounds__(256) void batch_inverse_kernel(BatchMat* __restrict__ mats, int count) {
+  if (static_cast<int>(blockIdx.x) >= count) return;
+  BatchMat* bm = mats + blockIdx.x;
+  if (bm->s == 0 || bm->nI == 0) return;
+  gj_inorder_tile(bm->Nk, bm->nI, &bm->info);
+}
+
+// End of an iteration, one workgroup per matrix: the column-residual norm (its tile
+// partials summed in a fixed order), the commit of the block, the stopping decision and
+// the record for the host.
+__global__ __launch_bounds__(256) void batch_end_kernel(BatchMat* __restrict__ mats, int count, int b,
+                                                        BatchRec* __restrict__ rec) {
+  __shared__ double red[4];
+  if (static_cast<int>(blockIdx.x) >= count) return;
+  BatchMat* bm = mats + blockIdx.x;
+  if (bm->s != 0) {
+    const int nJ = bm->nJ, nI = bm->nI;
+    if (nJ == 0 || nI == 0) {
+      if (threadIdx.x == 0) {
+        bm->status = ICUR_STALLED;
+        bm->s = 0;
+      }
+    } else if (bm->info != 0) {
+      if (threadIdx.x == 0) {
+        bm->status = ICUR_ERR_HIP;
+        bm->s = 0;
+      }
+    } else {
+      double v = 0.0;
+      for (int q = threadIdx.x; q < bm->nparts; q += 256) v += bm->normp[q];
+      const double tot = block_sum(v, red);
+      const int r = bm->r;
+      for (int t = threadIdx.x; t < nI; t += 256) {
+        const int64_t j = bm->Jk[t], i = bm->Ik[t];
+        bm->colmask[j] = 1;
+        bm->rowmask[i] = 1;
+        bm->Jall[r + t] = j;
+        bm->Iall[r + t] = i;
+      }
+      if (threadIdx.x == 0) {
+        const double rho = sqrt(tot / bm->denom2);
+        const int rn = r + nI;
+        bm->rho = rho;
+        bm->r = rn;
+        bm->iters += 1;
+        if (rho <= bm->thr) {
+          bm->status = ICUR_OK;
+          bm->s = 0;
+        } else if (rn >= bm->rmax) {
+          bm->status = ICUR_MAXRANK;
+          bm->s = 0;
+        } else {
+          bm->s = min(b, bm->rmax - rn);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BatchRec& o = rec[blockIdx.x];
+    o.r = bm->r;
+    o.s = bm->s;
+    o.status = bm->status;
+    o.info = bm->info;
+    o.iters = bm->iters;
+    o.rho = bm->rho;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host wrappers
+size_t batch_plan_bytes(int count) {
+  const size_t per = static_cast<size_t>(count) * kOpsPerMat;
+  return kNumStages * per * (sizeof(GemmOp) + sizeof(GatherOp)) + 2 * kNumStages * sizeof(int) + 512;
+}
+
+namespace {
+Plan bind_plan(void* ws, int count) {
+  Plan p;
+  char* q = static_cast<char*>(ws);
+  const size_t per = static_cast<size_t>(count) * kOpsPerMat;
+  for (int s = 0; s < kNumStages; ++s) {
+    p.gemm[s] = reinterpret_cast<GemmOp*>(q);
+    q += per * sizeof(GemmOp);
+    p.gather[s] = reinterpret_cast<GatherOp*>(q);
+    q += per * sizeof(GatherOp);
+  }
+  p.nops = reinterpret_cast<int*>(q);
+  p.ntiles = p.nops + kNumStages;
+  return p;
+}
+
+int gemm_stage(const Plan& p, int s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(gemm_kernel, dim3(grid), dim3(kPT), 0, st, p.gemm[s], p.nops + s, p.ntiles + s);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+int gather_stage(const Plan& p, int s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(kPT), 0, st, p.gather[s], p.nops + s, p.ntiles + s);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+}  // namespace
+
+// One iteration of Alg. 1 (residual form, with the bordered core) for every unfinished
+// matrix: 13 launches whose configuration depends only on count and the device.
+int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
+                           int grid, hipStream_t st) {
+  const Plan p = bind_plan(plan_ws, count);
+  ICUR_TRY(launch_batch_lupp(mats, count, false, 0.0, st));
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, 0, p);
+  ICUR_HIP(hipGetLastError());
+  ICUR_TRY(gather_stage(p, kGA, grid, st));
+  ICUR_TRY(gemm_stage(p, kP1, grid, st));
+  ICUR_TRY(launch_batch_lupp(mats, count, true, row_cut, st));
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, 1, p);
+  ICUR_HIP(hipGetLastError());
+  ICUR_TRY(gather_stage(p, kGB, grid, st));
+  hipLaunchKernelGGL(batch_inverse_kernel, dim3(count), dim3(256), 0, st, mats, count);
+  ICUR_HIP(hipGetLastError());
+  ICUR_TRY(gemm_stage(p, kP2, grid, st));
+  ICUR_TRY(gemm_stage(p, kP3, grid, st));
+  ICUR_TRY(gemm_stage(p, kP4, grid, st));
+  ICUR_TRY(gather_stage(p, kGC, grid, st));
+  hipLaunchKernelGGL(batch_end_kernel, dim3(count), dim3(256), 0, st, mats, count, b, rec);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
+}  // namespace icur

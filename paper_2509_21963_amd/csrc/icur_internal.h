@@ -112,6 +112,22 @@ int launch_split_f64(const double* src, int64_t rows, int64_t cols, int64_t lds,
 // Sum of per-block partials into out (device double, written in a fixed order).
 int launch_reduce_partials(const double* partials, int n, double* out, hipStream_t st);
 
+// Sketch accumulation: FP32 sums over 128 rows of A give X0 a relative noise near
+// sqrt(128) 2^-24; the column residual subtracts X0(:,J) times interpolation coefficients
+// whose norm reaches tens on ill-conditioned crosses, which puts a floor near 1e-5 under
+// rho.  Below this tolerance the sums are widened to FP64 after every 32 rows.
+constexpr double kSketchChunkFlushBelow = 1e-4;
+// BF16 pieces per FP32 operand of the split form for a tolerance (icur_api.hip).
+int terms_for_tol(double tol);
+// G drawn from (kind, seed, zeta) into G (c x ldg BF16), X0 = G A into S (c x n FP64,
+// leading dimension n) and ||X0||_F^2 into *normsq_dev (device).  terms: BF16 pieces of A
+// (1..3) or 0 for FP32 matrix cores; precise: FP64 flush every 32 rows.  partials holds
+// the norm partials (at least max(sketch_max_norm_partials, max_norm_partials)), ws the
+// product workspace.  ev_begin / ev_end (may be null) bracket the product kernel.
+int form_sketch(int kind, uint64_t seed, int64_t c, int64_t m, int64_t n, const float* A, int64_t lda, int zeta,
+                int terms, bool precise, uint16_t* G, int64_t ldg, double* S, double* partials, void* ws,
+                size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end);
+
 // ----- sparse input (icur_csr.hip) -----
 struct CsrMatrix {
   const int64_t* rowptr;  // m + 1
@@ -166,6 +182,12 @@ int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w);
 int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps,
                 const uint8_t* excluded, int64_t* piv, const LuppWork& w, hipStream_t st, double rel_cut = 0.0);
 
+// Pivots of QR with column pivoting on T = X^T (icur_qrcp.hip), same status words as
+// lupp_launch (status[0] pivots found); ws holds qrcp_workspace_bytes(K, N, 4 CUs).
+size_t qrcp_workspace_bytes(int64_t K, int64_t N, int groups);
+int qrcp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int steps, const uint8_t* excluded,
+                int64_t* piv, int* status, void* ws, size_t ws_bytes, hipStream_t st, double rel_cut = 0.0);
+
 // ----- gathers and small FP64 kernels (icur_gather.hip) -----
 int launch_gather_cols_T(const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols,
                          int64_t k, float* Ct, int64_t ldct, hipStream_t st);
@@ -211,6 +233,11 @@ int launch_to_host_flag(const HostSegs& segs, void* host_dev, unsigned* flag_dev
 int launch_commit_block(uint8_t* colmask, uint8_t* rowmask, const int64_t* Jk, const int64_t* Ik, int64_t k,
                         int64_t* Jall, int64_t* Iall, hipStream_t st);
 int launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
+// Per-workgroup FP64 partial sums of squares of an m x n FP32 matrix (ld lda): at most
+// kSumsqMaxParts partials (count in *nparts), summed by launch_reduce_partials.
+constexpr int kSumsqMaxParts = 1024;
+int launch_sumsq_f32(const float* A, int64_t m, int64_t n, int64_t lda, double* partials, int* nparts,
+                     hipStream_t st);
 int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 
 // ----- FP64 dense kernels (icur_core.hip) -----

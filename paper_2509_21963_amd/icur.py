@@ -19,6 +19,8 @@ OK, MAXRANK, STALLED = 0, 1, 2
 ERR_ARG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 GAUSSIAN, SPARSE_SIGN = 0, 1
 FP32, BF16_SPLIT = 0, 1
+DENOM_GA, DENOM_A = 0, 1
+LUPP, QRCP = 0, 1
 
 _STATUS_NAMES = {0: "ok", 1: "maxrank", 2: "stalled", -1: "bad argument",
                  -2: "non-finite input", -3: "out of device memory", -4: "HIP error",
@@ -36,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("max_rank", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("delta", ctypes.c_double),
                 ("split_terms", ctypes.c_int32), ("sketch_fp32", ctypes.c_int32),
-                ("residual_fp64", ctypes.c_int32), ("batch_workers", ctypes.c_int32)]
+                ("residual_fp64", ctypes.c_int32), ("batch_workers", ctypes.c_int32),
+                ("denominator", ctypes.c_int32), ("selection", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -46,13 +49,14 @@ class Info(ctypes.Structure):
                 ("ms_select", ctypes.c_double), ("ms_residual", ctypes.c_double),
                 ("ms_core", ctypes.c_double), ("ms_sketch_product", ctypes.c_double),
                 ("n_rho", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("rho", ctypes.c_double * 512)]
+                ("pad", ctypes.c_int32), ("rho", ctypes.c_double * 512),
+                ("block_sizes", ctypes.c_int32 * 512)]
 
 
 _lib = None
 EXPORTS = ["icur_run", "icur_run_csr", "icur_run_batched", "icur_last_info", "icur_last_error", "icur_release",
            "icur_make_sketch", "icur_sketch", "icur_lupp", "icur_residual", "icur_gather",
-           "icur_core_update", "icur_init_noalloc", "icur_lupp_noalloc"]
+           "icur_core_update", "icur_init_noalloc", "icur_lupp_noalloc", "icur_residual_f64", "icur_qrcp"]
 
 
 def load(path=LIB_PATH):
@@ -77,6 +81,8 @@ def load(path=LIB_PATH):
     lib.icur_lupp.argtypes = [P, I64, I64, I64, I32, P, P, ctypes.POINTER(I32), P]
     lib.icur_residual.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, I32, P, I64,
                                   ctypes.POINTER(D), P]
+    lib.icur_qrcp.argtypes = [P, I64, I64, I64, I32, P, P, ctypes.POINTER(I32), P]
+    lib.icur_residual_f64.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, P, I64, ctypes.POINTER(D), P]
     lib.icur_gather.argtypes = [P, I64, I64, I64, P, P, I64, P, I64, P, I64, P]
     lib.icur_core_update.argtypes = [P, I64, I64, I64, P, P, P, ctypes.POINTER(D), P]
     lib.icur_init_noalloc.argtypes = []
@@ -114,7 +120,8 @@ def _require(t, dtype, name):
 
 
 def run(A, tol, block, sketch_kind=GAUSSIAN, seed=0, precision=FP32, zeta=0, max_rank=0,
-        alpha=0.0, delta=0.0, split_terms=0, sketch_fp32=False, residual_fp64=0):
+        alpha=0.0, delta=0.0, split_terms=0, sketch_fp32=False, residual_fp64=0, denominator=DENOM_GA,
+        selection=LUPP):
     """icur_run on the m x n FP32 device tensor A.  Returns a dict with I, J (int64
     numpy arrays, selection order), U (rank x rank float64 numpy array), rank, rho
     (final estimate), status ("ok", "maxrank" or "stalled") and info (per-call
@@ -130,7 +137,7 @@ def run(A, tol, block, sketch_kind=GAUSSIAN, seed=0, precision=FP32, zeta=0, max
     rank = ctypes.c_int64(0)
     rho = ctypes.c_double(0.0)
     o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 1 if sketch_fp32 else 0,
-             int(residual_fp64), 0)
+             int(residual_fp64), 0, int(denominator), int(selection))
     st = lib.icur_run(_ptr(A), m, n, A.stride(0), float(tol), int(block), int(sketch_kind),
                       ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
                       I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
@@ -142,7 +149,8 @@ def run(A, tol, block, sketch_kind=GAUSSIAN, seed=0, precision=FP32, zeta=0, max
 
 
 def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, seed=0, precision=FP32,
-            zeta=0, max_rank=0, alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0):
+            zeta=0, max_rank=0, alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, denominator=DENOM_GA,
+            selection=LUPP):
     """icur_run_csr on device CSR arrays (rowptr int64, colind int32, vals float32) of an
     m x n matrix.  Returns the same dict as run()."""
     import torch
@@ -160,7 +168,8 @@ def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, se
     U = np.zeros(rmax * rmax, np.float64)
     rank = ctypes.c_int64(0)
     rho = ctypes.c_double(0.0)
-    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), 0)
+    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), 0,
+             int(denominator), int(selection))
     st = lib.icur_run_csr(_ptr(rowptr), _ptr(colind), _ptr(vals), m, n, nnz, float(tol), int(block),
                           int(sketch_kind), ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
                           I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
@@ -172,7 +181,8 @@ def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, se
 
 
 def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP32, zeta=0, max_rank=0,
-                alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, workers=0, check=True):
+                alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, workers=0, check=True,
+                denominator=DENOM_GA):
     """icur_run_batched on a list of m_i x n_i FP32 device tensors with per-matrix tolerances
     (and seeds, default 0..count-1).  Returns a list of dicts like run() (without info), each
     with its own "status"; raises on a failed matrix when check is True."""
@@ -203,7 +213,8 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
     rank = np.zeros(max(count, 1), np.int64)
     est = np.zeros(max(count, 1), np.float64)
     status = np.zeros(max(count, 1), np.int32)
-    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), int(workers))
+    o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), int(workers),
+             int(denominator))
     c_ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     st = lib.icur_run_batched(count, ptrs, c_ptr(m), c_ptr(n), c_ptr(lda), c_ptr(tol), int(block), int(sketch_kind),
                               c_ptr(sd), ctypes.byref(o), c_ptr(I), c_ptr(J), c_ptr(U), c_ptr(offs), c_ptr(rank),
@@ -222,8 +233,9 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
 def last_info():
     info = Info()
     load().icur_last_info(ctypes.byref(info))
-    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad")}
+    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "block_sizes")}
     d["rho"] = list(info.rho[:info.n_rho])
+    d["block_sizes"] = list(info.block_sizes[:info.n_rho])
     return d
 
 
@@ -277,6 +289,22 @@ def lupp(X, steps, excluded=None):
     return piv[:npiv.value].cpu().numpy()
 
 
+def qrcp(X, steps, excluded=None):
+    """icur_qrcp on the K x N FP32 device tensor X (candidates along N): returns the pivot
+    order as an int64 numpy array."""
+    import torch
+    lib = load()
+    _require(X, torch.float32, "X")
+    K, N = X.shape
+    piv = torch.zeros((steps,), dtype=torch.int64, device="cuda")
+    npiv = ctypes.c_int32(0)
+    if excluded is not None and (excluded.dtype != torch.uint8 or excluded.numel() != N):
+        raise ValueError("excluded must be a uint8 device tensor of length N")
+    _check(lib.icur_qrcp(_ptr(X), K, N, X.stride(0), steps, _ptr(excluded), _ptr(piv), ctypes.byref(npiv),
+                         _stream()))
+    return piv[:npiv.value].cpu().numpy()
+
+
 def lupp_noalloc(X, steps, piv, excluded=None):
     """icur_lupp_noalloc on the K x N FP32 device tensor X into the caller's int64 device
     tensor piv (capacity >= steps): the library allocates nothing.  Returns the pivot
@@ -312,6 +340,21 @@ def residual(X, W, B, terms):
     _check(lib.icur_residual(_ptr(X), X.stride(0) if X is not None else N, _ptr(W),
                              W.stride(0) if K > 0 else 1, _ptr(B), B.stride(0), M, K, N, terms,
                              _ptr(OUT), N, ctypes.byref(nsq), _stream()))
+    return OUT, nsq.value
+
+
+def residual_f64(X, W, B, out=None):
+    """icur_residual_f64: OUT = X - W B (FP64 device tensors; X may be `out` for in place,
+    or None for OUT = W B).  Returns (OUT, ||OUT||_F^2)."""
+    import torch
+    lib = load()
+    M, K = W.shape
+    N = B.shape[1]
+    OUT = out if out is not None else torch.empty((M, N), dtype=torch.float64, device="cuda")
+    nsq = ctypes.c_double(0.0)
+    _check(lib.icur_residual_f64(_ptr(X), X.stride(0) if X is not None else N, _ptr(W),
+                                 W.stride(0) if K > 0 else 1, _ptr(B), B.stride(0) if K > 0 else N,
+                                 M, K, N, _ptr(OUT), OUT.stride(0), ctypes.byref(nsq), _stream()))
     return OUT, nsq.value
 
 

@@ -58,6 +58,19 @@ def exact_lowrank(m, n, r, seed):
     return G1 @ G2.T
 
 
+def integer_spectrum(m, n, K, seed, emax=12, density=1.0):
+    """A = sum_k 2^e_k p_k q_k^T with p_k, q_k in {-1, 0, 1} (zero with probability
+    1 - density) and exponents e_k falling from emax to 0 over the K terms (FP64 holding
+    integers).  A has exact rank <= K and a decaying spectrum; with |a_ij| < 2^(8 T) its
+    entries are exact in T BF16 pieces, and its sketch with a +-1 operator is an exact
+    integer in FP32 while partial sums stay below 2^24."""
+    g = _rng(seed, 6)
+    e = emax - (np.arange(K) * (emax + 1)) // K
+    P = g.integers(-1, 2, (m, K)) * (g.random((m, K)) < density)
+    Q = g.integers(-1, 2, (n, K)) * (g.random((n, K)) < density)
+    return (P * (2.0 ** e)[None, :]) @ Q.T
+
+
 def rbf_points(m, n, seed, dim=3):
     """Seeded point sets x (m x dim) and y (n x dim), uniform on [0,1]^dim."""
     g = _rng(seed, 4)

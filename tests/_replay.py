@@ -1,0 +1,111 @@
+"""Pivot-by-pivot parity of a GPU run with the FP64 oracle (test helper, no tests here).
+
+The GPU's index blocks are replayed through the oracle (`iterative_cur(forced=...)`):
+at every LUPP step the oracle evaluates, along the GPU's own trajectory, the value of
+the candidate the GPU chose and the best and second-best eligible values.  Both sides
+carry rounding, so each value is known up to a noise bound `noise`:
+  * the GPU's choice is valid when   value >= best - 2 noise   (it lies in the tied set);
+  * the step is pinned when          second < best - 2 noise   (only the oracle's argmax
+    is valid, so validity means the GPU chose exactly the oracle's pivot).
+
+Noise bounds (absolute, per selection):
+  column steps: (eta + 4 cond 2^-52) max|X0|, with eta the sketch rounding of the form
+    relative to max|X0| (see sketch_eta) and cond = cond(A(I,J)) of the cross before
+    the block: the oracle forms S^col = X0 - X0(:,J) A(I,J)^+ A(I,:), whose rounding
+    grows with cond; the GPU's residual form does not, so the oracle's term dominates;
+  row steps: (eta_row + 4 sqrt(r + 1) cond 2^-52) max|A| (the row residual involves no
+    sketch and both sides form it in FP64 from the same FP32 values; eta_row covers the
+    opt-in FP32 residual factors).
+  With QRCP the compared values are residual 2-norms of K-vectors, so both bounds are
+  multiplied by sqrt(K).
+"""
+import math
+
+import numpy as np
+
+from oracle.icur import iterative_cur
+
+EPS64 = 2.0 ** -52
+EPS32 = 2.0 ** -24
+
+
+def sketch_eta(terms, chunk=128, sparse=False):
+    """Rounding of the GPU sketch relative to max|X0|, with a factor 16 of headroom.
+
+    Dense forms: each product of a BF16 piece sum with the BF16-valued G carries the
+    pieces' truncation, 2^-(8 T + 1) relative (T = 1, 2; three pieces are exact); FP32
+    sums over `chunk` rows add about sqrt(chunk) 2^-24 relative (random-walk growth of
+    the partial sums), FP64 across chunks.  The CSR sketch is FP64 throughout.
+    """
+    if sparse:
+        return 16 * 64 * EPS64
+    trunc = 0.0 if terms in (0, 3) else 2.0 ** -(8 * terms + 1)
+    return 16 * (trunc + math.sqrt(chunk) * EPS32)
+
+
+def blocks_of(rank, b, max_rank=None, sizes=None):
+    """Block sizes of a run: the reported ones, else b per block (the last one short)."""
+    if sizes:
+        assert sum(sizes) == rank
+        return list(sizes)
+    out, r = [], 0
+    cap = rank if max_rank is None else max_rank
+    while r < rank:
+        s = min(b, cap - r, rank - r)
+        out.append(s)
+        r += s
+    return out
+
+
+def replay(A64, I, J, blocks, tol, b, kind, seed, eta, zeta=8, selection="lupp",
+           denominator="GA", max_rank=None, eta_row=0.0, alpha=0.0):
+    """Replay the GPU's blocks through the oracle and check every pivot.
+
+    Returns (stats, rep) with stats = {"col_pinned", "col_tied", "row_pinned", "row_tied"}
+    and rep the oracle's replay.  Raises AssertionError at the first invalid choice.
+    """
+    I, J = [int(x) for x in I], [int(x) for x in J]
+    forced, o = [], 0
+    for s in blocks:
+        forced.append((J[o:o + s], I[o:o + s]))
+        o += s
+    assert o == len(I) == len(J)
+    rep = iterative_cur(A64, tol, b, kind=kind, seed=seed, zeta=zeta, forced=forced,
+                        selection=selection, denominator=denominator, max_rank=max_rank, alpha=alpha)
+    x0max = float(np.abs(rep["X0"]).max())
+    amax = float(np.abs(A64).max())
+    stats = {"col_pinned": 0, "col_tied": 0, "row_pinned": 0, "row_tied": 0}
+    cond, Ic, Jc = 1.0, [], []
+    for k, (Jk, Ik) in enumerate(forced):
+        h = rep["history"][k]
+        noise = {"col": (eta + 4 * cond * EPS64) * x0max,
+                 "row": (eta_row + 4 * math.sqrt(len(Ic) + 1) * cond * EPS64) * amax}
+        if selection == "qrcp":
+            # QRCP compares residual 2-norms of K-vectors: their error is up to sqrt(K)
+            # times an entry's
+            noise = {"col": noise["col"] * math.sqrt(rep["X0"].shape[0]),
+                     "row": noise["row"] * math.sqrt(len(Jk))}
+        for side, recs in (("col", h["col_replay"]), ("row", h["row_replay"])):
+            for t, rec in enumerate(recs):
+                lim = rec["best_value"] - 2 * noise[side]
+                assert rec["value"] >= lim, (
+                    "block %d %s step %d: GPU chose %d (|v| = %.6e), oracle's best %d (%.6e), "
+                    "noise %.3e" % (k, side, t, rec["pick"], rec["value"], rec["best"],
+                                    rec["best_value"], noise[side]))
+                if rec["second_value"] < lim:
+                    assert rec["pick"] == rec["best"]
+                    stats[side + "_pinned"] += 1
+                else:
+                    stats[side + "_tied"] += 1
+        Ic += Ik
+        Jc += Jk
+        cond = float(np.linalg.cond(A64[np.ix_(Ic, Jc)]))
+    return stats, rep
+
+
+def all_pinned(A64, ora, tol, b, kind, seed, eta, **kw):
+    """True when every step of the oracle's own run is pinned under the noise model of
+    `replay`: an input with well-separated pivots, whose whole index sets are unique."""
+    blocks = [len(h["I_k"]) for h in ora["history"]]
+    stats, _ = replay(A64, ora["I"], ora["J"], blocks, tol, b, kind, seed, eta, **kw)
+    return stats["col_tied"] == 0 and stats["row_tied"] == 0, stats

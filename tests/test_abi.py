@@ -42,10 +42,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     icur, _ = _lib()
-    # icur_opts: 2 x int32, int64, pointer, 2 x double, 4 x int32
-    assert ctypes.sizeof(icur.Opts) == 56
-    # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles
-    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8
+    # icur_opts: 2 x int32, int64, pointer, 2 x double, 6 x int32
+    assert ctypes.sizeof(icur.Opts) == 64
+    # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles, 512 x int32
+    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8 + 512 * 4
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation precedes device work
@@ -65,7 +65,7 @@ def _run_args(lib, m=10, n=8, lda=8, tol=1e-3, block=2, kind=0, opts=None):
 
 @pytest.mark.parametrize("kw", [
     dict(m=0), dict(n=0), dict(lda=7), dict(tol=0.0), dict(tol=float("nan")),
-    dict(tol=float("inf")), dict(block=0), dict(block=9), dict(kind=2),
+    dict(tol=float("inf")), dict(block=0), dict(block=9), dict(kind=3),
 ])
 def test_run_rejects_bad_arguments_before_device_work(kw):
     icur, lib = _lib()
@@ -80,9 +80,14 @@ def test_run_rejects_bad_options():
     for o in (icur.Opts(precision=5), icur.Opts(zeta=9), icur.Opts(split_terms=4),
               icur.Opts(max_rank=-1), icur.Opts(alpha=1e-10),     # c = 2 < -4 ln(alpha)
               icur.Opts(residual_fp64=2), icur.Opts(zeta=-1), icur.Opts(batch_workers=17),
-              icur.Opts(batch_workers=-1)):
+              icur.Opts(batch_workers=-1), icur.Opts(denominator=2), icur.Opts(denominator=-1),
+              icur.Opts(selection=2), icur.Opts(selection=-1)):
         st, _ = _run_args(lib, opts=ctypes.byref(o))
         assert st == icur.ERR_ARG, (o.precision, o.zeta)
+    # risk-aware stopping is for the Gaussian sketch (the section 3.3 Corollary)
+    o = icur.Opts(alpha=0.2)
+    st, _ = _run_args(lib, m=100, n=100, lda=100, block=20, kind=1, opts=ctypes.byref(o))
+    assert st == icur.ERR_ARG
     # sparse-sign needs c <= 255
     st, _ = _run_args(lib, m=300, n=300, lda=300, block=240, kind=1)
     assert st == icur.ERR_ARG

@@ -2,11 +2,10 @@
 
 The call is the one the benchmark times (tol 1e-4, b = 100, sparse-sign sketch with 8
 nonzeros per column, plain FP32 form, A resident on the device), and the oracle runs on
-the same matrix, copied to the host and widened to FP64.  Compared: the selected index
-sequences up to the oracle's first near tie, the first pivots' optimality, the rank and
-iteration count, the estimate,
-and the exact error ||A - CUR||_F / ||A||_F of the GPU's I, J, U (computed on the host
-in FP64, in row blocks).
+the same matrix, copied to the host and widened to FP64.  Compared: every pivot, replayed
+through the oracle along the GPU's trajectory (tests/_replay.py), the rank and iteration
+count, the estimate, and the exact error ||A - CUR||_F / ||A||_F of the GPU's I, J, U
+(computed on the host in FP64, in row blocks).
 """
 import numpy as np
 import pytest
@@ -16,7 +15,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from oracle.icur import iterative_cur                      # noqa: E402
+from oracle.lupp import lupp_replay                        # noqa: E402
 from paper_2509_21963_amd import workloads as W            # noqa: E402
+from _replay import replay, sketch_eta                     # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -26,20 +27,6 @@ def icur():
     from paper_2509_21963_amd import icur as m
     m.load()
     return m
-
-
-def _prefix(ora, margin):
-    pJ, pI = [], []
-    for h in ora["history"]:
-        for j, mg in zip(h["J_k"], h["col_margins"]):
-            if mg < margin:
-                return pJ, pI
-            pJ.append(j)
-        for i, mg in zip(h["I_k"], h["row_margins"]):
-            if mg < margin:
-                return pJ, pI
-            pI.append(i)
-    return pJ, pI
 
 
 def _relative_error_blocked(A64, I, J, U, rows=4000):
@@ -59,21 +46,16 @@ def test_rbf_40000_matches_oracle(icur):
     A64 = A.cpu().numpy().astype(np.float64)
     del A
     torch.cuda.empty_cache()
-    ora = iterative_cur(A64, 1e-4, 100, kind=1, seed=0, zeta=8, record=True)
     I, J = got["I"].tolist(), got["J"].tolist()
     assert got["status"] == "ok"
-    assert got["rank"] == ora["rank"]
-    assert got["info"]["iterations"] == len(ora["history"])
-    # unique part: the choices up to the oracle's first near tie (neighbouring points of
-    # a smooth kernel give near ties from the first step on, so this prefix may be empty)
-    pJ, pI = _prefix(ora, 1e-3)
-    assert J[:len(pJ)] == pJ and I[:len(pI)] == pI
-    # validity of the first pivots, a tie or not: the first column pivot maximises
-    # |X0(0, j)| and the first row pivot maximises |A(i, J_0)| up to rounding
-    X0 = ora["X0"]
-    assert abs(X0[0, J[0]]) >= (1 - 1e-6) * np.abs(X0[0]).max()
-    assert abs(A64[I[0], J[0]]) >= (1 - 1e-6) * np.abs(A64[:, J[0]]).max()
-    assert 0.8 <= got["rho"] / ora["rho"] <= 1.25
+    # every pivot along the GPU's trajectory; the replay goes on selecting if its own
+    # estimate is still above tol, so equal ranks mean the stopping points agree
+    stats, rep = replay(A64, I, J, got["info"]["block_sizes"], 1e-4, 100, 1, 0, sketch_eta(3, 128))
+    print("pivot parity", stats)
+    assert stats["col_pinned"] > 0 and stats["row_pinned"] > 0
+    assert got["rank"] == rep["rank"]
+    assert got["info"]["iterations"] == len(rep["history"])
+    assert 0.8 <= got["rho"] / rep["rho"] <= 1.25
     err = _relative_error_blocked(A64, I, J, got["U"])
     assert err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
 
@@ -87,29 +69,63 @@ def test_precision_form_60000x40000_matches_oracle(icur):
     A64 = A.cpu().numpy().astype(np.float64)
     del A
     torch.cuda.empty_cache()
-    ora = iterative_cur(A64, tol, b, kind=0, seed=0, record=True)
     I, J = got["I"].tolist(), got["J"].tolist()
     assert got["status"] == "ok" and got["info"]["split_terms"] == 2
-    assert got["rank"] == ora["rank"]
-    assert got["info"]["iterations"] == len(ora["history"])
-    # BF16 pieces agree with the FP64 oracle on pivots whose margin exceeds 1e-2
-    pJ, pI = _prefix(ora, 1e-2)
-    assert J[:len(pJ)] == pJ and I[:len(pI)] == pI
-    X0 = ora["X0"]
-    assert abs(X0[0, J[0]]) >= (1 - 1e-2) * np.abs(X0[0]).max()
-    assert 0.5 <= got["rho"] / ora["rho"] <= 2.0
+    stats, rep = replay(A64, I, J, got["info"]["block_sizes"], tol, b, 0, 0, sketch_eta(2, 128))
+    print("pivot parity", stats)
+    assert stats["col_pinned"] > 0 and stats["row_pinned"] > 0
+    assert got["rank"] == rep["rank"]
+    assert got["info"]["iterations"] == len(rep["history"])
+    assert 0.5 <= got["rho"] / rep["rho"] <= 2.0
     err = _relative_error_blocked(A64, I, J, got["U"])
     assert err <= 2 * tol and 0.5 <= got["rho"] / err <= 2.0
+
+
+def test_precision_form_60000x40000_tol_1e5_sampled(icur):
+    # the same matrix at tol 1e-5 (three BF16 pieces, rank about 4096 in 32 iterations).
+    # The oracle's full replay would take an SVD of every cross up to 4096 x 4096, so the
+    # run is checked through what the oracle computes piece by piece: the first column
+    # block (LUPP replay on the oracle's X0 = G A), the first row block (LUPP replay on
+    # A(:, J_1)), and the exact error on 1000 sampled rows.
+    from oracle.rng import make_G
+    m, n, b, tol = 60000, 40000, 128, 1e-5
+    A = W.precision_form_device(m, n, seed=0)
+    torch.cuda.synchronize()
+    got = icur.run(A, tol, b, icur.GAUSSIAN, seed=0, precision=icur.BF16_SPLIT)
+    A64 = A.cpu().numpy().astype(np.float64)
+    del A
+    torch.cuda.empty_cache()
+    I, J, U = got["I"].tolist(), got["J"].tolist(), got["U"]
+    r = got["rank"]
+    assert got["status"] == "ok" and got["rho"] <= tol and got["info"]["split_terms"] == 3
+    assert len(set(I)) == r and len(set(J)) == r
+    s1 = got["info"]["block_sizes"][0]
+    X0 = make_G(0, (11 * b) // 10, m, 0) @ A64
+    noise = sketch_eta(3, 32) * np.abs(X0).max()
+    pinned = [0, 0]
+    for side, recs, nz in ((0, lupp_replay(X0.T, J[:s1]), noise),
+                           (1, lupp_replay(A64[:, J[:s1]], I[:s1]), 4 * 2.0 ** -52 * np.abs(A64).max())):
+        for rec in recs:
+            lim = rec["best_value"] - 2 * nz
+            assert rec["value"] >= lim, (side, rec)
+            pinned[side] += rec["second_value"] < lim
+    print("first-block pivots pinned (columns, rows):", pinned)
+    assert pinned[0] > 0 and pinned[1] > 0
+    S = np.random.default_rng(0).choice(m, 1000, replace=False)
+    R = U @ A64[I, :]
+    AS = A64[S]
+    E = AS - AS[:, J] @ R
+    assert np.linalg.norm(E) <= 2 * tol * np.linalg.norm(AS)
 
 
 def test_csr_200000x100000_full_size(icur):
     # the sparse low-rank-plus-noise CSR matrix at full size (about 1.04e8 entries), BF16-split
     # form, tol 1e-6, block 64.  The dense oracle cannot hold it, so its results are checked
     # at this size through what the oracle computes one piece at a time: the first column
-    # selection (LUPP on the oracle's own sketch X0 = G A, formed with a sparse product),
-    # the core against the exact cross A(I,J), and the exact error on sampled rows.
+    # and row selections (replayed on the oracle's own sketch X0 = G A, formed with a sparse
+    # product, and on A(:, J_1)), the core against the exact cross A(I,J), and the exact
+    # error on sampled rows.
     import scipy.sparse as sp
-    from oracle.lupp import lupp_pivots
     from oracle.rng import make_G
     m, n, b, tol = 200000, 100000, 64, 1e-6
     A = W.sparse_lowrank(m, n, seed=0)
@@ -123,15 +139,22 @@ def test_csr_200000x100000_full_size(icur):
     I, J, U = got["I"].tolist(), got["J"].tolist(), got["U"]
     assert got["status"] == "ok" and got["rho"] <= tol
     assert 300 <= r <= 384 and len(set(I)) == r and len(set(J)) == r   # true rank 300
-    # first column block: LUPP on the oracle's sketch
+    # first block: LUPP replays on the oracle's sketch X0 = G A (a sparse product) and on
+    # A(:, J_1); the CSR sketch is FP64, so the noise bounds are FP64 rounding
     c = (11 * b) // 10
     G = make_G(0, c, m, 1, zeta=8)
     X0 = np.asarray((A.T @ G.T).T)
-    J1, margins = lupp_pivots(X0.T, b, return_margins=True)
-    k = 0
-    while k < len(J1) and margins[k] >= 1e-2:
-        k += 1
-    assert k >= 8 and J[:k] == list(J1[:k])
+    s1 = got["info"]["block_sizes"][0]
+    AJ = A[:, J[:s1]].toarray()
+    pinned = [0, 0]
+    for side, recs, nz in ((0, lupp_replay(X0.T, J[:s1]), sketch_eta(3, sparse=True) * np.abs(X0).max()),
+                           (1, lupp_replay(AJ, I[:s1]), 4 * 2.0 ** -52 * np.abs(AJ).max())):
+        for rec in recs:
+            lim = rec["best_value"] - 2 * nz
+            assert rec["value"] >= lim, (side, rec)
+            pinned[side] += rec["second_value"] < lim
+    print("first-block pivots pinned (columns, rows):", pinned)
+    assert pinned[0] >= 8 and pinned[1] >= 8
     # the core is the inverse of the cross
     C = A[I][:, J].toarray()
     resid = np.abs(C @ U - np.eye(r)).max()

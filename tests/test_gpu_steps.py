@@ -6,8 +6,11 @@ compared element by element with the oracle on the same inputs:
   G A                   within the FP32 accumulation bound (+ BF16 piece truncation)
   LUPP pivots           bit-exact pivot order (FP64 on both sides, same operation order)
   gathers               bit-exact copies
-  residual products     within the FP32 / BF16-piece bound
-  FP64 core update      within FP64 rounding times the block's condition number
+  residual products     within the FP32 / BF16-piece bound; the FP64 products the loop
+                        runs by default (both the library route and the short-M kernel)
+                        within the FP64 accumulation bound
+  FP64 core update      the oracle's pseudo-inverse within FP64 rounding times the
+                        block's condition number
 Sizes span several tiles and a ragged tail.
 """
 import numpy as np
@@ -17,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+from oracle.icur import pinv_svd                           # noqa: E402
 from oracle.lupp import lupp_pivots                        # noqa: E402
 from oracle.rng import gaussian_G, sparse_sign_pattern, sparse_sign_G  # noqa: E402
 
@@ -204,19 +208,119 @@ def test_residual_product(icur, terms, M, K, N):
     assert nsq == pytest.approx(float((got ** 2).sum()), rel=1e-12)
 
 
+@pytest.mark.parametrize("M,K,N,inplace", [
+    (110, 100, 40000, True),    # column residual shape of the 40000^2 run: library route (wide rows)
+    (128, 512, 3001, True),     # deep products of tall blocks: library route
+    (128, 512, 3001, False),    # same shape with a separate X: short-M kernel
+    (100, 0, 700, True),        # empty depth
+    (32, 700, 5000, True),      # short blocks stay on the short-M kernel
+    (35, 33, 8191, False),      # ragged tails
+    (140, 128, 40000, None),    # plain product OUT = W B (Ur_k = N_k^{-1} S(I_k,:))
+])
+def test_residual_product_fp64(icur, M, K, N, inplace):
+    # the default residual-form arithmetic: FP64 factors and FP64 output; exact products
+    # summed in FP64, so |error| <= (K + 2) 2^-52 (|X| + |W| |B|) elementwise
+    rng = np.random.default_rng(M * 7 + K + N)
+    W = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    X = rng.standard_normal((M, N))
+    Wd, Bd = dev(W), dev(B)
+    if inplace is None:
+        out, nsq = icur.residual_f64(None, Wd, Bd)
+        want = W @ B
+        bound = (K + 2) * 2.0 ** -52 * (np.abs(W) @ np.abs(B))
+    else:
+        Xd = dev(X)
+        out, nsq = icur.residual_f64(Xd, Wd, Bd, out=Xd if inplace else None)
+        want = X - W @ B
+        bound = (K + 2) * 2.0 ** -52 * (np.abs(X) + np.abs(W) @ np.abs(B))
+    got = out.cpu().numpy()
+    assert np.all(np.abs(got - want) <= bound)
+    assert nsq == pytest.approx(float((got ** 2).sum()), rel=1e-12)
+
+
+# ----------------------------------------------------------------- QRCP selection
+@pytest.mark.parametrize("K,N,steps,excl_frac,seed", [
+    (55, 1500, 50, 0.0, 0), (110, 40000, 100, 0.01, 1), (16, 257, 16, 0.0, 2), (1, 40, 1, 0.0, 3),
+    (35, 8000, 32, 0.1, 4), (140, 5000, 128, 0.0, 5)])
+def test_qrcp_pivots_match_oracle(icur, K, N, steps, excl_frac, seed):
+    # generic inputs (norm ties only at rounding level): the pivot order of the GPU's
+    # orthogonalised residuals equals the oracle's Householder QRCP
+    from oracle.qrcp import qrcp_pivots
+    rng = np.random.default_rng(seed)
+    X = (rng.standard_normal((K, N)) * np.exp(rng.standard_normal(N))[None, :]).astype(np.float32)
+    ex = rng.random(N) < excl_frac
+    exd = dev(ex.astype(np.uint8)) if excl_frac else None
+    got = icur.qrcp(dev(X), steps, exd).tolist()
+    want = qrcp_pivots(X.astype(np.float64).T, steps, exclude=np.nonzero(ex)[0].tolist())
+    assert got == want
+
+
+def test_qrcp_degenerate_inputs(icur):
+    # three nonzero candidates among zeros: the selection ends after them
+    X = np.zeros((5, 30), np.float32)
+    X[:, [4, 9, 20]] = np.random.default_rng(0).standard_normal((5, 3)).astype(np.float32)
+    assert sorted(icur.qrcp(dev(X), 5).tolist()) == [4, 9, 20]
+    # equal norms: the lowest index
+    E = np.hstack([np.eye(3), np.eye(3)]).astype(np.float32)
+    assert icur.qrcp(dev(E), 3).tolist() == [0, 1, 2]
+
+
 # ----------------------------------------------------------------- FP64 core update
 @pytest.mark.parametrize("r,k", [(0, 5), (40, 10), (150, 64), (300, 128), (64, 130)])
 def test_core_update_block_inverse(icur, r, k):
+    # the bordered core against the oracle's core (the SVD pseudo-inverse of the whole
+    # cross, which it recomputes every iteration): both are backward stable, so they
+    # differ by a few cond 2^-52 relative
     rng = np.random.default_rng(r + k)
     n = r + k
     M = rng.standard_normal((n, n)) + 4 * np.sqrt(n) * np.eye(n)   # well conditioned
     A11, A12, A21, A22 = M[:r, :r], M[:r, r:], M[r:, :r], M[r:, r:]
     Ucap = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    U11 = pinv_svd(A11) if r else np.zeros((0, 0))
     if r:
-        Ucap[:r, :r] = torch.from_numpy(np.linalg.inv(A11)).cuda()
-    Y = np.linalg.inv(A11) @ A12 if r else np.zeros((0, k))
+        Ucap[:r, :r] = torch.from_numpy(U11).cuda()
+    Y = U11 @ A12 if r else np.zeros((0, k))
     icur.core_update(Ucap, r, k, dev(Y), dev(A21), dev(A22))
     got = Ucap.cpu().numpy()
-    want = np.linalg.inv(M)
+    want = pinv_svd(M)
     kappa = np.linalg.cond(M)
-    assert np.abs(got - want).max() <= 1e-13 * kappa * np.abs(want).max() * n
+    assert np.abs(got - want).max() <= 16 * n * kappa * 2.0 ** -52 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("case", ["cond1e2", "cond1e6", "lupp_cross"])
+def test_core_update_chain_matches_oracle_recompute(icur, case):
+    # grow the core block by block, as the loop would, and compare with the oracle's
+    # pseudo-inverse recomputed from scratch at every size.  Random crosses of condition
+    # 1e2 and 1e6, and the cross the oracle's own selections build on a planted spectrum
+    # decaying to 1e-9 (its rows and columns in selection order, the order the loop borders
+    # in): there the Schur complements stay well scaled although the cross is not.
+    if case == "lupp_cross":
+        from oracle.icur import iterative_cur
+        from paper_2509_21963_amd import workloads as W
+        A, _ = W.planted_geometric(600, 500, 22.0, seed=3)
+        ora = iterative_cur(A, 1e-9, 40, seed=1)
+        M = A[np.ix_(ora["I"], ora["J"])]
+        n, k = M.shape[0], 40
+    else:
+        cond_target = 1e2 if case == "cond1e2" else 1e6
+        rng = np.random.default_rng(int(np.log10(cond_target)))
+        n, k = 200, 40
+        Q1, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        M = (Q1 * np.logspace(0, -np.log10(cond_target), n)) @ Q2.T
+    Ucap = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    for r in range(0, n, k):
+        kk = min(k, n - r)
+        A12, A21, A22 = M[:r, r:r + kk], M[r:r + kk, :r], M[r:r + kk, r:r + kk]
+        Ucur = Ucap[:r, :r].cpu().numpy()
+        icur.core_update(Ucap, r, kk, dev(Ucur @ A12 if r else np.zeros((0, kk))), dev(A21), dev(A22))
+        sub = M[:r + kk, :r + kk]
+        want = pinv_svd(sub)
+        got = Ucap[:r + kk, :r + kk].cpu().numpy()
+        kappa = np.linalg.cond(sub)
+        # each update adds about n kappa 2^-52 |U| and carries the earlier error on, so
+        # the bound grows with the number of blocks
+        blocks = r // k + 1
+        assert np.abs(got - want).max() <= 16 * n * blocks * kappa * 2.0 ** -52 * np.abs(want).max(), (r, kappa)
+    print("core chain %s: %d blocks, final cond %.2e" % (case, blocks, kappa))
