@@ -1,33 +1,25 @@
 """Time-to-tolerance benchmark of IterativeCUR on one MI355X.
 
-Default workload: the dense RBF kernel matrix A_ij = exp(-||x_i - y_j||^2 / (2 * 0.5^2)),
-40000 x 40000, x_i, y_j seeded U[0,1]^3, stored FP32 in HBM; tolerance 1e-4, block
-b = 100 (c = 110 sketch rows), sparse-sign sketch with 8 nonzeros per column, plain FP32
-form.  One step is one complete icur_run call (sketch, every selection and residual
-iteration until rho <= tol, and the FP64 core), with A already resident on the device.
-
-Prints one JSON line (the contract described in the repository's design doc):
-  value        mean time-to-tolerance over the timed steps, seconds (lower is better)
-  roofline     the sketch product (the dominant kernel) against HBM bandwidth, from
-               device events around its launches inside the timed calls
-  cpu_baseline the FP64 NumPy oracle timed on the host cores, one run on the same
-               matrix (copied from the device and widened to FP64)
-Other workloads (each prints its own line; the default is the one above):
-  --workload batched   the uneven batch: 512 planted FP32 matrices, m, n uniform in
-                       [500, 8000], sigma_i = exp(-i / r0) with r0 uniform in [10, 400],
-                       tol log-uniform in [1e-6, 1e-2], block 32, Gaussian sketch; value =
-                       time-to-tolerance of the whole batch through icur_run_batched, beside
-                       the same matrices through one icur_run call each (plain FP32 loop)
-  --workload precision the precision form: A = P diag((1+i)^-2) Q^T + E, 60000 x 40000
-                       FP32 (K = 4096 planted terms, ||E||_F = 1e-9 ||A||_F), block 128,
-                       Gaussian sketch, tol 1e-3 and 1e-5; value = BF16-split time-to-tol at
-                       1e-3, beside the plain FP32 form and both forms at 1e-5
-  --workload csr       the sparse form: A = P Q + E as CSR FP32, 200000 x 100000 (P with 5,
-                       Q with 100 Gaussian entries per row over 300 latent dimensions, E with
-                       20 entries of size 1e-8 per row), tol 1e-6, block 64, sparse-sign
-                       sketch; value = BF16-split time-to-tol, beside the plain FP32 form
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--form fp32|bf16]
-                       [--workload rbf|batched|precision|csr] [--count N]
+Default workload (the metric's headline comparison): the uneven batch, 512 planted FP32
+matrices A = P diag(sigma) Q^T with m, n uniform in [500, 8000], sigma_i = exp(-i / r0),
+r0 uniform in [10, 400], per-matrix tolerance log-uniform in [1e-6, 1e-2], block 32,
+Gaussian sketch.  One step is one icur_run_batched call on the whole batch (the grouped
+form: every matrix advanced together, one launch per step of Alg. 1), with all matrices
+resident in HBM.  Beside it, in the same line:
+  plain_loop_s          the same 512 matrices through one icur_run call each (the plain
+                        FP32 form, one matrix at a time), and the speed-up over it;
+  precision_form        the 60000 x 40000 precision-form matrix (block 128, Gaussian
+                        sketch) at tol 1e-3 and 1e-5, BF16-split against plain FP32.
+  roofline              the grouped FP64 product kernel of the batched loop (the kernel
+                        with the most device time), algorithmic bytes over its duration
+                        from device events inside the timed calls, against HBM;
+  cpu_baseline          the FP64 NumPy oracle on randomly drawn matrices of the batch
+                        (about 20 s of host time), scaled by count / drawn.
+Other workloads (--workload): rbf (40000 x 40000 RBF kernel, tol 1e-4, block 100,
+sparse-sign sketch, plain FP32), precision (the 60000 x 40000 form alone), csr (the
+200000 x 100000 sparse form), each printing its own line with the same fields.
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--workload batched|rbf|precision|csr] [--count N] [--workers W]
 """
 import argparse
 import hashlib
@@ -92,8 +84,39 @@ def oracle_threads():
         return os.cpu_count() or 1
 
 
+def precision_runs(A, steps, warmup, b=128):
+    """The precision-form matrix at tol 1e-3 and 1e-5: BF16-split against plain FP32."""
+    import torch
+    from paper_2509_21963_amd import icur
+    runs = {}
+    for tol in (1e-3, 1e-5):
+        for form, prec in (("bf16", icur.BF16_SPLIT), ("fp32", icur.FP32)):
+            for i in range(warmup):
+                icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
+            torch.cuda.synchronize()
+            times, outs = [], []
+            for i in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                outs.append(out)
+            last = outs[-1]
+            key = "%s@%g" % (form, tol)
+            runs[key] = {
+                "s": statistics.median(times), "rank": last["rank"], "rho": last["rho"],
+                "iterations": last["info"]["iterations"], "split_terms": last["info"]["split_terms"],
+                "sketch_ms": statistics.mean(o["info"]["ms_sketch_product"] for o in outs)}
+            print("precision form %s tol %g: %.2f ms, rank %d, rho %.3e" % (
+                form, tol, runs[key]["s"] * 1e3, last["rank"], last["rho"]), file=sys.stderr, flush=True)
+    return runs
+
+
 def bench_batched(a):
-    """The uneven batch through icur_run_batched, and through one icur_run per matrix."""
+    """The uneven batch through icur_run_batched (grouped form), beside one icur_run per
+    matrix (the plain FP32 loop) and the precision form's BF16-split / FP32 pair."""
+    import random
     import numpy as np
     import torch
     from paper_2509_21963_amd import icur
@@ -101,91 +124,114 @@ def bench_batched(a):
 
     icur.load()
     b = 32
+    c = (11 * b) // 10
     specs = W.batch_specs(a.count, seed=0)
     print("generating %d planted matrices on the device" % a.count, file=sys.stderr, flush=True)
     As = []
     for i, sp in enumerate(specs):
         As.append(W.planted_device(sp["m"], sp["n"], W.batch_sigma(sp["r0"], sp["K"]), seed=i))
-        if (i + 1) % 64 == 0:
+        if (i + 1) % 128 == 0:
             torch.cuda.synchronize()
             print("  %d generated" % (i + 1), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tols = [sp["tol"] for sp in specs]
     seeds = list(range(a.count))
     elems = float(sum(sp["m"] * sp["n"] for sp in specs))
-    # warm-up: one batched call (sizes every worker's workspace) and single calls on the
-    # four largest matrices (sizes the single-call workspace)
-    for _ in range(a.warmup):
+    for w in range(a.warmup):
         icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
-        print("batched warm-up done", file=sys.stderr, flush=True)
-    order = sorted(range(a.count), key=lambda i: -specs[i]["m"] * specs[i]["n"])
-    if a.warmup:
-        for i in order[:4]:
-            icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i])
+        print("batched warm-up %d done" % w, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    tb = []
+    tb, infos = [], []
     for s in range(a.steps):
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         got = icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t0)
+        infos.append(icur.last_info())
         print("batched step %d: %.3f s" % (s, tb[-1]), file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    plain, sk_ms, sk_bytes = [], 0.0, 0.0
-    for i in range(a.count):
-        out = icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i])
-        plain.append(out)
-        sk_ms += out["info"]["ms_sketch_product"]
-        m, n = As[i].shape
-        c = (11 * b) // 10
-        sk_bytes += 4.0 * m * n + 2.0 * c * m + 8.0 * c * n
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    print("plain loop: %.3f s" % t_plain, file=sys.stderr, flush=True)
-    same = all(g["rank"] == p["rank"] and np.array_equal(g["I"], p["I"]) and np.array_equal(g["J"], p["J"])
-               for g, p in zip(got, plain))
+    # the plain FP32 loop: one icur_run per matrix, once (its workspace is sized by a first
+    # call on the largest matrix)
+    if a.no_plain:
+        plain, t_plain = got, float("nan")
+    else:
+        big = max(range(a.count), key=lambda i: specs[i]["m"] * specs[i]["n"])
+        icur.run(As[big], tols[big], b, icur.GAUSSIAN, seeds[big])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = [icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i]) for i in range(a.count)]
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        print("plain loop: %.3f s" % t_plain, file=sys.stderr, flush=True)
     ranks = [g["rank"] for g in got]
+    same_rank = sum(1 for g, p in zip(got, plain) if g["rank"] == p["rank"])
+    same_idx = sum(1 for g, p in zip(got, plain) if np.array_equal(g["I"], p["I"]) and np.array_equal(g["J"], p["J"]))
     value = statistics.median(tb)
-    achieved = sk_bytes / (sk_ms * 1e-3) / 1e9 if sk_ms > 0 else None
+    inf = infos[-1]
+    # roofline of the grouped FP64 product kernel: algorithmic bytes over its device time
+    # (events around every product launch of the timed call)
+    prod_ms = statistics.mean(i["ms_products"] for i in infos)
+    prod_bytes = statistics.mean(i["product_bytes"] for i in infos)
+    achieved = prod_bytes / (prod_ms * 1e-3) / 1e9 if prod_ms > 0 else None
     line = {
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": value * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f64", "data": "synthetic",
         "config": {
             "workload": "uneven batch: %d planted FP32 matrices, m,n ~ U{500..8000}, sigma_i = exp(-i/r0), "
-                        "r0 ~ U[10,400], tol ~ 10^U[-6,-2], block 32, Gaussian sketch, fp32 form" % a.count,
-            "count": a.count, "elements": elems, "block": b, "workers": a.workers or 16,
+                        "r0 ~ U[10,400], tol ~ 10^U[-6,-2], block 32, Gaussian sketch; grouped batched form "
+                        "(every matrix advanced together) against one icur_run per matrix" % a.count,
+            "count": a.count, "elements": elems, "block": b, "form": "grouped" if not a.workers else "workers",
             "plain_loop_s": t_plain, "speedup_vs_plain_loop": t_plain / value,
-            "identical_to_plain_loop": bool(same),
+            "same_rank_as_plain_loop": same_rank, "same_indices_as_plain_loop": same_idx,
             "rank_min": min(ranks), "rank_median": statistics.median(ranks), "rank_max": max(ranks),
             "statuses": {k: sum(1 for g in got if g["status"] == k) for k in set(g["status"] for g in got)},
+            "grouped_iterations": inf["group_iterations"], "sketch_phase_ms": inf["ms_sketch"],
+            "select_ms": inf["ms_select"], "products_ms": inf["ms_products"],
+            "buffer_setup_ms": inf["ms_sketch_product"], "iterations_host_ms": inf["ms_residual"],
+            "results_copy_ms": inf["ms_core"],
         },
         "roofline": {
-            "kernel": "sketch product G A over the batch (sketch_kernel, from the plain loop's device events)",
+            "kernel": "grouped FP64 product kernel of the batched loop (gemm_kernel: residual-form products and "
+                      "the bordered core, %d launches per call)" % inf["product_launches"],
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-            "avg_ms": sk_ms / a.count, "algorithmic_bytes": sk_bytes / a.count,
+            "avg_ms": prod_ms / max(inf["product_launches"], 1),
+            "algorithmic_bytes": prod_bytes / max(inf["product_launches"], 1),
         },
     }
+    cpu = None
     if not a.no_cpu:
         from oracle.icur import iterative_cur
-        print("timing the CPU oracle on a sample of the batch", file=sys.stderr, flush=True)
-        spent, done_elems, k = 0.0, 0.0, 0
-        for i in sorted(range(a.count), key=lambda q: specs[q]["m"] * specs[q]["n"]):
+        print("timing the CPU oracle on randomly drawn matrices of the batch", file=sys.stderr, flush=True)
+        order = list(range(a.count))
+        random.Random(0).shuffle(order)
+        spent, k = 0.0, 0
+        for i in order:
             A64 = As[i].cpu().numpy().astype(np.float64)
             t0 = time.perf_counter()
             iterative_cur(A64, tols[i], b, kind=0, seed=seeds[i])
             spent += time.perf_counter() - t0
-            done_elems += A64.size
             k += 1
-            if spent > 15.0:
+            if spent > 20.0:
                 break
-        line["cpu_baseline"] = {
-            "value": spent * elems / done_elems, "unit": "s", "cores": int(oracle_threads()), "kind": "oracle",
-            "sample": "FP64 NumPy oracle on the %d smallest matrices of the batch (%.1f s measured), scaled by "
-                      "total m n / sampled m n to the whole batch" % (k, spent)}
-    else:
-        line["cpu_baseline"] = None
+        cpu = {"value": spent * a.count / k, "unit": "s", "cores": int(oracle_threads()), "kind": "oracle",
+               "sample": "FP64 NumPy oracle on %d matrices drawn at random from the batch (%.1f s measured), "
+                         "scaled by count / drawn to the whole batch" % (k, spent)}
+    line["cpu_baseline"] = cpu
+    if not a.no_precision:
+        del As, got, plain
+        torch.cuda.empty_cache()
+        m, n = 60000, 40000
+        print("generating the %dx%d precision-form matrix on the device" % (m, n), file=sys.stderr, flush=True)
+        A = W.precision_form_device(m, n, seed=0)
+        torch.cuda.synchronize()
+        runs = precision_runs(A, min(a.steps, 3), min(a.warmup, 1))
+        line["config"]["precision_form"] = {
+            "matrix": "A = P diag((1+i)^-2) Q^T + E, %dx%d FP32, K=4096, ||E||_F = 1e-9 ||A||_F, block 128, "
+                      "Gaussian sketch" % (m, n),
+            "runs": runs,
+            "speedup_bf16_vs_fp32": {t: runs["fp32@%s" % t]["s"] / runs["bf16@%s" % t]["s"] for t in ("0.001", "1e-05")}}
     print(json.dumps(line), flush=True)
 
 
@@ -202,28 +248,7 @@ def bench_precision(a):
     print("generating the %dx%d planted matrix on the device" % (m, n), file=sys.stderr, flush=True)
     A = W.precision_form_device(m, n, seed=0)
     torch.cuda.synchronize()
-    runs = {}
-    for tol in (1e-3, 1e-5):
-        for form, prec in (("bf16", icur.BF16_SPLIT), ("fp32", icur.FP32)):
-            for i in range(a.warmup):
-                icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
-            torch.cuda.synchronize()
-            times, outs = [], []
-            for i in range(a.steps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-                outs.append(out)
-            last = outs[-1]
-            runs["%s@%g" % (form, tol)] = {
-                "s": statistics.median(times), "rank": last["rank"], "rho": last["rho"],
-                "iterations": last["info"]["iterations"], "split_terms": last["info"]["split_terms"],
-                "sketch_ms": statistics.mean(o["info"]["ms_sketch_product"] for o in outs)}
-            print("%s tol %g: %.2f ms, rank %d, rho %.3e, %d iterations" % (
-                form, tol, runs["%s@%g" % (form, tol)]["s"] * 1e3, last["rank"], last["rho"],
-                last["info"]["iterations"]), file=sys.stderr, flush=True)
+    runs = precision_runs(A, a.steps, a.warmup, b)
     head = runs["bf16@0.001"]
     # the sketch kernel in the BF16-split form at tol 1e-3 (2 pieces of A): algorithmic
     # bytes read A once, the BF16 G, and write X0 in FP64
@@ -351,7 +376,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--form", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--size", type=int, default=40000)
-    ap.add_argument("--workload", choices=["rbf", "batched", "precision", "csr"], default="rbf")
+    ap.add_argument("--workload", choices=["rbf", "batched", "precision", "csr"], default="batched")
+    ap.add_argument("--no-precision", action="store_true", help="batched: skip the precision-form comparison")
+    ap.add_argument("--no-plain", action="store_true", help="batched: skip the plain loop (profiling runs)")
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--workers", type=int, default=0)
     a = ap.parse_args()

@@ -44,8 +44,12 @@ enum icur_status {
 };
 
 enum icur_sketch_kind {
-  ICUR_SKETCH_GAUSSIAN = 0,    /* N(0,1) entries rounded to BF16 (§3.4: Gaussian) */
-  ICUR_SKETCH_SPARSE_SIGN = 1  /* zeta entries +-1 per column of G (§2.1, §3.4) */
+  ICUR_SKETCH_GAUSSIAN = 0,     /* N(0,1) entries rounded to BF16 (§3.4: Gaussian) */
+  ICUR_SKETCH_SPARSE_SIGN = 1,  /* zeta entries +-1 per column of G (§2.1, §3.4) */
+  ICUR_SKETCH_SRTT = 2          /* subsampled randomized trigonometric transform (§3.4, for
+                                   very large m): sqrt(m/c) R F D with the orthonormal
+                                   DCT-II F, random signs D and c kept rows R; dense input
+                                   only, needs c <= m; applied in FP32 */
 };
 
 enum icur_precision {
@@ -108,6 +112,14 @@ typedef struct icur_info {
   double  rho[512];           /* rho after each iteration */
   int32_t block_sizes[512];   /* indices added by each iteration (b, or fewer when a
                                  block is cut short); I and J are these blocks in order */
+  /* icur_run_batched, grouped form: ms_sketch above is the batch's sketch phase,
+     ms_select the device time of its grouped selections, ms_residual the host clock of
+     the grouped iterations, ms_core the copies of the results to the caller's pools and
+     ms_sketch_product the set-up of the per-matrix buffers; and: */
+  double  ms_products;        /* device time of the grouped FP64 product launches */
+  double  product_bytes;      /* their algorithmic bytes: operands read once, output written once */
+  int32_t product_launches;
+  int32_t group_iterations;   /* grouped iterations (the longest matrix's count) */
 } icur_info;
 
 /*
@@ -209,6 +221,20 @@ int icur_release(void);
  */
 int icur_make_sketch(uint64_t seed, int64_t c, int64_t m, int32_t sketch_kind, int32_t zeta,
                      uint16_t* G_bf16, uint8_t* rows, uint8_t* signs, void* stream);
+
+/*
+ * icur_make_srtt: the SRTT sketch operator (ICUR_SKETCH_SRTT; §3.4): G = sqrt(m/c) R F D,
+ * F the orthonormal DCT-II of length m, D = diag(d_i) with d_i = -1 when bit 0 of word 0
+ * of Philox4x32-10 counter (lo32(i), hi32(i), 0, 0x53525444) is set, R the c distinct
+ * rows drawn by Floyd's algorithm (draw t from counter (t, 0, 0, 0x53525452), value
+ * (word1 * 2^32 + word0) mod (m - c + t + 1)), kept in increasing order; key (lo32(seed),
+ * hi32(seed)).  G[k][i] = d_i sqrt(m/c) s_r cos(pi r (2i+1) / (2m)), r = rows[k], s_0 =
+ * sqrt(1/m), s_r = sqrt(2/m), evaluated in FP64 and rounded to FP32.
+ *   G     device, c x m FP32 (leading dimension m), or NULL (rows only).
+ *   rows  device, c int64: the kept rows, increasing.
+ * 1 <= c <= m.  Allocates m bytes of device scratch for the call.
+ */
+int icur_make_srtt(uint64_t seed, int64_t c, int64_t m, float* G, int64_t* rows, void* stream);
 
 /*
  * icur_sketch: X0 = G A (Alg. 1, initial sketch S_0^col; §3.4 cost item 4) and

@@ -374,7 +374,7 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
   if (!sparse && lda < n) return arg_error("need lda >= n");
   if (!(tol > 0.0) || !std::isfinite(tol)) return arg_error("tol must be finite and > 0");
   if (block < 1 || block > std::min(m, n)) return arg_error("need 1 <= block <= min(m, n)");
-  if (kind != ICUR_SKETCH_GAUSSIAN && kind != ICUR_SKETCH_SPARSE_SIGN)
+  if (kind != ICUR_SKETCH_GAUSSIAN && kind != ICUR_SKETCH_SPARSE_SIGN && kind != ICUR_SKETCH_SRTT)
     return arg_error("unknown sketch kind");
   if (m > 0x7fffffffLL || n > 0x7fffffffLL) return arg_error("m and n must be below 2^31");
   std::memset(o, 0, sizeof(*o));
@@ -386,6 +386,8 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
   if (b > 512) return arg_error("block above 512 is not supported");
   if (kind == ICUR_SKETCH_SPARSE_SIGN && c > 255) return arg_error("sparse-sign sketch needs c <= 255");
   if (sparse && c > 256) return arg_error("the CSR sketch needs c = floor(1.1 b) <= 256");
+  if (sparse && kind == ICUR_SKETCH_SRTT) return arg_error("the CSR path takes the Gaussian or sparse-sign sketch");
+  if (kind == ICUR_SKETCH_SRTT && c > m) return arg_error("the SRTT sketch needs c = floor(1.1 b) <= m");
   if (o->zeta < 0 || o->zeta > 8) return arg_error("zeta must be at most 8");
   if (o->precision != ICUR_FP32 && o->precision != ICUR_BF16_SPLIT) return arg_error("unknown precision");
   if (o->split_terms < 0 || o->split_terms > 3) return arg_error("split_terms must be 0..3");
@@ -418,26 +420,38 @@ int terms_for_tol(double tol) {
 // (c x n FP64) and ||X0||_F^2 into *normsq_dev: the sketch kernel when the shape allows
 // (A split into `terms` BF16 pieces), else the general product.  ev_begin / ev_end (may
 // be null) bracket the product kernel.
+size_t sketch_G_bytes(int kind, int64_t c, int64_t m, int64_t ldg) {
+  if (kind == ICUR_SKETCH_SRTT)
+    return ((static_cast<size_t>(c) * ldg * 4 + 255) & ~size_t(255)) + static_cast<size_t>(c) * 8 + static_cast<size_t>(m) + 256;
+  return static_cast<size_t>(c) * ldg * 2;
+}
+
 int form_sketch(int kind, uint64_t seed, int64_t c, int64_t m, int64_t n, const float* A, int64_t lda, int zeta,
                 int terms, bool precise, uint16_t* G, int64_t ldg, double* S, double* partials, void* ws,
                 size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
-  if (kind == ICUR_SKETCH_GAUSSIAN)
+  const bool srtt = (kind == ICUR_SKETCH_SRTT);
+  if (kind == ICUR_SKETCH_GAUSSIAN) {
     ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
-  else
+  } else if (kind == ICUR_SKETCH_SPARSE_SIGN) {
     ICUR_TRY(launch_sparse_sign(seed, c, m, zeta, nullptr, nullptr, G, ldg, st));
+  } else {
+    // the SRTT operator is not BF16-exact: FP32 G on the FP32 matrix cores
+    char* gp = reinterpret_cast<char*>(G);
+    const size_t gbytes = (static_cast<size_t>(c) * ldg * 4 + 255) & ~size_t(255);
+    ICUR_TRY(launch_srtt(seed, c, m, reinterpret_cast<float*>(gp), ldg, reinterpret_cast<int64_t*>(gp + gbytes),
+                         reinterpret_cast<uint8_t*>(gp + gbytes + static_cast<size_t>(c) * 8), st));
+    terms = 0;
+  }
   int parts = 0;
   int sk = ICUR_ERR_UNSUPPORTED;
-  if (terms > 0)
-    sk = sketch_product(G, ldg, c, A, m, n, lda, terms, precise, S, n, partials, &parts, ws, ws_bytes, st, ev_begin,
-                        ev_end);
-  if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
+  if (terms > 0)  if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
   if (sk == ICUR_ERR_UNSUPPORTED) {
     if (ev_begin) ICUR_HIP(hipEventRecord(ev_begin, st));
     WideGemm g{};
     g.W = G;
     g.ldw = ldg;
     g.wterms = terms == 0 ? 0 : 1;
-    g.w_bf16 = true;
+    g.w_bf16 = !srtt;
     g.B = A;
     g.ldb = lda;
     g.bterms = terms;
@@ -524,7 +538,9 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   const double thr = xi * tol;
   const bool denom_a = (o.denominator == ICUR_DENOM_A);
   // s_G^2: E ||G x||^2 = s_G^2 ||x||^2 for the unscaled operators
-  const double sg2 = kind == ICUR_SKETCH_GAUSSIAN ? static_cast<double>(c) : static_cast<double>(std::min<int64_t>(zeta, c));
+  const double sg2 = kind == ICUR_SKETCH_GAUSSIAN ? static_cast<double>(c)
+                     : kind == ICUR_SKETCH_SRTT   ? 1.0
+                                                  : static_cast<double>(std::min<int64_t>(zeta, c));
   const bool split = (o.precision == ICUR_BF16_SPLIT);
   const int T = split ? (o.split_terms ? o.split_terms : terms_for_tol(tol)) : 0;
   // sketch pieces: the plain form forms every product exactly (three pieces of A times a
@@ -567,7 +583,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   // ---- fixed-size buffers
   void *pG, *pX0, *pSr, *pColMask, *pRowMask, *pJk, *pIk, *pLupp, *pGemm, *pNorm, *pScal, *pN;
   const int64_t ldg = (m + 7) / 8 * 8;  // 16-byte aligned rows of G for the sketch kernel
-  ICUR_TRY(ensure(dc, kG, sparse ? csr_sketch_aux_bytes(m, c) : static_cast<size_t>(c) * ldg * 2, &pG));
+  ICUR_TRY(ensure(dc, kG, sparse ? csr_sketch_aux_bytes(m, c) : sketch_G_bytes(kind, c, m, ldg), &pG));
   ICUR_TRY(ensure(dc, kX0, static_cast<size_t>(c) * n * 8, &pX0));
   ICUR_TRY(ensure(dc, kSrow, static_cast<size_t>(b) * n * fsz, &pSr));
   ICUR_TRY(ensure(dc, kColMask, static_cast<size_t>(n), &pColMask));
@@ -1029,6 +1045,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   // FP64 residual factors advances together with the others, one launch per step
   std::vector<std::string> errs(static_cast<size_t>(count), "not run: no worker thread could select the device");
   std::vector<int> grouped, rest;
+  BatchedCall gstat{};  // the grouped form's statistics, reported in icur_last_info
   const bool group_ok = o.batch_workers == 0 && block <= kGMaxSteps && o.residual_fp64 >= 0 &&
                         o.selection == ICUR_SELECT_LUPP;
   for (int32_t i = 0; i < count; ++i)
@@ -1067,6 +1084,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
       }
     }
     total_iters += bc.iterations;
+    gstat = bc;
   }
 
   constexpr int kBatchWorkers = 16;
@@ -1142,6 +1160,15 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
     }
   }
   std::memset(&t_info, 0, sizeof(t_info));
+  t_info.ms_sketch = gstat.ms_sketch;
+  t_info.ms_select = gstat.ms_select;
+  t_info.ms_products = gstat.ms_products;
+  t_info.product_bytes = gstat.product_bytes;
+  t_info.product_launches = gstat.product_launches;
+  t_info.group_iterations = gstat.iterations;
+  t_info.ms_residual = gstat.ms_loop;
+  t_info.ms_core = gstat.ms_results;
+  t_info.ms_sketch_product = gstat.ms_alloc;
   t_info.iterations = static_cast<int32_t>(std::min<int64_t>(total_iters, INT32_MAX));
   t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (first_err != ICUR_OK) {
@@ -1201,10 +1228,31 @@ int icur_make_sketch(uint64_t seed, int64_t c, int64_t m, int32_t sketch_kind, i
     if (!G_bf16 && !rows && !signs) return arg_error("no output given");
     if (zeta < 0 || zeta > 8) return arg_error("zeta must be in 0..8");
     ICUR_TRY(launch_sparse_sign(seed, c, m, zeta > 0 ? zeta : 8, rows, signs, G_bf16, m, st));
+  } else if (sketch_kind == ICUR_SKETCH_SRTT) {
+    return arg_error("the SRTT operator is not BF16-valued: use icur_make_srtt");
   } else {
     return arg_error("unknown sketch kind");
   }
   ICUR_HIP(hipStreamSynchronize(st));
+  return ICUR_OK;
+}
+
+int icur_make_srtt(uint64_t seed, int64_t c, int64_t m, float* G, int64_t* rows, void* stream) {
+  t_error.clear();
+  if (c < 1 || m < 1 || c > m) return arg_error("need 1 <= c <= m");
+  if (!rows) return arg_error("rows is null");
+  hipStream_t st = as_stream(stream);
+  void* mark = nullptr;
+  if (hipMalloc(&mark, static_cast<size_t>(m)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed");
+    return ICUR_ERR_NOMEM;
+  }
+  const int e = launch_srtt(seed, c, m, G, m, rows, static_cast<uint8_t*>(mark), st);
+  const hipError_t se = hipStreamSynchronize(st);
+  (void)hipFree(mark);
+  if (e != ICUR_OK) return e;
+  ICUR_HIP(se);
   return ICUR_OK;
 }
 

@@ -109,6 +109,14 @@ struct BatchedCall {
   int32_t* status;
   std::string* errs;      // per-matrix messages of failed matrices
   int iterations;         // out: grouped iterations run
+  double ms_sketch;       // out: the sketch phase (host clock, all sketch streams drained)
+  double ms_select;       // out: device time of the grouped selections
+  double ms_products;     // out: device time of the grouped product launches
+  double product_bytes;   // out: their algorithmic bytes (W, B and X read once, OUT written once)
+  int product_launches;   // out
+  double ms_alloc;        // out: host clock of the buffer set-up after the sketch
+  double ms_loop;         // out: host clock of the grouped iterations
+  double ms_results;      // out: host clock of the copies to the caller's pools
 };
 
 // Alg. 1 on the matrices listed in `which` (each with max(m, n) <= kGMaxN, block <=

@@ -10,6 +10,7 @@
 //   3. results: I, J and the core U of each matrix copied to the caller's pools.
 // Each matrix follows Alg. 1 on its own: the grouping changes no arithmetic.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -20,8 +21,9 @@
 namespace icur {
 
 int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
-                           int grid, hipStream_t st);
+                           int grid, hipStream_t st, hipEvent_t* ev);
 size_t batch_plan_bytes(int count);
+double* batch_plan_bytes_ptr(void* plan_ws, int count);
 
 namespace {
 
@@ -131,8 +133,9 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   constexpr int kSketchStreams = 4;
   std::vector<hipStream_t> ss(kSketchStreams);
   hipEvent_t ready;
-  ICUR_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  ICUR_HIP(hipEventCreate(&ready));
   ICUR_HIP(hipEventRecord(ready, st));
+  const auto t_sk0 = std::chrono::steady_clock::now();
   int64_t mmax = 0, nmax = 0;
   for (int q = 0; q < count; ++q) {
     mmax = std::max<int64_t>(mmax, hm[q].m);
@@ -143,7 +146,8 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
                             wide_gemm_workspace_bytes(c, mmax, nmax, dev.num_cus));
   const int nparts_cap = std::max(std::max(sketch_max_norm_partials(c, nmax), max_norm_partials(c, nmax)),
                                   kSumsqMaxParts);
-  const size_t per_stream = al(static_cast<size_t>(c) * ldg_max * 2) + al(gemm_ws) + al(nparts_cap * 8);
+  const size_t gbytes = al(sketch_G_bytes(a.kind, c, mmax, ldg_max));
+  const size_t per_stream = gbytes + al(gemm_ws) + al(nparts_cap * 8);
   DevBuf sk;
   ICUR_TRY(sk.alloc(per_stream * kSketchStreams + al(static_cast<size_t>(count) * 16)));
   double* norms_dev = reinterpret_cast<double*>(static_cast<char*>(sk.p) + per_stream * kSketchStreams);
@@ -159,8 +163,8 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
     hipStream_t s2 = ss[sidx];
     char* base = static_cast<char*>(sk.p) + per_stream * sidx;
     uint16_t* G = reinterpret_cast<uint16_t*>(base);
-    void* ws = base + al(static_cast<size_t>(c) * ldg_max * 2);
-    double* parts = reinterpret_cast<double*>(base + al(static_cast<size_t>(c) * ldg_max * 2) + al(gemm_ws));
+    void* ws = base + gbytes;
+    double* parts = reinterpret_cast<double*>(base + gbytes + al(gemm_ws));
     BatchMat& bm = hm[q];
     const int64_t m = bm.m, n = bm.n, ldg = (m + 7) / 8 * 8;
     const int terms = split ? (o.split_terms ? o.split_terms : terms_for_tol(a.tol[i])) : (o.sketch_fp32 ? 0 : 3);
@@ -184,11 +188,15 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   }
   (void)hipEventDestroy(ready);
   if (err != ICUR_OK) return err;
+  a.ms_sketch = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_sk0).count();
   std::vector<double> norms(2 * count);
   ICUR_HIP(hipMemcpy(norms.data(), norms_dev, norms.size() * 8, hipMemcpyDeviceToHost));
 
   // ---- loop state
-  const double sg2 = a.kind == ICUR_SKETCH_GAUSSIAN ? static_cast<double>(c) : static_cast<double>(std::min<int64_t>(zeta, c));
+  const auto t_al0 = std::chrono::steady_clock::now();
+  const double sg2 = a.kind == ICUR_SKETCH_GAUSSIAN ? static_cast<double>(c)
+                     : a.kind == ICUR_SKETCH_SRTT   ? 1.0
+                                                    : static_cast<double>(std::min<int64_t>(zeta, c));
   std::vector<DevBuf> rankbuf(count);
   for (int q = 0; q < count; ++q) {
     const int i = which[q];
@@ -209,10 +217,17 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
     a.est[i] = rho0;
     if (g2 == 0.0 || (denom_a && rho0 <= bm.thr)) continue;  // rank 0
     bm.s = static_cast<int>(std::min<int64_t>(b, bm.rmax));
-    const int64_t cap = std::min<int64_t>(bm.rmax, std::max<int64_t>(4 * b, 256));
-    ICUR_TRY(rankbuf[q].alloc(rank_bytes(cap, bm.m, bm.n, b)));
+    // rank-sized buffers for the whole rank bound when they fit (no growth, no host
+    // synchronisation inside the loop); else a quarter of it, grown on demand
+    int64_t cap = bm.rmax;
+    if (rankbuf[q].alloc(rank_bytes(cap, bm.m, bm.n, b)) != ICUR_OK) {
+      set_error("");
+      cap = std::min<int64_t>(bm.rmax, std::max<int64_t>(4 * b, bm.rmax / 4));
+      ICUR_TRY(rankbuf[q].alloc(rank_bytes(cap, bm.m, bm.n, b)));
+    }
     bind_rank(bm, static_cast<char*>(rankbuf[q].p), cap, b);
   }
+  a.ms_alloc = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_al0).count();
   DevBuf mats, plan;
   ICUR_TRY(mats.alloc(sizeof(BatchMat) * count));
   ICUR_TRY(plan.alloc(batch_plan_bytes(count)));
@@ -227,15 +242,42 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   ICUR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&drec), hrec, 0));
   ICUR_HIP(hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st));
   const int grid = 4 * dev.num_cus;
+  // device events around the selections and the product stages of every iteration
+  constexpr int kEv = 12;
+  hipEvent_t ev[kEv];
+  for (int e = 0; e < kEv; ++e) ICUR_HIP(hipEventCreate(&ev[e]));
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() {
+      for (int q = 0; q < kEv; ++q) (void)hipEventDestroy(e[q]);
+    }
+  } ev_guard{ev};
+  ICUR_HIP(hipMemsetAsync(batch_plan_bytes_ptr(plan.p, count), 0, 8 * 8, st));
+  a.ms_select = a.ms_products = 0.0;
+  a.product_launches = 0;
 
   bool any = false;
   for (const BatchMat& bm : hm) any |= bm.s != 0;
   int iters = 0;
+  const auto t_loop0 = std::chrono::steady_clock::now();
   while (any) {
     ICUR_TRY(launch_batch_iteration(dmats, count, static_cast<int>(c), static_cast<int>(b), a.row_cut, plan.p, drec,
-                                    grid, st));
+                                    grid, st, ev));
     ICUR_HIP(hipStreamSynchronize(st));
     ++iters;
+    for (int e = 0; e < kEv; e += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) != hipSuccess) {
+        (void)hipGetLastError();
+        ms = 0.f;
+      }
+      if (e < 4) {
+        a.ms_select += ms;
+      } else {
+        a.ms_products += ms;
+        a.product_launches += 1;
+      }
+    }
     any = false;
     bool grow = false;
     for (int q = 0; q < count; ++q) {
@@ -274,11 +316,18 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
     }
     if (grow) ICUR_HIP(hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st));
   }
+  a.ms_loop = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_loop0).count();
+  const auto t_res0 = std::chrono::steady_clock::now();
   // final state of every matrix (the host mirror holds r, status and rho of the last
   // iteration of each)
   ICUR_HIP(hipMemcpyAsync(hm.data(), dmats, sizeof(BatchMat) * count, hipMemcpyDeviceToHost, st));
+  double stage_bytes[8];
+  ICUR_HIP(hipMemcpyAsync(stage_bytes, batch_plan_bytes_ptr(plan.p, count), sizeof(stage_bytes), hipMemcpyDeviceToHost,
+                          st));
   ICUR_HIP(hipStreamSynchronize(st));
   a.iterations = iters;
+  a.product_bytes = 0.0;
+  for (double v : stage_bytes) a.product_bytes += v;
 
   // ---- results
   for (int q = 0; q < count; ++q) {
@@ -304,6 +353,7 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
                               hipMemcpyDeviceToHost, st));
   }
   ICUR_HIP(hipStreamSynchronize(st));
+  a.ms_results = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_res0).count();
   return ICUR_OK;
 }
 

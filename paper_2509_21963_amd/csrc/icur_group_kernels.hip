@@ -60,8 +60,9 @@ constexpr int kOpsPerMat = 6;
 struct Plan {
   GemmOp* gemm[kNumStages];
   GatherOp* gather[kNumStages];
-  int* nops;    // per stage
-  int* ntiles;  // per stage
+  int* nops;      // per stage
+  int* ntiles;    // per stage
+  double* bytes;  // per stage: algorithmic bytes of the products so far (the call's total)
 };
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -70,8 +71,12 @@ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // no tiles.  tile0 is filled in afterwards by a scan over the entries.
 __device__ __forceinline__ void set_gemm(GemmOp* ops, int i, int k, const double* X, int64_t ldx, const double* W,
                                          int64_t ldw, const double* B, int64_t ldb, double* OUT, int64_t ldo, int M,
-                                         int K, int N, double alpha, double* normp) {
+                                         int K, int N, double alpha, double* normp, double* bytes = nullptr) {
   GemmOp& o = ops[i * kOpsPerMat + k];
+  // algorithmic bytes: W and B read once, OUT written once, X read once when given
+  if (bytes && M > 0 && N > 0)
+    atomicAdd(bytes, 8.0 * (static_cast<double>(M) * K + static_cast<double>(K) * N +
+                            static_cast<double>(M) * N * (X ? 2.0 : 1.0)));
   o.X = X;
   o.ldx = ldx;
   o.W = W;
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
       set_gather(plan.gather[kGA], i, 1, bm.Ur, false, 1, n, bm.Jk, nullptr, bm.Wa, cap, nJ, r, 1.0);
       for (int k = 2; k < kOpsPerMat; ++k) set_gather(plan.gather[kGA], i, k, nullptr, false, 0, 0, nullptr, nullptr, nullptr, 0, 0, 0, 0.0);
       // P1: row residual S^row = A(:, J_k) - Lc Ur(:, J_k), stored transposed
-      set_gemm(plan.gemm[kP1], i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr);
+      set_gemm(plan.gemm[kP1], i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr, plan.bytes + kP1);
       for (int k = 1; k < kOpsPerMat; ++k) set_gemm(plan.gemm[kP1], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
     } else {
       const int nI = on ? bm.nI : 0;
@@ -172,18 +177,18 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
       set_gather(plan.gather[kGB], i, 4, bm.A, true, bm.lda, 1, bm.Iall, bm.Jk, bm.AIJk, nI, nR, nI, 1.0);
       set_gather(plan.gather[kGB], i, 5, bm.A, true, bm.lda, 1, bm.Ik, bm.Jall, bm.AIkJ, cap, nI, nR, 1.0);
       // P2: residual at the new rows Sr -= Lc(I_k,:) Ur; the core's Y = U A(I,J_k), Z = A(I_k,J) U
-      set_gemm(plan.gemm[kP2], i, 0, bm.Sr, n, bm.Wa, cap, bm.Ur, n, bm.Sr, n, nR > 0 ? nI : 0, r, n, -1.0, nullptr);
-      set_gemm(plan.gemm[kP2], i, 1, nullptr, 0, U, cap, bm.AIJk, nI, bm.Y, nI, nR, r, nI, 1.0, nullptr);
-      set_gemm(plan.gemm[kP2], i, 2, nullptr, 0, bm.AIkJ, cap, U, cap, bm.Z, cap, nR > 0 ? nI : 0, r, r, 1.0, nullptr);
+      set_gemm(plan.gemm[kP2], i, 0, bm.Sr, n, bm.Wa, cap, bm.Ur, n, bm.Sr, n, nR > 0 ? nI : 0, r, n, -1.0, nullptr, plan.bytes + kP2);
+      set_gemm(plan.gemm[kP2], i, 1, nullptr, 0, U, cap, bm.AIJk, nI, bm.Y, nI, nR, r, nI, 1.0, nullptr, plan.bytes + kP2);
+      set_gemm(plan.gemm[kP2], i, 2, nullptr, 0, bm.AIkJ, cap, U, cap, bm.Z, cap, nR > 0 ? nI : 0, r, r, 1.0, nullptr, plan.bytes + kP2);
       // P3: new row factors Ur_k = N_k^{-1} Sr; V = Y N_k^{-1}
-      set_gemm(plan.gemm[kP3], i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr);
-      set_gemm(plan.gemm[kP3], i, 1, nullptr, 0, bm.Y, nI, bm.Nk, nI, bm.V, nI, nR, nI, nI, 1.0, nullptr);
+      set_gemm(plan.gemm[kP3], i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr, plan.bytes + kP3);
+      set_gemm(plan.gemm[kP3], i, 1, nullptr, 0, bm.Y, nI, bm.Nk, nI, bm.V, nI, nR, nI, nI, 1.0, nullptr, plan.bytes + kP3);
       // P4: column residual S -= S(:, J_k) Ur_k (with its norm partials); the core's U += V Z
       // and its new block row -N_k^{-1} Z
-      set_gemm(plan.gemm[kP4], i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp);
-      set_gemm(plan.gemm[kP4], i, 1, U, cap, bm.V, nI, bm.Z, cap, U, cap, nR, nI, r, 1.0, nullptr);
+      set_gemm(plan.gemm[kP4], i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp, plan.bytes + kP4);
+      set_gemm(plan.gemm[kP4], i, 1, U, cap, bm.V, nI, bm.Z, cap, U, cap, nR, nI, r, 1.0, nullptr, plan.bytes + kP4);
       set_gemm(plan.gemm[kP4], i, 2, nullptr, 0, bm.Nk, nI, bm.Z, cap, U + static_cast<int64_t>(r) * cap, cap,
-               nR > 0 ? nI : 0, nI, r, -1.0, nullptr);
+               nR > 0 ? nI : 0, nI, r, -1.0, nullptr, plan.bytes + kP4);
       bm.nparts = plan.gemm[kP4][i * kOpsPerMat].pad;
       // GC: the core's new block column -V, and N_k^{-1} in the corner
       set_gather(plan.gather[kGC], i, 0, bm.V, false, nI, 1, nullptr, nullptr, U + r, cap, nR, nI, -1.0);
@@ -420,7 +425,7 @@ __global__ __launch_bounds__(256) void batch_end_kernel(BatchMat* __restrict__ m
 // ------------------------------------------------------------------ host wrappers
 size_t batch_plan_bytes(int count) {
   const size_t per = static_cast<size_t>(count) * kOpsPerMat;
-  return kNumStages * per * (sizeof(GemmOp) + sizeof(GatherOp)) + 2 * kNumStages * sizeof(int) + 512;
+  return kNumStages * per * (sizeof(GemmOp) + sizeof(GatherOp)) + 128 + kNumStages * sizeof(double) + 512;
 }
 
 namespace {
@@ -436,6 +441,7 @@ Plan bind_plan(void* ws, int count) {
   }
   p.nops = reinterpret_cast<int*>(q);
   p.ntiles = p.nops + kNumStages;
+  p.bytes = reinterpret_cast<double*>(q + 128);
   return p;
 }
 
@@ -454,23 +460,41 @@ int gather_stage(const Plan& p, int s, int grid, hipStream_t st) {
 
 // One iteration of Alg. 1 (residual form, with the bordered core) for every unfinished
 // matrix: 13 launches whose configuration depends only on count and the device.
+double* batch_plan_bytes_ptr(void* plan_ws, int count) { return bind_plan(plan_ws, count).bytes; }
+
 int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
-                           int grid, hipStream_t st) {
+                           int grid, hipStream_t st, hipEvent_t* ev) {
   const Plan p = bind_plan(plan_ws, count);
+  auto mark = [&](int k) -> int {
+    if (ev) ICUR_HIP(hipEventRecord(ev[k], st));
+    return ICUR_OK;
+  };
+  ICUR_TRY(mark(0));
   ICUR_TRY(launch_batch_lupp(mats, count, false, 0.0, st));
+  ICUR_TRY(mark(1));
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, 0, p);
   ICUR_HIP(hipGetLastError());
   ICUR_TRY(gather_stage(p, kGA, grid, st));
+  ICUR_TRY(mark(4));
   ICUR_TRY(gemm_stage(p, kP1, grid, st));
+  ICUR_TRY(mark(5));
+  ICUR_TRY(mark(2));
   ICUR_TRY(launch_batch_lupp(mats, count, true, row_cut, st));
+  ICUR_TRY(mark(3));
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, 1, p);
   ICUR_HIP(hipGetLastError());
   ICUR_TRY(gather_stage(p, kGB, grid, st));
   hipLaunchKernelGGL(batch_inverse_kernel, dim3(count), dim3(256), 0, st, mats, count);
   ICUR_HIP(hipGetLastError());
+  ICUR_TRY(mark(6));
   ICUR_TRY(gemm_stage(p, kP2, grid, st));
+  ICUR_TRY(mark(7));
+  ICUR_TRY(mark(8));
   ICUR_TRY(gemm_stage(p, kP3, grid, st));
+  ICUR_TRY(mark(9));
+  ICUR_TRY(mark(10));
   ICUR_TRY(gemm_stage(p, kP4, grid, st));
+  ICUR_TRY(mark(11));
   ICUR_TRY(gather_stage(p, kGC, grid, st));
   hipLaunchKernelGGL(batch_end_kernel, dim3(count), dim3(256), 0, st, mats, count, b, rec);
   ICUR_HIP(hipGetLastError());

@@ -52,6 +52,10 @@ int launch_gaussian_G_strided(uint64_t seed, int64_t c, int64_t m, uint16_t* G, 
                               hipStream_t st);
 int launch_sparse_sign(uint64_t seed, int64_t c, int64_t m, int zeta, uint8_t* rows,
                        uint8_t* signs, uint16_t* G_dense, int64_t ldg, hipStream_t st);
+// SRTT operator (c <= m): kept rows (c int64, increasing) and, when G is given, the
+// dense c x ldg FP32 operator.  mark: m bytes of scratch.
+int launch_srtt(uint64_t seed, int64_t c, int64_t m, float* G, int64_t ldg, int64_t* rows, uint8_t* mark,
+                hipStream_t st);
 
 // ----- wide products (icur_gemm.hip, icur_wide_*.hip) -----
 // OUT(M x N) = X - W(M x K) B(K x N) (subtract) or W B.  X and OUT are FP32, or FP64 when
@@ -119,6 +123,9 @@ int launch_reduce_partials(const double* partials, int n, double* out, hipStream
 constexpr double kSketchChunkFlushBelow = 1e-4;
 // BF16 pieces per FP32 operand of the split form for a tolerance (icur_api.hip).
 int terms_for_tol(double tol);
+// Bytes of the G buffer form_sketch needs (BF16 operators: c x ldg x 2; SRTT: the FP32
+// operator, its kept rows and m bytes of scratch).
+size_t sketch_G_bytes(int kind, int64_t c, int64_t m, int64_t ldg);
 // G drawn from (kind, seed, zeta) into G (c x ldg BF16), X0 = G A into S (c x n FP64,
 // leading dimension n) and ||X0||_F^2 into *normsq_dev (device).  terms: BF16 pieces of A
 // (1..3) or 0 for FP32 matrix cores; precise: FP64 flush every 32 rows.  partials holds

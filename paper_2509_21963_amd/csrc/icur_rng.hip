@@ -10,6 +10,13 @@
 //   sparse-sign column i: Floyd's sampling of min(zeta, c) distinct rows, the t-th draw
 //     from counter (lo32(i), hi32(i), t, 'SPRS'): row = word0 mod (c - z + t + 1),
 //     replaced by c - z + t when already taken; sign negative when bit 0 of word1 is 1.
+//   SRTT (the subsampled randomized trigonometric transform of §3.4): G = sqrt(m/c) R F D
+//     with F the orthonormal DCT-II of length m, D = diag(d_i), d_i = -1 when bit 0 of
+//     word0 of counter (lo32(i), hi32(i), 0, 'SRTD') is set, and R keeping c distinct rows
+//     of F D chosen by Floyd's algorithm (draw t from counter (t, 0, 0, 'SRTR'),
+//     v = (word1 * 2^32 + word0) mod (m - c + t + 1)), listed in increasing order.
+//     G[k][i] = d_i sqrt(m/c) s_r cos(pi r (2 i + 1) / (2 m)) for kept row r = R[k]
+//     (s_0 = sqrt(1/m), s_r = sqrt(2/m)), the angle reduced exactly as q = r (2i+1) mod 4m.
 #include "icur_internal.h"
 
 namespace icur {
@@ -17,6 +24,8 @@ namespace {
 
 constexpr uint32_t kTagGauss = 0x47415553u;
 constexpr uint32_t kTagSign = 0x53505253u;
+constexpr uint32_t kTagSrttSign = 0x53525444u;
+constexpr uint32_t kTagSrttRows = 0x53525452u;
 
 struct U32x4 {
   uint32_t x0, x1, x2, x3;
@@ -103,7 +112,83 @@ __global__ void zero_columns_kernel(uint16_t* __restrict__ G, int64_t m, int64_t
   if (i < m) G[static_cast<int64_t>(blockIdx.y) * ldg + i] = 0;
 }
 
+// Floyd's sampling of the c kept rows into a bitmap of m bytes (zeroed before): one thread,
+// c draws; the value j = m - c + t is never taken before draw t.
+__global__ void srtt_floyd_kernel(uint64_t seed, int64_t c, int64_t m, uint8_t* __restrict__ mark) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int64_t t = 0; t < c; ++t) {
+    const U32x4 w = philox4x32_10(static_cast<uint32_t>(t), 0u, 0u, kTagSrttRows, static_cast<uint32_t>(seed),
+                                  static_cast<uint32_t>(seed >> 32));
+    const uint64_t j = static_cast<uint64_t>(m - c + t);
+    const uint64_t v = ((static_cast<uint64_t>(w.x1) << 32) | w.x0) % (j + 1);
+    if (mark[v]) mark[j] = 1;
+    else mark[v] = 1;
+  }
+}
+
+// The marked rows in increasing order: one workgroup scans the bitmap in chunks.
+__global__ __launch_bounds__(1024) void srtt_compact_kernel(const uint8_t* __restrict__ mark, int64_t m,
+                                                            int64_t* __restrict__ rows) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int64_t base_out = 0;
+  for (int64_t base = 0; base < m; base += 1024) {
+    const int64_t i = base + tid;
+    const int v = (i < m && mark[i]) ? 1 : 0;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < 16; ++q) {
+      before += q < w ? wsum[q] : 0;
+      total += wsum[q];
+    }
+    if (v) rows[base_out + before + x - 1] = i;
+    base_out += total;
+  }
+}
+
+__global__ void srtt_G_kernel(uint64_t seed, int64_t c, int64_t m, const int64_t* __restrict__ rows,
+                              float* __restrict__ G, int64_t ldg) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (i >= m || k >= c) return;
+  const uint64_t ui = static_cast<uint64_t>(i);
+  const U32x4 w = philox4x32_10(static_cast<uint32_t>(ui), static_cast<uint32_t>(ui >> 32), 0u, kTagSrttSign,
+                                static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  const double d = (w.x0 & 1u) ? -1.0 : 1.0;
+  const int64_t r = rows[k];
+  const int64_t q = (r * (2 * i + 1)) % (4 * m);
+  const double scale = (r == 0 ? sqrt(1.0 / static_cast<double>(m)) : sqrt(2.0 / static_cast<double>(m))) *
+                       sqrt(static_cast<double>(m) / static_cast<double>(c));
+  const double v = d * scale * cos(3.141592653589793 * static_cast<double>(q) / (2.0 * static_cast<double>(m)));
+  G[k * ldg + i] = static_cast<float>(v);
+}
+
 }  // namespace
+
+int launch_srtt(uint64_t seed, int64_t c, int64_t m, float* G, int64_t ldg, int64_t* rows, uint8_t* mark,
+                hipStream_t st) {
+  if (c <= 0 || m <= 0) return ICUR_OK;
+  if (c > m) return arg_error("SRTT sketch needs c <= m");
+  if (c > 65535) return arg_error("sketch rows c exceed 65535");
+  if (G && ldg < m) return arg_error("sketch: need ldg >= m");
+  if (m > (int64_t(1) << 40)) return arg_error("SRTT sketch: m too large");
+  ICUR_TRY(launch_fill_u8(mark, m, 0, st));
+  hipLaunchKernelGGL(srtt_floyd_kernel, dim3(1), dim3(64), 0, st, seed, c, m, mark);
+  hipLaunchKernelGGL(srtt_compact_kernel, dim3(1), dim3(1024), 0, st, mark, m, rows);
+  if (G) {
+    dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(c));
+    hipLaunchKernelGGL(srtt_G_kernel, grid, dim3(256), 0, st, seed, c, m, rows, G, ldg);
+  }
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
 
 int launch_gaussian_G(uint64_t seed, int64_t c, int64_t m, uint16_t* G, int64_t ldg, hipStream_t st) {
   if (c <= 0 || m <= 0) return ICUR_OK;

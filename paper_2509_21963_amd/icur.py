@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libicur.so")
 
 OK, MAXRANK, STALLED = 0, 1, 2
 ERR_ARG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
-GAUSSIAN, SPARSE_SIGN = 0, 1
+GAUSSIAN, SPARSE_SIGN, SRTT = 0, 1, 2
 FP32, BF16_SPLIT = 0, 1
 DENOM_GA, DENOM_A = 0, 1
 LUPP, QRCP = 0, 1
@@ -50,13 +50,16 @@ class Info(ctypes.Structure):
                 ("ms_core", ctypes.c_double), ("ms_sketch_product", ctypes.c_double),
                 ("n_rho", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("rho", ctypes.c_double * 512),
-                ("block_sizes", ctypes.c_int32 * 512)]
+                ("block_sizes", ctypes.c_int32 * 512),
+                ("ms_products", ctypes.c_double), ("product_bytes", ctypes.c_double),
+                ("product_launches", ctypes.c_int32), ("group_iterations", ctypes.c_int32)]
 
 
 _lib = None
 EXPORTS = ["icur_run", "icur_run_csr", "icur_run_batched", "icur_last_info", "icur_last_error", "icur_release",
            "icur_make_sketch", "icur_sketch", "icur_lupp", "icur_residual", "icur_gather",
-           "icur_core_update", "icur_init_noalloc", "icur_lupp_noalloc", "icur_residual_f64", "icur_qrcp"]
+           "icur_core_update", "icur_init_noalloc", "icur_lupp_noalloc", "icur_residual_f64", "icur_qrcp",
+           "icur_make_srtt"]
 
 
 def load(path=LIB_PATH):
@@ -81,6 +84,7 @@ def load(path=LIB_PATH):
     lib.icur_lupp.argtypes = [P, I64, I64, I64, I32, P, P, ctypes.POINTER(I32), P]
     lib.icur_residual.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, I32, P, I64,
                                   ctypes.POINTER(D), P]
+    lib.icur_make_srtt.argtypes = [U64, I64, I64, P, P, P]
     lib.icur_qrcp.argtypes = [P, I64, I64, I64, I32, P, P, ctypes.POINTER(I32), P]
     lib.icur_residual_f64.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64, P, I64, ctypes.POINTER(D), P]
     lib.icur_gather.argtypes = [P, I64, I64, I64, P, P, I64, P, I64, P, I64, P]
@@ -255,6 +259,16 @@ def make_sketch(seed, c, m, kind=GAUSSIAN, zeta=0, want_dense=True, want_pattern
     _check(lib.icur_make_sketch(ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), c, m, kind, zeta,
                                 _ptr(G), _ptr(rows), _ptr(signs), _stream()))
     return G, rows, signs
+
+
+def make_srtt(seed, c, m, want_dense=True):
+    """icur_make_srtt: returns (G c x m FP32 device tensor or None, rows int64 device tensor)."""
+    import torch
+    lib = load()
+    G = torch.empty((c, m), dtype=torch.float32, device="cuda") if want_dense else None
+    rows = torch.empty((c,), dtype=torch.int64, device="cuda")
+    _check(lib.icur_make_srtt(ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), c, m, _ptr(G), _ptr(rows), _stream()))
+    return G, rows
 
 
 def sketch(G, A, terms):

@@ -8,7 +8,13 @@ carry rounding, so each value is known up to a noise bound `noise`:
   * the step is pinned when          second < best - 2 noise   (only the oracle's argmax
     is valid, so validity means the GPU chose exactly the oracle's pivot).
 
-Noise bounds (absolute, per selection):
+Noise bounds (absolute, per candidate i at step t of a selection on T, the N x K
+candidate matrix, P the t pivots so far): an input perturbation of size d0 in every
+entry of T moves the step-t Schur complement v_i = T(i,t) - x_i T(P,t) by at most
+d0 (1 + ||x_i||_1) (1 + ||y||_1), x_i = T(i,0:t) T(P,0:t)^{-1}, y = T(P,0:t)^{-1} T(P,t)
+(first order).  A choice is valid when its interval meets the best candidate's; a step
+is pinned when no other interval reaches the best one's.  (QRCP steps use the cruder
+factor (1 + a_t)^2, a_t = t max|T| ||T(P,0:t)^{-1}||_1.)  The input perturbation d0:
   column steps: (eta + 4 cond 2^-52) max|X0|, with eta the sketch rounding of the form
     relative to max|X0| (see sketch_eta) and cond = cond(A(I,J)) of the cross before
     the block: the oracle forms S^col = X0 - X0(:,J) A(I,J)^+ A(I,:), whose rounding
@@ -57,6 +63,60 @@ def blocks_of(rank, b, max_rank=None, sizes=None):
     return out
 
 
+def growth(T, piv):
+    """(1 + a_t)^2 for every step t of a selection on T (N x K) with the pivots `piv`,
+    a_t = t max|T| ||T(piv[:t], :t)^{-1}||_1 (1 at t = 0): a cheap upper bound of the
+    factor step_margins computes exactly (used for QRCP)."""
+    T = np.asarray(T, dtype=np.float64)
+    tmax = float(np.abs(T).max()) if T.size else 0.0
+    out = []
+    for t in range(len(piv)):
+        if t == 0:
+            out.append(1.0)
+            continue
+        B = T[np.ix_(list(piv[:t]), list(range(t)))]
+        try:
+            inv1 = float(np.abs(np.linalg.inv(B)).sum(axis=0).max())
+        except np.linalg.LinAlgError:
+            inv1 = float("inf")
+        a = t * tmax * inv1
+        out.append((1.0 + a) ** 2)
+    return out
+
+
+def lupp_steps_with_noise(T, piv, exclude, d0):
+    """For each step t of LUPP on T (N x K) with the given pivots: the step-t Schur
+    complements v_i of every eligible candidate (first-order formula, not the replay's
+    elimination) and their noise bounds n_i = d0 (1 + ||x_i||_1) (1 + ||y||_1) with
+    x_i = T(i, 0:t) T(P, 0:t)^{-1}, y = T(P, 0:t)^{-1} T(P, t).  Yields
+    (eligible indices, |v|, n) per step."""
+    T = np.asarray(T, dtype=np.float64)
+    N = T.shape[0]
+    elig = np.ones(N, dtype=bool)
+    ex = np.asarray(list(exclude), dtype=np.int64)
+    if ex.size:
+        elig[ex] = False
+    P = []
+    for t in range(len(piv)):
+        if t == 0:
+            v = T[:, 0].copy()
+            xn = np.zeros(N)
+            yn = 0.0
+        else:
+            B = T[np.ix_(P, list(range(t)))]
+            Binv = np.linalg.inv(B)
+            y = Binv @ T[P, t]
+            X = T[:, :t] @ Binv
+            v = T[:, t] - X @ T[P, t]
+            xn = np.abs(X).sum(axis=1)
+            yn = float(np.abs(y).sum())
+        idx = np.nonzero(elig)[0]
+        yield idx, np.abs(v[idx]), d0 * (1.0 + xn[idx]) * (1.0 + yn)
+        p = int(piv[t])
+        elig[p] = False
+        P.append(p)
+
+
 def replay(A64, I, J, blocks, tol, b, kind, seed, eta, zeta=8, selection="lupp",
            denominator="GA", max_rank=None, eta_row=0.0, alpha=0.0):
     """Replay the GPU's blocks through the oracle and check every pivot.
@@ -76,6 +136,8 @@ def replay(A64, I, J, blocks, tol, b, kind, seed, eta, zeta=8, selection="lupp",
     amax = float(np.abs(A64).max())
     stats = {"col_pinned": 0, "col_tied": 0, "row_pinned": 0, "row_tied": 0}
     cond, Ic, Jc = 1.0, [], []
+    assert len(rep["history"]) >= len(forced), (
+        "the oracle stops after %d blocks along this trajectory, the GPU ran %d" % (len(rep["history"]), len(forced)))
     for k, (Jk, Ik) in enumerate(forced):
         h = rep["history"][k]
         noise = {"col": (eta + 4 * cond * EPS64) * x0max,
@@ -85,15 +147,35 @@ def replay(A64, I, J, blocks, tol, b, kind, seed, eta, zeta=8, selection="lupp",
             # times an entry's
             noise = {"col": noise["col"] * math.sqrt(rep["X0"].shape[0]),
                      "row": noise["row"] * math.sqrt(len(Jk))}
-        for side, recs in (("col", h["col_replay"]), ("row", h["row_replay"])):
-            for t, rec in enumerate(recs):
-                lim = rec["best_value"] - 2 * noise[side]
-                assert rec["value"] >= lim, (
-                    "block %d %s step %d: GPU chose %d (|v| = %.6e), oracle's best %d (%.6e), "
-                    "noise %.3e" % (k, side, t, rec["pick"], rec["value"], rec["best"],
-                                    rec["best_value"], noise[side]))
-                if rec["second_value"] < lim:
-                    assert rec["pick"] == rec["best"]
+        # the candidate matrices of the block: (S^col)^T before it, and S^row
+        Tcol = (rep["X0"] if k == 0 else rep["history"][k - 1]["S_col"]).T
+        for side, T, piv, excl, recs in (("col", Tcol, Jk, Jc, h["col_replay"]),
+                                         ("row", h["S_row"], Ik, Ic, h["row_replay"])):
+            if selection == "qrcp":
+                amp = growth(T, piv)
+                for t, rec in enumerate(recs):
+                    lim = rec["best_value"] - 2 * noise[side] * amp[t]
+                    assert rec["value"] >= lim, (
+                        "block %d %s step %d: GPU chose %d (|v| = %.6e), oracle's best %d (%.6e)"
+                        % (k, side, t, rec["pick"], rec["value"], rec["best"], rec["best_value"]))
+                    if rec["second_value"] < lim:
+                        assert rec["pick"] == rec["best"]
+                        stats[side + "_pinned"] += 1
+                    else:
+                        stats[side + "_tied"] += 1
+                continue
+            for t, (idx, av, nz) in enumerate(lupp_steps_with_noise(T, piv, excl, noise[side])):
+                pick = int(piv[t])
+                b = int(np.argmax(av))
+                lo_best = av[b] - nz[b]
+                j = int(np.searchsorted(idx, pick))
+                assert j < idx.size and idx[j] == pick
+                assert av[j] + nz[j] >= lo_best, (
+                    "block %d %s step %d: GPU chose %d (|v| = %.6e +- %.2e), oracle's best %d (%.6e +- %.2e)"
+                    % (k, side, t, pick, av[j], nz[j], idx[b], av[b], nz[b]))
+                others = np.delete(np.arange(idx.size), b)
+                if others.size == 0 or np.max(av[others] + nz[others]) < lo_best:
+                    assert pick == idx[b]
                     stats[side + "_pinned"] += 1
                 else:
                     stats[side + "_tied"] += 1

@@ -44,8 +44,8 @@ def test_struct_layouts_match_header():
     icur, _ = _lib()
     # icur_opts: 2 x int32, int64, pointer, 2 x double, 6 x int32
     assert ctypes.sizeof(icur.Opts) == 64
-    # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles, 512 x int32
-    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8 + 512 * 4
+    # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles, 512 x int32, 2 doubles, 2 x int32
+    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8 + 512 * 4 + 16 + 8
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation precedes device work
@@ -84,6 +84,9 @@ def test_run_rejects_bad_options():
               icur.Opts(selection=2), icur.Opts(selection=-1)):
         st, _ = _run_args(lib, opts=ctypes.byref(o))
         assert st == icur.ERR_ARG, (o.precision, o.zeta)
+    # the SRTT operator needs c <= m
+    st, _ = _run_args(lib, m=19, n=30, lda=30, block=19, kind=2)   # c = 20 > m
+    assert st == icur.ERR_ARG
     # risk-aware stopping is for the Gaussian sketch (the section 3.3 Corollary)
     o = icur.Opts(alpha=0.2)
     st, _ = _run_args(lib, m=100, n=100, lda=100, block=20, kind=1, opts=ctypes.byref(o))

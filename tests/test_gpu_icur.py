@@ -53,14 +53,15 @@ def check_against_oracle(icur, A32, tol, b, kind, seed, precision=0, eta=None, e
     if eta is None:
         eta = form_eta(got, tol, precision, kw.get("sketch_fp32", False))
     # every pivot of the GPU run, replayed through the oracle along the GPU's trajectory
+    denominator = "A" if kw.get("denominator") == 1 else "GA"
     stats, rep = replay(A64, I, J, got["info"]["block_sizes"], tol, b, kind, seed, eta,
                         zeta=kw.get("zeta") or 8, max_rank=kw.get("max_rank") or None, eta_row=eta_row,
-                        selection=selection)
+                        selection=selection, denominator=denominator)
     got["parity"] = stats
     print("pivot parity", stats)
     assert stats["col_pinned"] > 0 and stats["row_pinned"] > 0
     ora = iterative_cur(A64, tol, b, kind=kind, seed=seed, record=True,
-                        max_rank=kw.get("max_rank") or None, selection=selection)
+                        max_rank=kw.get("max_rank") or None, selection=selection, denominator=denominator)
     # U against the oracle's pseudo-inverse of the same cross: both are backward stable,
     # so they differ by at most a few cond(A(I,J)) 2^-52 relative
     err = exact_relative_error(A64, I, J, U) if r else 1.0
@@ -144,6 +145,18 @@ def test_qrcp_selection_matches_oracle(icur, kind):
     lu = icur.run(torch.from_numpy(A32).cuda(), 1e-5, 32, kind, 2)
     assert got["status"] == "ok" and err <= 2e-5 and 0.5 <= got["rho"] / err <= 2.0
     assert abs(got["rank"] - ora["rank"]) <= 32 and abs(got["rank"] - lu["rank"]) <= 64
+
+
+@pytest.mark.parametrize("denominator", [0, 1])
+def test_srtt_sketch_matches_oracle(icur, denominator):
+    # the SRTT operator (FP32 values on FP32 matrix cores, 32-deep chunks summed in FP64):
+    # every pivot replayed through the oracle's SRTT run
+    A, _ = W.planted_geometric(2000, 1500, 30.0, seed=7)
+    A32, _ = W.to_f32(A)
+    got, ora, err = check_against_oracle(icur, A32, 1e-5, 40, icur.SRTT, 4, eta=sketch_eta(0, 32),
+                                         denominator=denominator)
+    assert got["status"] == "ok" and err <= 2e-5 and 0.5 <= got["rho"] / err <= 2.0
+    assert abs(got["rank"] - ora["rank"]) <= 40
 
 
 def test_fp32_matrix_core_sketch_option(icur):

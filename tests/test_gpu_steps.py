@@ -239,6 +239,19 @@ def test_residual_product_fp64(icur, M, K, N, inplace):
     assert nsq == pytest.approx(float((got ** 2).sum()), rel=1e-12)
 
 
+# ----------------------------------------------------------------- SRTT operator
+@pytest.mark.parametrize("c,m,seed", [(11, 97, 3), (110, 40000, 0), (35, 8000, 5), (64, 64, 1)])
+def test_srtt_operator_matches_oracle(icur, c, m, seed):
+    # kept rows bit-exact (integer generator); entries the oracle's FP64 cosines rounded to
+    # FP32 (device cos within a few FP64 ulps, far below the FP32 rounding)
+    from oracle.rng import srtt_G, srtt_rows
+    G, rows = icur.make_srtt(seed, c, m)
+    assert rows.cpu().numpy().tolist() == srtt_rows(seed, c, m).tolist()
+    want = srtt_G(seed, c, m)
+    got = G.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= U24 * np.abs(want) + 1e-15)
+
+
 # ----------------------------------------------------------------- QRCP selection
 @pytest.mark.parametrize("K,N,steps,excl_frac,seed", [
     (55, 1500, 50, 0.0, 0), (110, 40000, 100, 0.01, 1), (16, 257, 16, 0.0, 2), (1, 40, 1, 0.0, 3),
