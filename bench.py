@@ -188,8 +188,8 @@ def bench_batched(a):
             "statuses": {k: sum(1 for g in got if g["status"] == k) for k in set(g["status"] for g in got)},
             "grouped_iterations": inf["group_iterations"], "sketch_phase_ms": inf["ms_sketch"],
             "select_ms": inf["ms_select"], "products_ms": inf["ms_products"],
-            "buffer_setup_ms": inf["ms_sketch_product"], "iterations_host_ms": inf["ms_residual"],
-            "results_copy_ms": inf["ms_core"],
+            "buffer_setup_ms": inf["ms_setup"], "iterations_host_ms": inf["ms_residual"],
+            "core_products_ms": inf["ms_core"], "results_copy_ms": inf["ms_results"],
         },
         "roofline": {
             "kernel": "grouped FP64 product kernel of the batched loop (gemm_kernel: residual-form products and "

@@ -75,8 +75,9 @@ typedef struct icur_opts {
                             matrix cores; -1 = FP32 (plain form) or BF16 pieces (split form),
                             which round N_k^-1 before it multiplies, so the estimate can be
                             off by about cond(N_k) 2^-24: only for well-conditioned blocks */
-  int32_t batch_workers; /* icur_run_batched only: matrices run concurrently, 0 -> 16,
-                            at most 16; ignored by the single-matrix calls */
+  int32_t batch_workers; /* icur_run_batched only: 0 (default) the grouped form; 1..16
+                            the worker form with that many concurrent matrices; ignored
+                            by the single-matrix calls */
   int32_t denominator;  /* estimate's denominator: ICUR_DENOM_GA (0, default, Alg. 1) or
                            ICUR_DENOM_A (1): rho = ||S^col||_F / (s_G ||A||_F), the quantity
                            the §3.3 Corollary bounds (s_G^2 = c for the Gaussian G, min(zeta,c)
@@ -114,12 +115,15 @@ typedef struct icur_info {
                                  block is cut short); I and J are these blocks in order */
   /* icur_run_batched, grouped form: ms_sketch above is the batch's sketch phase,
      ms_select the device time of its grouped selections, ms_residual the host clock of
-     the grouped iterations, ms_core the copies of the results to the caller's pools and
-     ms_sketch_product the set-up of the per-matrix buffers; and: */
+     the grouped iterations and ms_core the device time of the closing core products
+     (ms_sketch_product is 0); and: */
   double  ms_products;        /* device time of the grouped FP64 product launches */
-  double  product_bytes;      /* their algorithmic bytes: operands read once, output written once */
+  double  product_bytes;      /* their algorithmic bytes: the nonzero parts of the operands
+                                 read once, the output written once */
   int32_t product_launches;
   int32_t group_iterations;   /* grouped iterations (the longest matrix's count) */
+  double  ms_setup;           /* host clock of the per-matrix buffer set-up */
+  double  ms_results;         /* host clock of the copies to the caller's pools */
 } icur_info;
 
 /*
@@ -163,11 +167,21 @@ int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals
 
 /*
  * icur_run_batched: Alg. 1 on `count` independent dense FP32 matrices of uneven sizes and
- * tolerances (many small CUR problems at once; each follows Alg. 1 on its own).  The
- * matrices run concurrently, opts->batch_workers (default 16) at a time, each on a worker
- * stream of its own with its own cached workspace, largest first; the caller's stream (opts->stream) is waited on
- * before any of them starts.  Each matrix gets exactly the result icur_run would return
- * for it (same kernels, same arithmetic).
+ * tolerances (many small CUR problems at once; each follows Alg. 1 on its own).
+ *   Grouped form (opts->batch_workers == 0, the default): every matrix with max(m, n) <=
+ *   8192 (with block <= 64, LUPP selection and FP64 residual factors) advances together
+ *   with the others, one launch per step of Alg. 1 for all of them, on the caller's
+ *   stream; its rank-sized buffers come from one device arena that the call keeps for
+ *   the next one (icur_release frees it), and its results are copied to the pools by a
+ *   helper thread while the others go on.  Each matrix's arithmetic is its own (the
+ *   result does not depend on the rest of the batch); its pivots are icur_run's
+ *   wherever the selection is not decided by rounding, its core is A(I,J)^{-1} formed
+ *   from the two block-triangular factors of A(I,J).
+ *   Worker form (batch_workers 1..16), and matrices the grouped form does not take: the
+ *   matrices run concurrently, batch_workers (16 for the rest of a grouped call) at a
+ *   time, each on a worker stream with its own cached workspace, largest first; each
+ *   gets exactly the result icur_run returns for it (same kernels, same arithmetic).
+ * The caller's stream (opts->stream) is waited on before any matrix starts.
  *   count        >= 0 (0 returns ICUR_OK at once).
  *   A, m, n, lda host arrays of count entries: device pointer, rows, columns and leading
  *                dimension of each matrix (row-major, lda[i] >= n[i]).
@@ -198,7 +212,7 @@ int icur_last_info(icur_info* info);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* icur_last_error(void);
 
-/* Free the calling process's cached device workspaces (all devices). */
+/* Free the calling process's cached device workspaces and batched arenas (all devices). */
 int icur_release(void);
 
 /* ------------------------------------------------------------------------------------

@@ -1167,8 +1167,9 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   t_info.product_launches = gstat.product_launches;
   t_info.group_iterations = gstat.iterations;
   t_info.ms_residual = gstat.ms_loop;
-  t_info.ms_core = gstat.ms_results;
-  t_info.ms_sketch_product = gstat.ms_alloc;
+  t_info.ms_core = gstat.ms_final;
+  t_info.ms_setup = gstat.ms_alloc;
+  t_info.ms_results = gstat.ms_results;
   t_info.iterations = static_cast<int32_t>(std::min<int64_t>(total_iters, INT32_MAX));
   t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (first_err != ICUR_OK) {
@@ -1212,6 +1213,7 @@ int icur_release(void) {
   }
   g_cache.clear();
   release_blas_handles();
+  release_batch_arenas();
   ICUR_HIP(hipSetDevice(dev0));
   return ICUR_OK;
 }

@@ -46,16 +46,19 @@ struct BatchMat {
   uint8_t* rowmask;   // m
   int64_t* Jk;        // b
   int64_t* Ik;        // b
-  // rank-sized buffers (capacity cap, grown by the host between iterations)
-  double* LcT;        // cap x m: column factors (row t = S^{(k-1)}(:, J_k[t])^T)
+  // rank-sized buffers (capacity cap, grown by the host between iterations).  The core
+  // A(I,J)^{-1} is kept factored: A(I,J) = P Q with P = Lc(I,:) block lower triangular
+  // (diagonal blocks N_k) and Q = Ur(:,J) block upper triangular with identity diagonal
+  // blocks, so A(I,J)^{-1} = Q^{-1} P^{-1}; both inverses grow by one block per iteration
+  // and are multiplied out once, after the loop.
+  double* LcT;        // cap x m: column factors (row t = S^{(k-1)}(:, J_k[t])^T); after the
+                      // loop the core A(I,J)^{-1}, r x r, leading dimension r
   double* Ur;         // cap x n: row factors (N_k^{-1} S^{(k-1)}(I_k, :))
-  double* U;          // cap x cap: the core A(I,J)^{-1}, leading dimension cap
-  double* Wa;         // b x cap: Ur(:, J_k)^T, then Lc(I_k, :)
-  double* AIJk;       // cap x b: A(I, J_k)
-  double* AIkJ;       // b x cap: A(I_k, J)
-  double* Y;          // cap x b: U A(I, J_k)
-  double* Z;          // b x cap: A(I_k, J) U
-  double* V;          // cap x b: Y N_k^{-1}
+  double* QT;         // cap x cap: (Q^{-1})^T, block lower triangular, identity diagonal blocks
+  double* Pi;         // cap x cap: P^{-1}, block lower triangular, diagonal blocks N_k^{-1}
+  double* Wa;         // b x cap: Ur(:, J_k)^T, the new block column of Q (transposed)
+  double* Wl;         // b x cap: Lc(I_k, :), the new block row of P
+  double* Wp;         // b x cap: N_k^{-1} Lc(I_k, :)
   int64_t* Jall;      // cap
   int64_t* Iall;      // cap
   int cap;
@@ -71,7 +74,7 @@ struct BatchMat {
   double thr;         // stopping threshold xi * tol
   double rho;
   int nparts;         // norm partials written by the last update
-  int pad;
+  int fin;            // the core has been multiplied out (set once the matrix stops)
 };
 
 // The column (rows = false) or row selection of every unfinished matrix, one workgroup
@@ -116,6 +119,7 @@ struct BatchedCall {
   int product_launches;   // out
   double ms_alloc;        // out: host clock of the buffer set-up after the sketch
   double ms_loop;         // out: host clock of the grouped iterations
+  double ms_final;        // out: device time of the closing core products Q^{-1} P^{-1}
   double ms_results;      // out: host clock of the copies to the caller's pools
 };
 
@@ -124,5 +128,8 @@ struct BatchedCall {
 // failures go to status / errs; the return value is an error only when the whole group
 // could not run.
 int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream_t st);
+
+// Frees the device arenas the grouped calls keep between calls (all devices).
+void release_batch_arenas();
 
 }  // namespace icur

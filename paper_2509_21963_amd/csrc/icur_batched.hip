@@ -7,13 +7,24 @@
 //      grouped selections, grouped gathers and FP64 products, the pivot-block inverses,
 //      the bordered core and the stopping decision), then one read-back of a small record
 //      per matrix (rank, state), from which the host only grows rank-sized buffers;
-//   3. results: I, J and the core U of each matrix copied to the caller's pools.
+//   3. results: a matrix that stops has its core multiplied out at the end of that
+//      iteration (one launch for all that stopped), and a copy thread moves its I, J
+//      and core to the caller's pools while the others go on.
+// The rank-sized buffers come from one device arena: at the full rank bound when that
+// fits in free memory, else at a fraction of it, grown (first fit, stream ordered) when
+// a matrix needs more.
 // Each matrix follows Alg. 1 on its own: the grouping changes no arithmetic.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "icur_batched.h"
@@ -22,8 +33,11 @@ namespace icur {
 
 int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
                            int grid, hipStream_t st, hipEvent_t* ev);
+int launch_batch_final(BatchMat* mats, int count, int c, int b, void* plan_ws, int grid, hipStream_t st);
 size_t batch_plan_bytes(int count);
 double* batch_plan_bytes_ptr(void* plan_ws, int count);
+int batch_plan_stages();
+int batch_plan_final_stage();
 
 namespace {
 
@@ -31,7 +45,7 @@ size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Rank-sized part of a matrix's state for capacity cap.
 size_t rank_bytes(int64_t cap, int64_t m, int64_t n, int64_t b) {
-  return al(cap * m * 8) + al(cap * n * 8) + al(cap * cap * 8) + 6 * al(b * cap * 8) + 2 * al(cap * 8);
+  return al(cap * m * 8) + al(cap * n * 8) + 2 * al(cap * cap * 8) + 3 * al(b * cap * 8) + 2 * al(cap * 8);
 }
 
 void bind_rank(BatchMat& bm, char* p, int64_t cap, int64_t b) {
@@ -40,10 +54,12 @@ void bind_rank(BatchMat& bm, char* p, int64_t cap, int64_t b) {
   p += al(cap * m * 8);
   bm.Ur = reinterpret_cast<double*>(p);
   p += al(cap * n * 8);
-  bm.U = reinterpret_cast<double*>(p);
+  bm.QT = reinterpret_cast<double*>(p);
   p += al(cap * cap * 8);
-  double** six[6] = {&bm.Wa, &bm.AIJk, &bm.AIkJ, &bm.Y, &bm.Z, &bm.V};
-  for (double** q : six) {
+  bm.Pi = reinterpret_cast<double*>(p);
+  p += al(cap * cap * 8);
+  double** three[3] = {&bm.Wa, &bm.Wl, &bm.Wp};
+  for (double** q : three) {
     *q = reinterpret_cast<double*>(p);
     p += al(b * cap * 8);
   }
@@ -53,8 +69,15 @@ void bind_rank(BatchMat& bm, char* p, int64_t cap, int64_t b) {
   bm.cap = static_cast<int>(cap);
 }
 
+// Columns right of a row's diagonal block that the grouped products may read (the band
+// written with each new block row, see icur_group_kernels.hip): kGMaxSteps + 128.
+constexpr int64_t kCoreBand = kGMaxSteps + 128;
+
 struct DevBuf {
   void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
@@ -69,7 +92,165 @@ struct DevBuf {
   }
 };
 
+// First-fit allocator over one device arena (offsets in 256-byte units of the arena).
+// Regions are released in stream order: every use of a region is enqueued on the one
+// stream of the loop, so a later allocation of the same bytes is used after them.
+class Arena {
+ public:
+  char* base = nullptr;
+  size_t size = 0;
+  void reset(void* p, size_t bytes) {
+    base = static_cast<char*>(p);
+    size = bytes & ~size_t(255);
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  char* take(size_t bytes) {
+    bytes = al(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > bytes) free_[off + bytes] = len - bytes;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void give(char* p, size_t bytes) {
+    size_t off = static_cast<size_t>(p - base);
+    bytes = al(bytes);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  bool owns(const char* p) const { return p >= base && p < base + size; }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+// The arena of the last grouped call on each device, kept for the next one (allocating
+// and clearing a few hundred GB of device memory costs seconds); released by icur_release.
+// A call takes it out for its duration, so concurrent calls never share one.
+struct CachedArena {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_arena_mu;
+std::map<int, CachedArena> g_arenas;
+
+CachedArena take_arena(int device) {
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  CachedArena a = g_arenas[device];
+  g_arenas[device] = CachedArena();
+  return a;
+}
+
+void put_arena(int device, CachedArena a) {
+  if (!a.p) return;
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  CachedArena& slot = g_arenas[device];
+  if (slot.p && slot.bytes >= a.bytes) {
+    (void)hipFree(a.p);
+    return;
+  }
+  if (slot.p) (void)hipFree(slot.p);
+  slot = a;
+}
+
+// Owns a call's arena; gives it back to the cache at the end of the call.
+struct ArenaHold {
+  int device = 0;
+  CachedArena a;
+  ~ArenaHold() { put_arena(device, a); }
+};
+
+// A host thread that copies finished matrices' results to the caller's (pageable) pools
+// on a stream of its own while the loop goes on.
+class ResultCopier {
+ public:
+  struct Job {
+    void* dst[3];
+    const void* src[3];
+    size_t bytes[3];
+  };
+  explicit ResultCopier(int device) : th_([this, device] { run(device); }) {}
+  ~ResultCopier() { finish(); }
+  void push(const Job& j) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q_.push_back(j);
+    }
+    cv_.notify_one();
+  }
+  // Waits for every queued copy; returns the first failure's message ("" when none).
+  std::string finish() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      done_ = true;
+    }
+    cv_.notify_one();
+    if (th_.joinable()) th_.join();
+    return err_;
+  }
+
+ private:
+  void run(int device) {
+    hipStream_t cs = nullptr;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      err_ = "copy thread: no stream";
+      cs = nullptr;
+    }
+    for (;;) {
+      Job j;
+      {
+        std::unique_lock<std::mutex> g(mu_);
+        cv_.wait(g, [this] { return done_ || !q_.empty(); });
+        if (q_.empty()) break;
+        j = q_.front();
+        q_.pop_front();
+      }
+      if (!cs || !err_.empty()) continue;
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        if (j.bytes[k]) e = hipMemcpyAsync(j.dst[k], j.src[k], j.bytes[k], hipMemcpyDeviceToHost, cs);
+      if (e == hipSuccess) e = hipStreamSynchronize(cs);
+      if (e != hipSuccess) err_ = std::string("copy of the results: ") + hipGetErrorString(e);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<Job> q_;
+  bool done_ = false;
+  std::string err_;
+  std::thread th_;
+};
+
 }  // namespace
+
+void release_batch_arenas() {
+  std::lock_guard<std::mutex> g(g_arena_mu);
+  int dev0 = 0;
+  (void)hipGetDevice(&dev0);
+  for (auto& kv : g_arenas) {
+    if (!kv.second.p) continue;
+    (void)hipSetDevice(kv.first);
+    (void)hipFree(kv.second.p);
+  }
+  g_arenas.clear();
+  (void)hipSetDevice(dev0);
+}
 
 // Runs the matrices listed in `which` (all with max(m, n) <= kGMaxN, block <= kGMaxSteps).
 int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream_t st) {
@@ -197,7 +378,7 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   const double sg2 = a.kind == ICUR_SKETCH_GAUSSIAN ? static_cast<double>(c)
                      : a.kind == ICUR_SKETCH_SRTT   ? 1.0
                                                     : static_cast<double>(std::min<int64_t>(zeta, c));
-  std::vector<DevBuf> rankbuf(count);
+  std::vector<char> live(count, 0);
   for (int q = 0; q < count; ++q) {
     const int i = which[q];
     BatchMat& bm = hm[q];
@@ -217,15 +398,77 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
     a.est[i] = rho0;
     if (g2 == 0.0 || (denom_a && rho0 <= bm.thr)) continue;  // rank 0
     bm.s = static_cast<int>(std::min<int64_t>(b, bm.rmax));
-    // rank-sized buffers for the whole rank bound when they fit (no growth, no host
-    // synchronisation inside the loop); else a quarter of it, grown on demand
-    int64_t cap = bm.rmax;
-    if (rankbuf[q].alloc(rank_bytes(cap, bm.m, bm.n, b)) != ICUR_OK) {
-      set_error("");
-      cap = std::min<int64_t>(bm.rmax, std::max<int64_t>(4 * b, bm.rmax / 4));
-      ICUR_TRY(rankbuf[q].alloc(rank_bytes(cap, bm.m, bm.n, b)));
+    live[q] = 1;
+  }
+  for (int q = 0; q < count; ++q) {
+    if (!live[q]) hm[q].fin = 1;  // nothing to multiply out
+  }
+  // rank-sized buffers: the whole rank bound of every matrix when that fits in the free
+  // device memory (no growth), else the largest common fraction of it that fills 60% of
+  // the arena, grown on demand
+  ArenaHold hold;
+  hold.device = dev.device;
+  hold.a = take_arena(dev.device);
+  size_t free_b = 0, total_b = 0;
+  ICUR_HIP(hipMemGetInfo(&free_b, &total_b));
+  free_b += hold.a.bytes;
+  const size_t reserve = std::max<size_t>(size_t(2) << 30, total_b / 32) + batch_plan_bytes(count) +
+                         sizeof(BatchMat) * count + (size_t(64) << 20);
+  size_t budget = free_b > reserve ? free_b - reserve : 0;
+  // ICUR_BATCH_MEMORY_LIMIT (bytes) lowers the budget, which exercises the growth path
+  if (const char* lim = std::getenv("ICUR_BATCH_MEMORY_LIMIT")) {
+    const unsigned long long v = std::strtoull(lim, nullptr, 10);
+    if (v > 0) budget = std::min<size_t>(budget, static_cast<size_t>(v));
+  }
+  std::vector<int64_t> cap0(count, 0);
+  auto total_for = [&](double f) {
+    size_t t = 0;
+    for (int q = 0; q < count; ++q) {
+      if (!live[q]) continue;
+      const BatchMat& bm = hm[q];
+      const int64_t cq = std::min<int64_t>(bm.rmax, std::max<int64_t>(std::min<int64_t>(4 * b, bm.rmax),
+                                                                      static_cast<int64_t>(std::ceil(f * bm.rmax))));
+      cap0[q] = cq;
+      t += al(rank_bytes(cq, bm.m, bm.n, b));
     }
-    bind_rank(bm, static_cast<char*>(rankbuf[q].p), cap, b);
+    return t;
+  };
+  size_t need = total_for(1.0);
+  size_t arena_bytes = need;
+  if (need > budget) {
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 30; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (total_for(mid) <= budget * 6 / 10) lo = mid;
+      else hi = mid;
+    }
+    need = total_for(lo);
+    arena_bytes = std::max(need, budget);
+  }
+  if (need > 0 && hold.a.bytes < arena_bytes) {
+    if (hold.a.p) ICUR_HIP(hipFree(hold.a.p));
+    hold.a = CachedArena();
+    void* p = nullptr;
+    if (hipMalloc(&p, arena_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      arena_bytes = need;
+      if (hipMalloc(&p, arena_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of " + std::to_string(arena_bytes) + " bytes failed (batched)");
+        return ICUR_ERR_NOMEM;
+      }
+    }
+    hold.a.p = p;
+    hold.a.bytes = arena_bytes;
+  }
+  Arena arena;
+  arena.reset(hold.a.p, need > 0 ? arena_bytes : 0);
+  std::deque<DevBuf> extra;  // growth beyond the arena (a deque: elements never move)
+  for (int q = 0; q < count; ++q) {
+    if (!live[q]) continue;
+    char* p = arena.take(rank_bytes(cap0[q], hm[q].m, hm[q].n, b));
+    if (!p) return arg_error("batched: arena plan");  // cannot happen: sized from the same sums
+    bind_rank(hm[q], p, cap0[q], b);
   }
   a.ms_alloc = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_al0).count();
   DevBuf mats, plan;
@@ -242,8 +485,9 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   ICUR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&drec), hrec, 0));
   ICUR_HIP(hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st));
   const int grid = 4 * dev.num_cus;
-  // device events around the selections and the product stages of every iteration
-  constexpr int kEv = 12;
+  // device events around the selections, the product stages and the closing core
+  // products of every iteration
+  constexpr int kEv = 14;
   hipEvent_t ev[kEv];
   for (int e = 0; e < kEv; ++e) ICUR_HIP(hipEventCreate(&ev[e]));
   struct EvFree {
@@ -252,18 +496,62 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
       for (int q = 0; q < kEv; ++q) (void)hipEventDestroy(e[q]);
     }
   } ev_guard{ev};
-  ICUR_HIP(hipMemsetAsync(batch_plan_bytes_ptr(plan.p, count), 0, 8 * 8, st));
-  a.ms_select = a.ms_products = 0.0;
+  ICUR_HIP(hipMemsetAsync(batch_plan_bytes_ptr(plan.p, count), 0, sizeof(double) * batch_plan_stages(), st));
+  a.ms_select = a.ms_products = a.ms_final = 0.0;
   a.product_launches = 0;
+
+  // a matrix that stops: its results to the copy thread (its core was multiplied out by
+  // the same iteration's closing launch)
+  ResultCopier copier(dev.device);
+  auto settle = [&](int q) {
+    const int i = which[q];
+    const BatchMat& bm = hm[q];
+    if (bm.status == ICUR_ERR_HIP || bm.info != 0) {
+      a.status[i] = ICUR_ERR_HIP;
+      a.errs[i] = "the residual block N_k = S(I_k, J_k) is exactly singular";
+      a.rank[i] = 0;
+      a.est[i] = 0.0;
+      return;
+    }
+    const int64_t r = bm.r;
+    a.rank[i] = r;
+    a.est[i] = bm.rho;
+    a.status[i] = bm.status;
+    if (r == 0) return;
+    ResultCopier::Job j;
+    j.dst[0] = a.I_pool + a.cap_offsets[i];
+    j.src[0] = bm.Iall;
+    j.bytes[0] = r * 8;
+    j.dst[1] = a.J_pool + a.cap_offsets[i];
+    j.src[1] = bm.Jall;
+    j.bytes[1] = r * 8;
+    j.dst[2] = a.U_pool + a.uoff[i];
+    j.src[2] = bm.LcT;
+    j.bytes[2] = r * r * 8;
+    copier.push(j);
+  };
 
   bool any = false;
   for (const BatchMat& bm : hm) any |= bm.s != 0;
   int iters = 0;
   const auto t_loop0 = std::chrono::steady_clock::now();
-  while (any) {
-    ICUR_TRY(launch_batch_iteration(dmats, count, static_cast<int>(c), static_cast<int>(b), a.row_cut, plan.p, drec,
-                                    grid, st, ev));
-    ICUR_HIP(hipStreamSynchronize(st));
+  int err_loop = ICUR_OK;
+  while (any && err_loop == ICUR_OK) {
+    err_loop = launch_batch_iteration(dmats, count, static_cast<int>(c), static_cast<int>(b), a.row_cut, plan.p, drec,
+                                      grid, st, ev);
+    if (err_loop != ICUR_OK) break;
+    if (hipEventRecord(ev[12], st) != hipSuccess ||
+        (err_loop = launch_batch_final(dmats, count, static_cast<int>(c), static_cast<int>(b), plan.p, grid, st)) !=
+            ICUR_OK ||
+        hipEventRecord(ev[13], st) != hipSuccess) {
+      if (err_loop == ICUR_OK) err_loop = hip_error(hipGetLastError(), "batched: event record");
+      break;
+    }
+    const hipError_t se = hipStreamSynchronize(st);
+    if (se != hipSuccess) {
+      err_loop = hip_error(se, "batched loop");
+      break;
+    }
     ++iters;
     for (int e = 0; e < kEv; e += 2) {
       float ms = 0.f;
@@ -273,14 +561,16 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
       }
       if (e < 4) {
         a.ms_select += ms;
-      } else {
+      } else if (e < 12) {
         a.ms_products += ms;
         a.product_launches += 1;
+      } else {
+        a.ms_final += ms;
       }
     }
     any = false;
     bool grow = false;
-    for (int q = 0; q < count; ++q) {
+    for (int q = 0; q < count && err_loop == ICUR_OK; ++q) {
       BatchMat& bm = hm[q];
       if (bm.s == 0) continue;
       const BatchRec& rc = hrec[q];
@@ -290,69 +580,75 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
       bm.info = rc.info;
       bm.iters = rc.iters;
       bm.rho = rc.rho;
-      if (bm.s == 0) continue;
+      if (bm.s == 0) {
+        bm.fin = 1;  // as the device set it in this iteration's closing launch
+        settle(q);
+        continue;
+      }
       any = true;
       if (bm.r + bm.s > bm.cap) {
-        // grow the rank-sized buffers: keep LcT, Ur (rows 0..r), U (r x r, new leading
-        // dimension) and the index lists
+        // grow the rank-sized buffers: keep LcT, Ur and the two inverses (rows 0..r, new
+        // leading dimension) and the index lists
         const int64_t ncap = std::min<int64_t>(bm.rmax, std::max<int64_t>(2 * bm.cap, bm.r + bm.s));
-        DevBuf nb;
-        ICUR_TRY(nb.alloc(rank_bytes(ncap, bm.m, bm.n, b)));
+        const size_t nbytes = rank_bytes(ncap, bm.m, bm.n, b);
+        char* np = arena.take(nbytes);
+        if (!np) {
+          extra.emplace_back();
+          err_loop = extra.back().alloc(nbytes);
+          if (err_loop != ICUR_OK) break;
+          np = static_cast<char*>(extra.back().p);
+        }
         BatchMat nm = bm;
-        bind_rank(nm, static_cast<char*>(nb.p), ncap, b);
+        bind_rank(nm, np, ncap, b);
         const size_t r = static_cast<size_t>(bm.r);
-        ICUR_HIP(hipMemcpyAsync(nm.LcT, bm.LcT, r * bm.m * 8, hipMemcpyDeviceToDevice, st));
-        ICUR_HIP(hipMemcpyAsync(nm.Ur, bm.Ur, r * bm.n * 8, hipMemcpyDeviceToDevice, st));
-        if (r > 0)
-          ICUR_HIP(hipMemcpy2DAsync(nm.U, ncap * 8, bm.U, static_cast<size_t>(bm.cap) * 8, r * 8, r,
-                                    hipMemcpyDeviceToDevice, st));
-        ICUR_HIP(hipMemcpyAsync(nm.Jall, bm.Jall, r * 8, hipMemcpyDeviceToDevice, st));
-        ICUR_HIP(hipMemcpyAsync(nm.Iall, bm.Iall, r * 8, hipMemcpyDeviceToDevice, st));
-        ICUR_HIP(hipStreamSynchronize(st));
-        std::swap(rankbuf[q].p, nb.p);
+        hipError_t e = hipMemcpyAsync(nm.LcT, bm.LcT, r * bm.m * 8, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(nm.Ur, bm.Ur, r * bm.n * 8, hipMemcpyDeviceToDevice, st);
+        if (r > 0) {
+          // the r block rows of both inverses, their band beyond the old width zeroed
+          const size_t oc = static_cast<size_t>(bm.cap);
+          const size_t zc = std::min<size_t>(ncap, r + kCoreBand);
+          for (int f = 0; f < 2 && e == hipSuccess; ++f) {
+            double* dst = f ? nm.Pi : nm.QT;
+            const double* src = f ? bm.Pi : bm.QT;
+            e = hipMemcpy2DAsync(dst, ncap * 8, src, oc * 8, oc * 8, r, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess && zc > oc) e = hipMemset2DAsync(dst + oc, ncap * 8, 0, (zc - oc) * 8, r, st);
+          }
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(nm.Jall, bm.Jall, r * 8, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(nm.Iall, bm.Iall, r * 8, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) {
+          err_loop = hip_error(e, "batched: growth copies");
+          break;
+        }
+        // the old region is free for later allocations (stream ordered)
+        char* old = reinterpret_cast<char*>(bm.LcT);
+        if (arena.owns(old)) arena.give(old, rank_bytes(bm.cap, bm.m, bm.n, b));
         bm = nm;
         grow = true;
       }
     }
-    if (grow) ICUR_HIP(hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st));
+    if (grow && err_loop == ICUR_OK) {
+      const hipError_t e = hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) err_loop = hip_error(e, "batched: state upload");
+    }
   }
   a.ms_loop = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_loop0).count();
   const auto t_res0 = std::chrono::steady_clock::now();
-  // final state of every matrix (the host mirror holds r, status and rho of the last
-  // iteration of each)
-  ICUR_HIP(hipMemcpyAsync(hm.data(), dmats, sizeof(BatchMat) * count, hipMemcpyDeviceToHost, st));
+  const std::string cerr = copier.finish();
+  if (err_loop != ICUR_OK) return err_loop;
+  if (!cerr.empty()) {
+    set_error(cerr);
+    return ICUR_ERR_HIP;
+  }
   double stage_bytes[8];
-  ICUR_HIP(hipMemcpyAsync(stage_bytes, batch_plan_bytes_ptr(plan.p, count), sizeof(stage_bytes), hipMemcpyDeviceToHost,
-                          st));
+  if (batch_plan_stages() > 8) return arg_error("batched: plan stage count");
+  ICUR_HIP(hipMemcpyAsync(stage_bytes, batch_plan_bytes_ptr(plan.p, count), sizeof(double) * batch_plan_stages(),
+                          hipMemcpyDeviceToHost, st));
   ICUR_HIP(hipStreamSynchronize(st));
   a.iterations = iters;
   a.product_bytes = 0.0;
-  for (double v : stage_bytes) a.product_bytes += v;
-
-  // ---- results
-  for (int q = 0; q < count; ++q) {
-    const int i = which[q];
-    const BatchMat& bm = hm[q];
-    if (a.status[i] < 0 && bm.cap == 0) continue;  // non-finite sketch
-    if (bm.cap == 0) continue;                       // rank 0 (a zero matrix, or met at once)
-    if (bm.status == ICUR_ERR_HIP || bm.info != 0) {
-      a.status[i] = ICUR_ERR_HIP;
-      a.errs[i] = "the residual block N_k = S(I_k, J_k) is exactly singular";
-      a.rank[i] = 0;
-      a.est[i] = 0.0;
-      continue;
-    }
-    const int64_t r = bm.r;
-    a.rank[i] = r;
-    a.est[i] = bm.rho;
-    a.status[i] = bm.status;
-    if (r == 0) continue;
-    ICUR_HIP(hipMemcpyAsync(a.I_pool + a.cap_offsets[i], bm.Iall, r * 8, hipMemcpyDeviceToHost, st));
-    ICUR_HIP(hipMemcpyAsync(a.J_pool + a.cap_offsets[i], bm.Jall, r * 8, hipMemcpyDeviceToHost, st));
-    ICUR_HIP(hipMemcpy2DAsync(a.U_pool + a.uoff[i], r * 8, bm.U, static_cast<size_t>(bm.cap) * 8, r * 8, r,
-                              hipMemcpyDeviceToHost, st));
-  }
-  ICUR_HIP(hipStreamSynchronize(st));
+  for (int q = 0; q < batch_plan_stages(); ++q)
+    if (q != batch_plan_final_stage()) a.product_bytes += stage_bytes[q];
   a.ms_results = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_res0).count();
   return ICUR_OK;
 }

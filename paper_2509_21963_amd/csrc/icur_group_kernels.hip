@@ -4,9 +4,15 @@
 // launch configuration never depends on the data (the same launches every iteration).
 //
 // Products are OUT(M x N) = beta X + alpha W(M x K) B(K x N) in FP64 on the FP64 matrix
-// cores (v_mfma_f64_16x16x4f64): tiles of 32 rows x 128 columns, the whole depth K per
-// tile in 32-deep chunks (W staged through LDS, B straight to registers), so the result
-// of every element is a fixed-order FP64 sum that does not depend on the grouping.
+// cores (v_mfma_f64_16x16x4f64): tiles of 32 rows x 128 columns, the depth K per tile in
+// 32-deep chunks (W staged through LDS, B straight to registers), so the result of every
+// element is a fixed-order FP64 sum that does not depend on the grouping.  Products with
+// a block-triangular operand skip the depth range where that operand is zero.
+//
+// The core A(I,J)^{-1} is carried as two block-triangular inverses (A(I,J) = P Q with
+// P = Lc(I,:), Q = Ur(:,J); see BatchMat): each iteration appends one block row to
+// (Q^{-1})^T and to P^{-1}, reading only their nonzero halves, and one product after the
+// loop forms Q^{-1} P^{-1}.
 #include <algorithm>
 #include <climits>
 
@@ -37,10 +43,14 @@ struct GemmOp {
   double alpha;
   double* normp;    // per-tile sums of OUT^2 (indexed by the op's local tile), or null
   int tile0, pad;   // pad: the op's tile count while the plan is built
+  int wt;           // W stored transposed: W(row, k) at W[k * ldw + row]
+  int kskip;        // bit 0: W(row, k) = 0 for k < row - kband; bit 1: B(k, col) = 0 for
+                    // k < col - kband (block-triangular operands, blocks of <= kband + 1)
+  int kband, pad2;
 };
 
 struct GatherOp {
-  const void* src;  // FP32 when f32, else FP64
+  const void* src;  // FP32 when f32, else FP64; null: the identity (times scale)
   int64_t rs, cs;   // src element strides per row index / column index
   const int64_t* ridx;
   const int64_t* cidx;
@@ -53,9 +63,15 @@ struct GatherOp {
 
 // Stage lists of one iteration.  Phase 0 (after the column selection): gathers GA and
 // the row-residual product P1.  Phase 1 (after the row selection): gathers GB, products
-// P2 (with the core's Y and Z), P3 (with V), P4 (with the core update), copies GC.
-enum Stage { kGA, kP1, kGB, kP2, kP3, kP4, kGC, kNumStages };
-constexpr int kOpsPerMat = 6;
+// P2, P3, P4 (residual form and the two inverses' new block rows), copies GC (their
+// diagonal blocks).  Phase 2, once after the loop: the core products FIN.
+enum Stage { kGA, kP1, kGB, kP2, kP3, kP4, kGC, kFin, kNumStages };
+constexpr int kOpsPerMat = 4;
+// Columns right of a new diagonal block that are written with it (identity or zeros), so
+// that every entry a depth-skipping product reads inside its tile is defined: a tile of
+// kColsT columns starting at n0 reads rows k >= n0 - kband, so entries up to k + kband +
+// kColsT - 1 to the right of the diagonal.
+constexpr int kBandCols = kGMaxSteps + kColsT;
 
 struct Plan {
   GemmOp* gemm[kNumStages];
@@ -69,14 +85,20 @@ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; 
 
 // Ops occupy fixed slots (matrix i, slot k -> entry i * kOpsPerMat + k); an unused slot has
 // no tiles.  tile0 is filled in afterwards by a scan over the entries.
+__device__ __forceinline__ double tri_sum(int64_t j) { return j > 0 ? 0.5 * static_cast<double>(j) * (j + 1) : 0.0; }
+
 __device__ __forceinline__ void set_gemm(GemmOp* ops, int i, int k, const double* X, int64_t ldx, const double* W,
                                          int64_t ldw, const double* B, int64_t ldb, double* OUT, int64_t ldo, int M,
-                                         int K, int N, double alpha, double* normp, double* bytes = nullptr) {
+                                         int K, int N, double alpha, double* normp, double* bytes = nullptr,
+                                         int kskip = 0, int kband = 0, int wt = 0) {
   GemmOp& o = ops[i * kOpsPerMat + k];
-  // algorithmic bytes: W and B read once, OUT written once, X read once when given
-  if (bytes && M > 0 && N > 0)
-    atomicAdd(bytes, 8.0 * (static_cast<double>(M) * K + static_cast<double>(K) * N +
-                            static_cast<double>(M) * N * (X ? 2.0 : 1.0)));
+  // algorithmic bytes: the nonzero parts of W and B read once, OUT written once, X read
+  // once when given
+  if (bytes && M > 0 && N > 0) {
+    const double wnz = static_cast<double>(M) * K - ((kskip & 1) ? tri_sum(M - 1 - kband) : 0.0);
+    const double bnz = static_cast<double>(K) * N - ((kskip & 2) ? tri_sum(N - 1 - kband) : 0.0);
+    atomicAdd(bytes, 8.0 * (wnz + bnz + static_cast<double>(M) * N * (X ? 2.0 : 1.0)));
+  }
   o.X = X;
   o.ldx = ldx;
   o.W = W;
@@ -92,6 +114,13 @@ __device__ __forceinline__ void set_gemm(GemmOp* ops, int i, int k, const double
   o.alpha = alpha;
   o.normp = normp;
   o.pad = (M > 0 && N > 0) ? ceil_div(M, kRowsT) * o.tiles_n : 0;  // tiles (until the scan)
+  o.wt = wt;
+  o.kskip = kskip;
+  o.kband = kband;
+}
+
+__device__ __forceinline__ void no_gemm(GemmOp* ops, int i, int k) {
+  set_gemm(ops, i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
 }
 
 __device__ __forceinline__ void set_gather(GatherOp* ops, int i, int k, const void* src, bool f32, int64_t rs,
@@ -111,6 +140,10 @@ __device__ __forceinline__ void set_gather(GatherOp* ops, int i, int k, const vo
   o.tiles_c = (rows > 0 && cols > 0) ? ceil_div(cols, kGatherCols) : 0;
   o.scale = scale;
   o.pad = rows > 0 ? rows * o.tiles_c : 0;
+}
+
+__device__ __forceinline__ void no_gather(GatherOp* ops, int i, int k) {
+  set_gather(ops, i, k, nullptr, false, 0, 0, nullptr, nullptr, nullptr, 0, 0, 0, 0.0);
 }
 
 // Exclusive scan of the per-slot tile counts (held in .pad) into .tile0, and the total.
@@ -145,10 +178,12 @@ __device__ void scan_tiles(OP* ops, int n, int* total, int* nops, int* warp_sums
 }
 
 // The lists of a phase, from every matrix's state.  Phase 0 (after the column selection):
-// GA, P1.  Phase 1 (after the row selection): GB, P2, P3, P4, GC.
-__global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats, int count, int c, int phase,
+// GA, P1.  Phase 1 (after the row selection): GB, P2, P3, P4, GC.  Phase 2 (after the
+// loop): FIN.
+__global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats, int count, int c, int b, int phase,
                                                     Plan plan) {
   __shared__ int warp_sums[16];
+  const int band = b - 1;
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
     BatchMat& bm = mats[i];
     const bool on = bm.s != 0;
@@ -159,48 +194,64 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
       // GA: A(:, J_k)^T -> the next rows of LcT; Ur(:, J_k)^T -> Wa
       set_gather(plan.gather[kGA], i, 0, bm.A, true, 1, bm.lda, bm.Jk, nullptr, Lk, m, nJ, m, 1.0);
       set_gather(plan.gather[kGA], i, 1, bm.Ur, false, 1, n, bm.Jk, nullptr, bm.Wa, cap, nJ, r, 1.0);
-      for (int k = 2; k < kOpsPerMat; ++k) set_gather(plan.gather[kGA], i, k, nullptr, false, 0, 0, nullptr, nullptr, nullptr, 0, 0, 0, 0.0);
+      for (int k = 2; k < kOpsPerMat; ++k) no_gather(plan.gather[kGA], i, k);
       // P1: row residual S^row = A(:, J_k) - Lc Ur(:, J_k), stored transposed
-      set_gemm(plan.gemm[kP1], i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr, plan.bytes + kP1);
-      for (int k = 1; k < kOpsPerMat; ++k) set_gemm(plan.gemm[kP1], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
-    } else {
+      set_gemm(plan.gemm[kP1], i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr,
+               plan.bytes + kP1);
+      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kP1], i, k);
+    } else if (phase == 1) {
       const int nI = on ? bm.nI : 0;
-      const int nR = nI > 0 ? r : 0;  // the core's old block takes part from the second block on
+      const int nR = nI > 0 ? r : 0;   // products with the old blocks, from the second block on
+      const int mR = nR > 0 ? nI : 0;  // their row count
       const double* Lk = bm.LcT + static_cast<int64_t>(r) * m;
       double* Urk = bm.Ur + static_cast<int64_t>(r) * n;
-      double* U = bm.U;
-      // GB: N_k = S(I_k, J_k); A(I_k, :); Lc(I_k, :); S(:, J_k); A(I, J_k); A(I_k, J)
+      double* QTk = bm.QT + static_cast<int64_t>(r) * cap;  // new block rows of (Q^{-1})^T, P^{-1}
+      double* Pik = bm.Pi + static_cast<int64_t>(r) * cap;
+      // GB: N_k = S(I_k, J_k); A(I_k, :); Lc(I_k, :); S(:, J_k)
       set_gather(plan.gather[kGB], i, 0, Lk, false, 1, m, bm.Ik, nullptr, bm.Nk, nI, nI, nI, 1.0);
       set_gather(plan.gather[kGB], i, 1, bm.A, true, bm.lda, 1, bm.Ik, nullptr, bm.Sr, n, nI, n, 1.0);
-      set_gather(plan.gather[kGB], i, 2, bm.LcT, false, 1, m, bm.Ik, nullptr, bm.Wa, cap, nI, nR, 1.0);
+      set_gather(plan.gather[kGB], i, 2, bm.LcT, false, 1, m, bm.Ik, nullptr, bm.Wl, cap, nI, nR, 1.0);
       set_gather(plan.gather[kGB], i, 3, bm.S, false, n, 1, nullptr, bm.Jk, bm.Wc, nI, nI > 0 ? c : 0, nI, 1.0);
-      set_gather(plan.gather[kGB], i, 4, bm.A, true, bm.lda, 1, bm.Iall, bm.Jk, bm.AIJk, nI, nR, nI, 1.0);
-      set_gather(plan.gather[kGB], i, 5, bm.A, true, bm.lda, 1, bm.Ik, bm.Jall, bm.AIkJ, cap, nI, nR, 1.0);
-      // P2: residual at the new rows Sr -= Lc(I_k,:) Ur; the core's Y = U A(I,J_k), Z = A(I_k,J) U
-      set_gemm(plan.gemm[kP2], i, 0, bm.Sr, n, bm.Wa, cap, bm.Ur, n, bm.Sr, n, nR > 0 ? nI : 0, r, n, -1.0, nullptr, plan.bytes + kP2);
-      set_gemm(plan.gemm[kP2], i, 1, nullptr, 0, U, cap, bm.AIJk, nI, bm.Y, nI, nR, r, nI, 1.0, nullptr, plan.bytes + kP2);
-      set_gemm(plan.gemm[kP2], i, 2, nullptr, 0, bm.AIkJ, cap, U, cap, bm.Z, cap, nR > 0 ? nI : 0, r, r, 1.0, nullptr, plan.bytes + kP2);
-      // P3: new row factors Ur_k = N_k^{-1} Sr; V = Y N_k^{-1}
-      set_gemm(plan.gemm[kP3], i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr, plan.bytes + kP3);
-      set_gemm(plan.gemm[kP3], i, 1, nullptr, 0, bm.Y, nI, bm.Nk, nI, bm.V, nI, nR, nI, nI, 1.0, nullptr, plan.bytes + kP3);
-      // P4: column residual S -= S(:, J_k) Ur_k (with its norm partials); the core's U += V Z
-      // and its new block row -N_k^{-1} Z
-      set_gemm(plan.gemm[kP4], i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp, plan.bytes + kP4);
-      set_gemm(plan.gemm[kP4], i, 1, U, cap, bm.V, nI, bm.Z, cap, U, cap, nR, nI, r, 1.0, nullptr, plan.bytes + kP4);
-      set_gemm(plan.gemm[kP4], i, 2, nullptr, 0, bm.Nk, nI, bm.Z, cap, U + static_cast<int64_t>(r) * cap, cap,
-               nR > 0 ? nI : 0, nI, r, -1.0, nullptr, plan.bytes + kP4);
+      // P2: residual at the new rows Sr -= Lc(I_k,:) Ur; the new block row of (Q^{-1})^T,
+      // -Ur(:, J_k)^T (Q^{-1})^T (bordering Q with the block column Ur(:, J_k)); and
+      // Wp = N_k^{-1} Lc(I_k, :)
+      set_gemm(plan.gemm[kP2], i, 0, bm.Sr, n, bm.Wl, cap, bm.Ur, n, bm.Sr, n, mR, r, n, -1.0, nullptr,
+               plan.bytes + kP2);
+      set_gemm(plan.gemm[kP2], i, 1, nullptr, 0, bm.Wa, cap, bm.QT, cap, QTk, cap, mR, r, r, -1.0, nullptr,
+               plan.bytes + kP2, 2, band);
+      set_gemm(plan.gemm[kP2], i, 2, nullptr, 0, bm.Nk, nI, bm.Wl, cap, bm.Wp, cap, mR, nI, r, 1.0, nullptr,
+               plan.bytes + kP2);
+      no_gemm(plan.gemm[kP2], i, 3);
+      // P3: new row factors Ur_k = N_k^{-1} Sr; the new block row of P^{-1}, -Wp P^{-1}
+      // (bordering P with the block row Lc(I_k, :) and the diagonal block N_k)
+      set_gemm(plan.gemm[kP3], i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr,
+               plan.bytes + kP3);
+      set_gemm(plan.gemm[kP3], i, 1, nullptr, 0, bm.Wp, cap, bm.Pi, cap, Pik, cap, mR, r, r, -1.0, nullptr,
+               plan.bytes + kP3, 2, band);
+      for (int k = 2; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kP3], i, k);
+      // P4: column residual S -= S(:, J_k) Ur_k, with its norm partials
+      set_gemm(plan.gemm[kP4], i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp,
+               plan.bytes + kP4);
+      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kP4], i, k);
       bm.nparts = plan.gemm[kP4][i * kOpsPerMat].pad;
-      // GC: the core's new block column -V, and N_k^{-1} in the corner
-      set_gather(plan.gather[kGC], i, 0, bm.V, false, nI, 1, nullptr, nullptr, U + r, cap, nR, nI, -1.0);
-      set_gather(plan.gather[kGC], i, 1, bm.Nk, false, nI, 1, nullptr, nullptr, U + static_cast<int64_t>(r) * cap + r,
-                 cap, nI, nI, 1.0);
-      for (int k = 2; k < kOpsPerMat; ++k) set_gather(plan.gather[kGC], i, k, nullptr, false, 0, 0, nullptr, nullptr, nullptr, 0, 0, 0, 0.0);
-      for (int k = 3; k < kOpsPerMat; ++k) {
-        set_gemm(plan.gemm[kP2], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
-        set_gemm(plan.gemm[kP4], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
-      }
-      for (int k = 2; k < kOpsPerMat; ++k)
-        set_gemm(plan.gemm[kP3], i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
+      // GC: the diagonal blocks (identity in (Q^{-1})^T, N_k^{-1} in P^{-1}) and zeros to
+      // their right
+      const int wq = nI > 0 ? min(cap - r, nI + kBandCols) : 0;
+      const int wp = nI > 0 ? min(cap - r - nI, kBandCols) : 0;
+      set_gather(plan.gather[kGC], i, 0, nullptr, false, 0, 0, nullptr, nullptr, QTk + r, cap, nI, wq, 1.0);
+      set_gather(plan.gather[kGC], i, 1, bm.Nk, false, nI, 1, nullptr, nullptr, Pik + r, cap, nI, nI, 1.0);
+      set_gather(plan.gather[kGC], i, 2, nullptr, false, 0, 0, nullptr, nullptr, Pik + r + nI, cap, wp > 0 ? nI : 0,
+                 wp, 0.0);
+      no_gather(plan.gather[kGC], i, 3);
+    } else {
+      // FIN, for the matrices that stopped in this iteration: A(I,J)^{-1} = Q^{-1} P^{-1}
+      // into LcT (leading dimension r), depth skipped on both triangular factors
+      const bool due = bm.s == 0 && bm.fin == 0;
+      const int rf = (due && bm.info == 0 && bm.cap > 0) ? r : 0;
+      if (due) bm.fin = 1;
+      set_gemm(plan.gemm[kFin], i, 0, nullptr, 0, bm.QT, cap, bm.Pi, cap, bm.LcT, rf, rf, rf, rf, 1.0, nullptr,
+               plan.bytes + kFin, 3, band, 1);
+      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kFin], i, k);
     }
   }
   __syncthreads();
@@ -208,12 +259,14 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
   if (phase == 0) {
     scan_tiles(plan.gather[kGA], n, plan.ntiles + kGA, plan.nops + kGA, warp_sums);
     scan_tiles(plan.gemm[kP1], n, plan.ntiles + kP1, plan.nops + kP1, warp_sums);
-  } else {
+  } else if (phase == 1) {
     scan_tiles(plan.gather[kGB], n, plan.ntiles + kGB, plan.nops + kGB, warp_sums);
     scan_tiles(plan.gemm[kP2], n, plan.ntiles + kP2, plan.nops + kP2, warp_sums);
     scan_tiles(plan.gemm[kP3], n, plan.ntiles + kP3, plan.nops + kP3, warp_sums);
     scan_tiles(plan.gemm[kP4], n, plan.ntiles + kP4, plan.nops + kP4, warp_sums);
     scan_tiles(plan.gather[kGC], n, plan.ntiles + kGC, plan.nops + kGC, warp_sums);
+  } else {
+    scan_tiles(plan.gemm[kFin], n, plan.ntiles + kFin, plan.nops + kFin, warp_sums);
   }
 }
 
@@ -228,7 +281,8 @@ __device__ __forceinline__ int find_op(const OP* ops, int nops, int tile) {
   return lo;
 }
 
-// dst[i][j] = scale * src[ridx[i] rs + cidx[j] cs] (identity where an index list is null)
+// dst[i][j] = scale * src[ridx[i] rs + cidx[j] cs] (identity where an index list is null);
+// with no src, dst[i][j] = scale * (i == j)
 __global__ __launch_bounds__(kPT) void gather_kernel(const GatherOp* __restrict__ ops, const int* __restrict__ pnops,
                                                      const int* __restrict__ pntiles) {
   const int nops = *pnops, ntiles = *pntiles;
@@ -237,8 +291,12 @@ __global__ __launch_bounds__(kPT) void gather_kernel(const GatherOp* __restrict_
     const int lt = g - o.tile0;
     const int i = lt / o.tiles_c;
     const int j = (lt % o.tiles_c) * kGatherCols + threadIdx.x;
-    const int64_t ri = o.ridx ? o.ridx[i] : i;
     double* d = o.dst + static_cast<int64_t>(i) * o.ldd;
+    if (!o.src) {
+      for (int jj = j; jj < min(o.cols, j + kGatherCols); jj += kPT) d[jj] = jj == i ? o.scale : 0.0;
+      continue;
+    }
+    const int64_t ri = o.ridx ? o.ridx[i] : i;
     for (int jj = j; jj < min(o.cols, j + kGatherCols); jj += kPT) {
       const int64_t cj = o.cidx ? o.cidx[jj] : jj;
       const int64_t e = ri * o.rs + cj * o.cs;
@@ -300,13 +358,25 @@ __global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ op
         for (int s = 0; s < 2; ++s) b[j][s] = (kok && cok[s]) ? row[col[s]] : 0.0;
       }
     };
-    if (o.K > 0) load_b(0);
-    for (int k0 = 0; k0 < o.K; k0 += kKC) {
+    // depth range: block-triangular operands are zero below kbeg for the whole tile
+    int kbeg = 0;
+    if (o.kskip & 1) kbeg = max(kbeg, m0 - o.kband);
+    if (o.kskip & 2) kbeg = max(kbeg, (lt % o.tiles_n) * kColsT - o.kband);
+    if (kbeg < o.K) load_b(kbeg);
+    for (int k0 = kbeg; k0 < o.K; k0 += kKC) {
       __syncthreads();  // the previous chunk's W reads are done
-      for (int e = threadIdx.x; e < kRowsT * kKC; e += kPT) {
-        const int row = e / kKC, kk = e % kKC;
-        const int gr = m0 + row, gk = k0 + kk;
-        wl[kk * kStride + row] = (gr < o.M && gk < o.K) ? o.W[static_cast<int64_t>(gr) * o.ldw + gk] : 0.0;
+      if (o.wt) {
+        for (int e = threadIdx.x; e < kRowsT * kKC; e += kPT) {
+          const int kk = e / kRowsT, row = e % kRowsT;
+          const int gr = m0 + row, gk = k0 + kk;
+          wl[kk * kStride + row] = (gr < o.M && gk < o.K) ? o.W[static_cast<int64_t>(gk) * o.ldw + gr] : 0.0;
+        }
+      } else {
+        for (int e = threadIdx.x; e < kRowsT * kKC; e += kPT) {
+          const int row = e / kKC, kk = e % kKC;
+          const int gr = m0 + row, gk = k0 + kk;
+          wl[kk * kStride + row] = (gr < o.M && gk < o.K) ? o.W[static_cast<int64_t>(gr) * o.ldw + gk] : 0.0;
+        }
       }
       __syncthreads();
       double bc[8][2];
@@ -458,9 +528,12 @@ int gather_stage(const Plan& p, int s, int grid, hipStream_t st) {
 }
 }  // namespace
 
-// One iteration of Alg. 1 (residual form, with the bordered core) for every unfinished
-// matrix: 13 launches whose configuration depends only on count and the device.
+// One iteration of Alg. 1 (residual form, with the core's two inverses) for every
+// unfinished matrix: 13 launches whose configuration depends only on count and the device.
 double* batch_plan_bytes_ptr(void* plan_ws, int count) { return bind_plan(plan_ws, count).bytes; }
+
+int batch_plan_stages() { return kNumStages; }
+int batch_plan_final_stage() { return kFin; }
 
 int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
                            int grid, hipStream_t st, hipEvent_t* ev) {
@@ -472,7 +545,7 @@ int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_c
   ICUR_TRY(mark(0));
   ICUR_TRY(launch_batch_lupp(mats, count, false, 0.0, st));
   ICUR_TRY(mark(1));
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, 0, p);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, b, 0, p);
   ICUR_HIP(hipGetLastError());
   ICUR_TRY(gather_stage(p, kGA, grid, st));
   ICUR_TRY(mark(4));
@@ -481,7 +554,7 @@ int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_c
   ICUR_TRY(mark(2));
   ICUR_TRY(launch_batch_lupp(mats, count, true, row_cut, st));
   ICUR_TRY(mark(3));
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, 1, p);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, b, 1, p);
   ICUR_HIP(hipGetLastError());
   ICUR_TRY(gather_stage(p, kGB, grid, st));
   hipLaunchKernelGGL(batch_inverse_kernel, dim3(count), dim3(256), 0, st, mats, count);
@@ -499,6 +572,15 @@ int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_c
   hipLaunchKernelGGL(batch_end_kernel, dim3(count), dim3(256), 0, st, mats, count, b, rec);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
+}
+
+// At the end of an iteration: the core A(I,J)^{-1} = Q^{-1} P^{-1} of every matrix that
+// stopped in it, into its LcT buffer (r x r, leading dimension r), one launch for all.
+int launch_batch_final(BatchMat* mats, int count, int c, int b, void* plan_ws, int grid, hipStream_t st) {
+  const Plan p = bind_plan(plan_ws, count);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, b, 2, p);
+  ICUR_HIP(hipGetLastError());
+  return gemm_stage(p, kFin, grid, st);
 }
 
 }  // namespace icur

@@ -35,6 +35,11 @@ inline int arg_error(const std::string& msg) {
   return ICUR_ERR_ARG;
 }
 
+inline int hip_error(hipError_t e, const std::string& where) {
+  set_error(where + ": " + hipGetErrorString(e));
+  return ICUR_ERR_HIP;
+}
+
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Device properties of the current device (cached).

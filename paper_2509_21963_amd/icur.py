@@ -52,7 +52,8 @@ class Info(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("rho", ctypes.c_double * 512),
                 ("block_sizes", ctypes.c_int32 * 512),
                 ("ms_products", ctypes.c_double), ("product_bytes", ctypes.c_double),
-                ("product_launches", ctypes.c_int32), ("group_iterations", ctypes.c_int32)]
+                ("product_launches", ctypes.c_int32), ("group_iterations", ctypes.c_int32),
+                ("ms_setup", ctypes.c_double), ("ms_results", ctypes.c_double)]
 
 
 _lib = None

@@ -131,6 +131,23 @@ def test_batched_meets_the_oracle(icur, workers):
     assert pinned["col_pinned"] > 0 and pinned["row_pinned"] > 0
 
 
+def test_grouped_growth_gives_the_same_results(icur, monkeypatch):
+    # a memory budget far below the batch's rank bounds: every matrix starts with room for
+    # a few blocks and its rank-sized buffers grow (in the arena, then beyond it) as it
+    # goes; the arithmetic does not depend on the capacity, so the results are identical
+    specs, mats = _batch(8, seed=5, m_range=(200, 700), r0_range=(10.0, 40.0))
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    full = icur.run_batched(dev, tols, 16, icur.GAUSSIAN)
+    for limit in (1 << 20, 24 << 20):
+        monkeypatch.setenv("ICUR_BATCH_MEMORY_LIMIT", str(limit))
+        small = icur.run_batched(dev, tols, 16, icur.GAUSSIAN)
+        for a, b in zip(full, small):
+            assert a["status"] == b["status"]
+            _same(a, b)
+    assert max(g["rank"] for g in full) > 4 * 16  # beyond the smallest first capacity
+
+
 def test_batched_edge_cases(icur):
     # one zero matrix (rank 0), one capped by max_rank (maxrank), one wide matrix whose
     # column selection needs more candidates than a concurrent worker's share of the CUs
