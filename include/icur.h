@@ -123,7 +123,13 @@ typedef struct icur_info {
   int32_t product_launches;
   int32_t group_iterations;   /* grouped iterations (the longest matrix's count) */
   double  ms_setup;           /* host clock of the per-matrix buffer set-up */
-  double  ms_results;         /* host clock of the copies to the caller's pools */
+  double  ms_results;         /* host clock of the copies to the caller's pools after the loop */
+  double  ms_stage[5];        /* device time of the product stages: row residual (P1), new-row
+                                 residual and (Q^-1)^T block (P2), row factors and P^-1 block
+                                 (P3), column update (P4), core products (FIN) */
+  int32_t tiles[4];           /* tile shapes used for P1, P2, P3, FIN (0..5: workgroup tiles
+                                 16x128, 32x128, 48x128, 64x128, 32x256, 64x256; 6..8: wave
+                                 tiles 32x32, 16x64, 32x64) */
 } icur_info;
 
 /*

@@ -1170,6 +1170,8 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   t_info.ms_core = gstat.ms_final;
   t_info.ms_setup = gstat.ms_alloc;
   t_info.ms_results = gstat.ms_results;
+  for (int q = 0; q < 5; ++q) t_info.ms_stage[q] = gstat.ms_stage[q];
+  for (int q = 0; q < 4; ++q) t_info.tiles[q] = gstat.tiles[q];
   t_info.iterations = static_cast<int32_t>(std::min<int64_t>(total_iters, INT32_MAX));
   t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (first_err != ICUR_OK) {

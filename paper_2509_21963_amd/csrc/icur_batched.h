@@ -14,6 +14,19 @@ namespace icur {
 constexpr int kGMaxN = 8192;     // candidates per selection (one workgroup holds them all)
 constexpr int kGMaxSteps = 64;   // pivots per selection (so block <= 64, c <= 70)
 
+// ----- the grouped FP64 product
+constexpr int kGemmShapes = 9;     // tile shapes (rows x columns): workgroup tiles 16x128,
+                                   // 32x128, 48x128, 64x128, 32x256, 64x256; wave tiles
+                                   // 32x32, 16x64, 32x64
+constexpr int kGemmMaxCols = 256;  // widest tile
+constexpr int kGemmKChunk = 16;    // depth chunk; chunks start at multiples of it, so an
+                                   // element's sum does not depend on the tile shape
+// Columns right of a new diagonal block of the core's inverses that are written with it
+// (identity or zeros), so that every entry a depth-skipping product reads is defined: a
+// tile whose columns start at n0 reads rows k >= n0 - (b - 1) rounded down to a chunk, so
+// entries up to k + b + kGemmMaxCols + kGemmKChunk - 2 to the right of the diagonal.
+constexpr int kBandCols = kGMaxSteps + kGemmMaxCols + kGemmKChunk;
+
 // One LUPP selection: pivots of T = X^T (N candidates x K >= *steps columns), FP64,
 // textbook right-looking rounding (the pivots of icur_lupp on the same values).
 struct GroupLuppJob {
@@ -81,6 +94,18 @@ struct BatchMat {
 // each: writes Jk / nJ or Ik / nI.
 int launch_batch_lupp(BatchMat* mats_dev, int count, bool rows, double rel_cut, hipStream_t st);
 
+// Tile shapes (indices into the shape table above) of the grouped product stages: the
+// row residual P1, the new-row residual and (Q^{-1})^T block P2, the row factors and P^{-1}
+// block P3, and the core products FIN.  The column update's shape follows c.  Every
+// choice gives the same results: only the speed differs.
+struct GemmTiles {
+  int p1 = 1, p2 = 1, p3 = 1, fin = 1;
+};
+
+// The tile shapes for block size b: defaults, the tune file's entry for b, and the
+// ICUR_BATCH_TILES override, in that order.
+GemmTiles batch_tiles(int b);
+
 // Per-matrix record copied to host-mapped memory at the end of every iteration.
 struct BatchRec {
   int r, s, status, info, iters, pad;
@@ -120,6 +145,8 @@ struct BatchedCall {
   double ms_alloc;        // out: host clock of the buffer set-up after the sketch
   double ms_loop;         // out: host clock of the grouped iterations
   double ms_final;        // out: device time of the closing core products Q^{-1} P^{-1}
+  double ms_stage[5];     // out: device time of the product stages P1, P2, P3, P4, FIN
+  int tiles[4];           // out: tile shapes used for P1, P2, P3, FIN
   double ms_results;      // out: host clock of the copies to the caller's pools
 };
 

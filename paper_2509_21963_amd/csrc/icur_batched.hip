@@ -14,7 +14,10 @@
 // fits in free memory, else at a fraction of it, grown (first fit, stream ordered) when
 // a matrix needs more.
 // Each matrix follows Alg. 1 on its own: the grouping changes no arithmetic.
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -32,8 +35,9 @@
 namespace icur {
 
 int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
-                           int grid, hipStream_t st, hipEvent_t* ev);
-int launch_batch_final(BatchMat* mats, int count, int c, int b, void* plan_ws, int grid, hipStream_t st);
+                           const GemmTiles& tiles, int grid, hipStream_t st, hipEvent_t* ev);
+int launch_batch_final(BatchMat* mats, int count, int c, int b, void* plan_ws, const GemmTiles& tiles,
+                       hipStream_t st);
 size_t batch_plan_bytes(int count);
 double* batch_plan_bytes_ptr(void* plan_ws, int count);
 int batch_plan_stages();
@@ -69,9 +73,6 @@ void bind_rank(BatchMat& bm, char* p, int64_t cap, int64_t b) {
   bm.cap = static_cast<int>(cap);
 }
 
-// Columns right of a row's diagonal block that the grouped products may read (the band
-// written with each new block row, see icur_group_kernels.hip): kGMaxSteps + 128.
-constexpr int64_t kCoreBand = kGMaxSteps + 128;
 
 struct DevBuf {
   void* p = nullptr;
@@ -238,6 +239,93 @@ class ResultCopier {
 };
 
 }  // namespace
+
+// ---- tile shapes of the grouped products
+// Defaults: row tiles that hold a block (P1 - P3), 32 x 128 for the core products.  A tune
+// file written by the package's autotuner (measured per stage on the device) overrides
+// them for the block sizes it lists; ICUR_BATCH_TILES="p1,p2,p3,fin" overrides both (the
+// autotuner's own runs use it).  The file is ICUR_TUNE_FILE, else tune_gfx950.json beside
+// the library.
+namespace {
+
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+std::string g_tune_text;
+
+std::string library_dir() {
+  Dl_info di;
+  if (dladdr(reinterpret_cast<void*>(&release_batch_arenas), &di) == 0 || !di.dli_fname) return ".";
+  std::string f = di.dli_fname;
+  const size_t slash = f.rfind('/');
+  return slash == std::string::npos ? "." : f.substr(0, slash);
+}
+
+const std::string& tune_text() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  if (!g_tune_loaded) {
+    g_tune_loaded = true;
+    const char* env = std::getenv("ICUR_TUNE_FILE");
+    const std::string path = env ? std::string(env) : library_dir() + "/tune_gfx950.json";
+    if (FILE* f = std::fopen(path.c_str(), "rb")) {
+      char buf[4096];
+      size_t k;
+      while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0 && g_tune_text.size() < (size_t(1) << 20))
+        g_tune_text.append(buf, k);
+      std::fclose(f);
+    }
+  }
+  return g_tune_text;
+}
+
+// The integer after "key": within text[from, to), or -1.
+int json_int(const std::string& text, size_t from, size_t to, const std::string& key) {
+  const std::string k = "\"" + key + "\"";
+  const size_t at = text.find(k, from);
+  if (at == std::string::npos || at >= to) return -1;
+  size_t p = text.find(':', at + k.size());
+  if (p == std::string::npos || p >= to) return -1;
+  ++p;
+  while (p < to && (text[p] == ' ' || text[p] == '\t' || text[p] == '\n' || text[p] == '\r')) ++p;
+  if (p >= to || text[p] < '0' || text[p] > '9') return -1;
+  int v = 0;
+  while (p < to && text[p] >= '0' && text[p] <= '9' && v < 1000000) v = 10 * v + (text[p++] - '0');
+  return v;
+}
+
+}  // namespace
+
+GemmTiles batch_tiles(int b) {
+  GemmTiles t;
+  const int rows = b <= 16 ? 0 : b <= 32 ? 1 : b <= 48 ? 2 : 3;
+  t.p1 = t.p2 = t.p3 = rows;
+  t.fin = 1;
+  // tune file: "batched_tiles": { "<b>": {"p1": .., "p2": .., "p3": .., "fin": ..}, ... }
+  const std::string& txt = tune_text();
+  const size_t sec = txt.find("\"batched_tiles\"");
+  if (sec != std::string::npos) {
+    const size_t at = txt.find("\"" + std::to_string(b) + "\"", sec);
+    if (at != std::string::npos) {
+      const size_t open = txt.find('{', at), close = txt.find('}', at);
+      if (open != std::string::npos && close != std::string::npos && open < close) {
+        int* f[4] = {&t.p1, &t.p2, &t.p3, &t.fin};
+        const char* names[4] = {"p1", "p2", "p3", "fin"};
+        for (int q = 0; q < 4; ++q) {
+          const int v = json_int(txt, open, close, names[q]);
+          if (v >= 0 && v < kGemmShapes) *f[q] = v;
+        }
+      }
+    }
+  }
+  if (const char* env = std::getenv("ICUR_BATCH_TILES")) {
+    int v[4];
+    if (std::sscanf(env, "%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3]) == 4) {
+      int* f[4] = {&t.p1, &t.p2, &t.p3, &t.fin};
+      for (int q = 0; q < 4; ++q)
+        if (v[q] >= 0 && v[q] < kGemmShapes) *f[q] = v[q];
+    }
+  }
+  return t;
+}
 
 void release_batch_arenas() {
   std::lock_guard<std::mutex> g(g_arena_mu);
@@ -485,6 +573,12 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   ICUR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&drec), hrec, 0));
   ICUR_HIP(hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st));
   const int grid = 4 * dev.num_cus;
+  const GemmTiles tiles = batch_tiles(static_cast<int>(b));
+  a.tiles[0] = tiles.p1;
+  a.tiles[1] = tiles.p2;
+  a.tiles[2] = tiles.p3;
+  a.tiles[3] = tiles.fin;
+  for (double& v : a.ms_stage) v = 0.0;
   // device events around the selections, the product stages and the closing core
   // products of every iteration
   constexpr int kEv = 14;
@@ -538,10 +632,10 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   int err_loop = ICUR_OK;
   while (any && err_loop == ICUR_OK) {
     err_loop = launch_batch_iteration(dmats, count, static_cast<int>(c), static_cast<int>(b), a.row_cut, plan.p, drec,
-                                      grid, st, ev);
+                                      tiles, grid, st, ev);
     if (err_loop != ICUR_OK) break;
     if (hipEventRecord(ev[12], st) != hipSuccess ||
-        (err_loop = launch_batch_final(dmats, count, static_cast<int>(c), static_cast<int>(b), plan.p, grid, st)) !=
+        (err_loop = launch_batch_final(dmats, count, static_cast<int>(c), static_cast<int>(b), plan.p, tiles, st)) !=
             ICUR_OK ||
         hipEventRecord(ev[13], st) != hipSuccess) {
       if (err_loop == ICUR_OK) err_loop = hip_error(hipGetLastError(), "batched: event record");
@@ -567,6 +661,7 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
       } else {
         a.ms_final += ms;
       }
+      if (e >= 4) a.ms_stage[(e - 4) / 2] += ms;
     }
     any = false;
     bool grow = false;
@@ -606,7 +701,7 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
         if (r > 0) {
           // the r block rows of both inverses, their band beyond the old width zeroed
           const size_t oc = static_cast<size_t>(bm.cap);
-          const size_t zc = std::min<size_t>(ncap, r + kCoreBand);
+          const size_t zc = std::min<size_t>(ncap, r + kBandCols);
           for (int f = 0; f < 2 && e == hipSuccess; ++f) {
             double* dst = f ? nm.Pi : nm.QT;
             const double* src = f ? bm.Pi : bm.QT;

@@ -25,10 +25,8 @@ namespace {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPT = 256;           // threads of the product and gather kernels
-constexpr int kRowsT = 32;         // product tile rows (two 16-row MFMA tiles)
-constexpr int kColsT = 128;        // product tile columns (four waves x two 16-column tiles)
-constexpr int kKC = 32;            // K chunk
 constexpr int kGatherCols = 256;   // gather tile: one row x 256 columns
+constexpr int kKC = kGemmKChunk;   // product depth chunk
 
 struct GemmOp {
   const double* X;  // may be null (beta = 0)
@@ -67,11 +65,15 @@ struct GatherOp {
 // diagonal blocks).  Phase 2, once after the loop: the core products FIN.
 enum Stage { kGA, kP1, kGB, kP2, kP3, kP4, kGC, kFin, kNumStages };
 constexpr int kOpsPerMat = 4;
-// Columns right of a new diagonal block that are written with it (identity or zeros), so
-// that every entry a depth-skipping product reads inside its tile is defined: a tile of
-// kColsT columns starting at n0 reads rows k >= n0 - kband, so entries up to k + kband +
-// kColsT - 1 to the right of the diagonal.
-constexpr int kBandCols = kGMaxSteps + kColsT;
+// Tile shapes of the grouped product (selected per stage by the host).  Workgroup tiles
+// (wave = 0): rows 16 TR, columns 128 WN, four waves of 32 WN columns sharing W through
+// LDS.  Wave tiles (wave = 1): rows 16 TR, columns 32 WN, each wave on its own tile with
+// W and B straight to registers (no LDS, no barrier).
+struct TileShape {
+  int tr, wn, wave;
+};
+constexpr TileShape kShapes[kGemmShapes] = {{1, 1, 0}, {2, 1, 0}, {3, 1, 0}, {4, 1, 0}, {2, 2, 0},
+                                            {4, 2, 0}, {2, 1, 1}, {1, 2, 1}, {2, 2, 1}};
 
 struct Plan {
   GemmOp* gemm[kNumStages];
@@ -79,6 +81,7 @@ struct Plan {
   int* nops;      // per stage
   int* ntiles;    // per stage
   double* bytes;  // per stage: algorithmic bytes of the products so far (the call's total)
+  int rt[kNumStages], ct[kNumStages];  // product tile rows / columns of each stage
 };
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -87,11 +90,13 @@ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // no tiles.  tile0 is filled in afterwards by a scan over the entries.
 __device__ __forceinline__ double tri_sum(int64_t j) { return j > 0 ? 0.5 * static_cast<double>(j) * (j + 1) : 0.0; }
 
-__device__ __forceinline__ void set_gemm(GemmOp* ops, int i, int k, const double* X, int64_t ldx, const double* W,
-                                         int64_t ldw, const double* B, int64_t ldb, double* OUT, int64_t ldo, int M,
-                                         int K, int N, double alpha, double* normp, double* bytes = nullptr,
-                                         int kskip = 0, int kband = 0, int wt = 0) {
-  GemmOp& o = ops[i * kOpsPerMat + k];
+__device__ __forceinline__ void set_gemm(const Plan& pl, int stage, int i, int k, const double* X, int64_t ldx,
+                                         const double* W, int64_t ldw, const double* B, int64_t ldb, double* OUT,
+                                         int64_t ldo, int M, int K, int N, double alpha, double* normp,
+                                         bool count_bytes = true, int kskip = 0, int kband = 0, int wt = 0) {
+  GemmOp& o = pl.gemm[stage][i * kOpsPerMat + k];
+  double* bytes = count_bytes ? pl.bytes + stage : nullptr;
+  const int rt = pl.rt[stage], ct = pl.ct[stage];
   // algorithmic bytes: the nonzero parts of W and B read once, OUT written once, X read
   // once when given
   if (bytes && M > 0 && N > 0) {
@@ -110,17 +115,17 @@ __device__ __forceinline__ void set_gemm(GemmOp* ops, int i, int k, const double
   o.M = M;
   o.K = K;
   o.N = N;
-  o.tiles_n = (M > 0 && N > 0) ? ceil_div(N, kColsT) : 0;
+  o.tiles_n = (M > 0 && N > 0) ? ceil_div(N, ct) : 0;
   o.alpha = alpha;
   o.normp = normp;
-  o.pad = (M > 0 && N > 0) ? ceil_div(M, kRowsT) * o.tiles_n : 0;  // tiles (until the scan)
+  o.pad = (M > 0 && N > 0) ? ceil_div(M, rt) * o.tiles_n : 0;  // tiles (until the scan)
   o.wt = wt;
   o.kskip = kskip;
   o.kband = kband;
 }
 
-__device__ __forceinline__ void no_gemm(GemmOp* ops, int i, int k) {
-  set_gemm(ops, i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr);
+__device__ __forceinline__ void no_gemm(const Plan& pl, int stage, int i, int k) {
+  set_gemm(pl, stage, i, k, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0, 0, 0, 0, 0.0, nullptr, false);
 }
 
 __device__ __forceinline__ void set_gather(GatherOp* ops, int i, int k, const void* src, bool f32, int64_t rs,
@@ -196,9 +201,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
       set_gather(plan.gather[kGA], i, 1, bm.Ur, false, 1, n, bm.Jk, nullptr, bm.Wa, cap, nJ, r, 1.0);
       for (int k = 2; k < kOpsPerMat; ++k) no_gather(plan.gather[kGA], i, k);
       // P1: row residual S^row = A(:, J_k) - Lc Ur(:, J_k), stored transposed
-      set_gemm(plan.gemm[kP1], i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr,
-               plan.bytes + kP1);
-      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kP1], i, k);
+      set_gemm(plan, kP1, i, 0, Lk, m, bm.Wa, cap, bm.LcT, m, Lk, m, r > 0 ? nJ : 0, r, m, -1.0, nullptr);
+      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan, kP1, i, k);
     } else if (phase == 1) {
       const int nI = on ? bm.nI : 0;
       const int nR = nI > 0 ? r : 0;   // products with the old blocks, from the second block on
@@ -215,24 +219,20 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
       // P2: residual at the new rows Sr -= Lc(I_k,:) Ur; the new block row of (Q^{-1})^T,
       // -Ur(:, J_k)^T (Q^{-1})^T (bordering Q with the block column Ur(:, J_k)); and
       // Wp = N_k^{-1} Lc(I_k, :)
-      set_gemm(plan.gemm[kP2], i, 0, bm.Sr, n, bm.Wl, cap, bm.Ur, n, bm.Sr, n, mR, r, n, -1.0, nullptr,
-               plan.bytes + kP2);
-      set_gemm(plan.gemm[kP2], i, 1, nullptr, 0, bm.Wa, cap, bm.QT, cap, QTk, cap, mR, r, r, -1.0, nullptr,
-               plan.bytes + kP2, 2, band);
-      set_gemm(plan.gemm[kP2], i, 2, nullptr, 0, bm.Nk, nI, bm.Wl, cap, bm.Wp, cap, mR, nI, r, 1.0, nullptr,
-               plan.bytes + kP2);
-      no_gemm(plan.gemm[kP2], i, 3);
+      set_gemm(plan, kP2, i, 0, bm.Sr, n, bm.Wl, cap, bm.Ur, n, bm.Sr, n, mR, r, n, -1.0, nullptr);
+      set_gemm(plan, kP2, i, 1, nullptr, 0, bm.Wa, cap, bm.QT, cap, QTk, cap, mR, r, r, -1.0, nullptr,
+               true, 2, band);
+      set_gemm(plan, kP2, i, 2, nullptr, 0, bm.Nk, nI, bm.Wl, cap, bm.Wp, cap, mR, nI, r, 1.0, nullptr);
+      no_gemm(plan, kP2, i, 3);
       // P3: new row factors Ur_k = N_k^{-1} Sr; the new block row of P^{-1}, -Wp P^{-1}
       // (bordering P with the block row Lc(I_k, :) and the diagonal block N_k)
-      set_gemm(plan.gemm[kP3], i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr,
-               plan.bytes + kP3);
-      set_gemm(plan.gemm[kP3], i, 1, nullptr, 0, bm.Wp, cap, bm.Pi, cap, Pik, cap, mR, r, r, -1.0, nullptr,
-               plan.bytes + kP3, 2, band);
-      for (int k = 2; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kP3], i, k);
+      set_gemm(plan, kP3, i, 0, nullptr, 0, bm.Nk, nI, bm.Sr, n, Urk, n, nI, nI, n, 1.0, nullptr);
+      set_gemm(plan, kP3, i, 1, nullptr, 0, bm.Wp, cap, bm.Pi, cap, Pik, cap, mR, r, r, -1.0, nullptr,
+               true, 2, band);
+      for (int k = 2; k < kOpsPerMat; ++k) no_gemm(plan, kP3, i, k);
       // P4: column residual S -= S(:, J_k) Ur_k, with its norm partials
-      set_gemm(plan.gemm[kP4], i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp,
-               plan.bytes + kP4);
-      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kP4], i, k);
+      set_gemm(plan, kP4, i, 0, bm.S, n, bm.Wc, nI, Urk, n, bm.S, n, nI > 0 ? c : 0, nI, n, -1.0, bm.normp);
+      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan, kP4, i, k);
       bm.nparts = plan.gemm[kP4][i * kOpsPerMat].pad;
       // GC: the diagonal blocks (identity in (Q^{-1})^T, N_k^{-1} in P^{-1}) and zeros to
       // their right
@@ -249,9 +249,9 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchMat* __restrict__ mats,
       const bool due = bm.s == 0 && bm.fin == 0;
       const int rf = (due && bm.info == 0 && bm.cap > 0) ? r : 0;
       if (due) bm.fin = 1;
-      set_gemm(plan.gemm[kFin], i, 0, nullptr, 0, bm.QT, cap, bm.Pi, cap, bm.LcT, rf, rf, rf, rf, 1.0, nullptr,
-               plan.bytes + kFin, 3, band, 1);
-      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan.gemm[kFin], i, k);
+      set_gemm(plan, kFin, i, 0, nullptr, 0, bm.QT, cap, bm.Pi, cap, bm.LcT, rf, rf, rf, rf, 1.0, nullptr,
+               true, 3, band, 1);
+      for (int k = 1; k < kOpsPerMat; ++k) no_gemm(plan, kFin, i, k);
     }
   }
   __syncthreads();
@@ -318,104 +318,320 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Persistent FP64 product over a list of ops.  Lane (lr, lg) of wave w: MFMA A operand
-// W[row lr][k 4j + lg], B operand B[k 4j + lg][column lr], accumulator slot v = row
-// 4 v + lg, column lr; the wave owns columns 32 w .. 32 w + 31 of the tile.
+// Persistent FP64 product over a list of ops, tiles of 16 TR rows x 128 WN columns.  Lane
+// (lr, lg) of wave w, MFMA step j of a chunk starting at k0: A operand W[row lr][k0 + 4 lg
+// + j] (from LDS), B operand B[k0 + 4 lg + j][column], accumulator slot v = row 4 v + lg
+// (every shape and both kernels use this k order, so the sums are the same).  The wave owns 32 WN columns of
+// the tile in pairs: 16-column sub-tile s holds the columns n0 + 32 (s / 2) + 2 lr + s % 2,
+// so a lane reads the two columns of a pair of B (and of X and OUT) with one 16-byte
+// access.  The depth runs in chunks of kKC: W of the next chunk and B of the next chunk
+// are loaded into registers while the current one is multiplied, W through two LDS
+// buffers (one barrier per chunk).
+template <int TR, int WN>
 __global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
                                                    const int* __restrict__ pntiles) {
-  constexpr int kStride = kRowsT + 2;  // LDS row stride of the transposed W chunk
-  __shared__ double wl[kKC * kStride];
+  constexpr int RT = 16 * TR;          // tile rows
+  constexpr int CT = 128 * WN;         // tile columns
+  constexpr int S = 2 * WN;            // 16-column sub-tiles per wave
+  constexpr int kStride = RT + 2;      // LDS row stride of the transposed W chunk
+  constexpr int WPT = RT * kKC / kPT;  // W entries per thread per chunk
+  static_assert(WPT * kPT == RT * kKC, "W chunk must split evenly over the threads");
+  __shared__ double wl[2][kKC * kStride];
   __shared__ double red[kPT / 64];
   const int nops = *pnops, ntiles = *pntiles;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
     const GemmOp& o = ops[find_op(ops, nops, g)];
     const int lt = g - o.tile0;
-    const int m0 = (lt / o.tiles_n) * kRowsT;
-    const int n0 = (lt % o.tiles_n) * kColsT + wave * 32;
-    int col[2];
-    bool cok[2];
+    const int M = o.M, K = o.K, N = o.N;
+    const int m0 = (lt / o.tiles_n) * RT;
+    const int n0t = (lt % o.tiles_n) * CT;
+    const int n0 = n0t + wave * 32 * WN;
+    const double* __restrict__ W = o.W;
+    const double* __restrict__ B = o.B;
+    const int64_t ldw = o.ldw, ldb = o.ldb;
+    const bool wt = o.wt != 0;
+    // 16-byte accesses where the pair is aligned: even leading dimension, aligned base
+    const bool bvec = ((ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    int col[S];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      col[s] = n0 + 16 * s + lr;
-      cok[s] = col[s] < o.N;
-      if (!cok[s]) col[s] = 0;
-    }
-    doublex4 acc[2][2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int s = 0; s < 2; ++s) acc[t][s] = doublex4{0.0, 0.0, 0.0, 0.0};
-    double b[8][2];
-    auto load_b = [&](int k0) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + 4 * j + lg;
-        const bool kok = k < o.K;
-        const double* row = o.B + static_cast<int64_t>(kok ? k : 0) * o.ldb;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) b[j][s] = (kok && cok[s]) ? row[col[s]] : 0.0;
-      }
-    };
-    // depth range: block-triangular operands are zero below kbeg for the whole tile
+    for (int s2 = 0; s2 < S; ++s2) col[s2] = n0 + 32 * (s2 >> 1) + 2 * lr + (s2 & 1);
+    // depth range: block-triangular operands are zero below kbeg for the whole tile; it
+    // starts at a chunk boundary so the grouping of the sums does not depend on the tile
     int kbeg = 0;
     if (o.kskip & 1) kbeg = max(kbeg, m0 - o.kband);
-    if (o.kskip & 2) kbeg = max(kbeg, (lt % o.tiles_n) * kColsT - o.kband);
-    if (kbeg < o.K) load_b(kbeg);
-    for (int k0 = kbeg; k0 < o.K; k0 += kKC) {
-      __syncthreads();  // the previous chunk's W reads are done
-      if (o.wt) {
-        for (int e = threadIdx.x; e < kRowsT * kKC; e += kPT) {
-          const int kk = e / kRowsT, row = e % kRowsT;
-          const int gr = m0 + row, gk = k0 + kk;
-          wl[kk * kStride + row] = (gr < o.M && gk < o.K) ? o.W[static_cast<int64_t>(gk) * o.ldw + gr] : 0.0;
-        }
-      } else {
-        for (int e = threadIdx.x; e < kRowsT * kKC; e += kPT) {
-          const int row = e / kKC, kk = e % kKC;
-          const int gr = m0 + row, gk = k0 + kk;
-          wl[kk * kStride + row] = (gr < o.M && gk < o.K) ? o.W[static_cast<int64_t>(gr) * o.ldw + gk] : 0.0;
+    if (o.kskip & 2) kbeg = max(kbeg, n0t - o.kband);
+    kbeg = (kbeg / kKC) * kKC;
+    const int nch = kbeg < K ? (K - kbeg + kKC - 1) / kKC : 0;
+
+    doublex4 acc[TR][S];
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) acc[t][s2] = doublex4{0.0, 0.0, 0.0, 0.0};
+    constexpr int NJ = kKC / 4;  // MFMA steps per chunk
+    double b[NJ][S];
+    double wr[WPT];
+    auto load_b = [&](int k0) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int k = k0 + 4 * lg + j;
+        const bool kok = k < K;
+        const double* row = B + static_cast<int64_t>(kok ? k : 0) * ldb;
+#pragma unroll
+        for (int p = 0; p < WN; ++p) {
+          const int c0 = col[2 * p];
+          if (bvec && kok && c0 + 1 < N) {
+            const double2 v = *reinterpret_cast<const double2*>(row + c0);
+            b[j][2 * p] = v.x;
+            b[j][2 * p + 1] = v.y;
+          } else {
+            b[j][2 * p] = (kok && c0 < N) ? row[c0] : 0.0;
+            b[j][2 * p + 1] = (kok && c0 + 1 < N) ? row[c0 + 1] : 0.0;
+          }
         }
       }
-      __syncthreads();
-      double bc[8][2];
+    };
+    auto load_w = [&](int k0) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-#pragma unroll
-        for (int s = 0; s < 2; ++s) bc[j][s] = b[j][s];
-      if (k0 + kKC < o.K) load_b(k0 + kKC);
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        double a[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = wl[(4 * j + lg) * kStride + t * 16 + lr];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) acc[t][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bc[j][s], acc[t][s], 0, 0, 0);
+      for (int q = 0; q < WPT; ++q) {
+        const int e = tid + kPT * q;
+        int row, kk;
+        if (wt) {
+          kk = e / RT;
+          row = e % RT;
+        } else {
+          row = e / kKC;
+          kk = e % kKC;
+        }
+        const int gr = m0 + row, gk = k0 + kk;
+        const bool ok = gr < M && gk < K;
+        wr[q] = ok ? (wt ? W[static_cast<int64_t>(gk) * ldw + gr] : W[static_cast<int64_t>(gr) * ldw + gk]) : 0.0;
       }
+    };
+    auto store_w = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        const int e = tid + kPT * q;
+        const int row = wt ? e % RT : e / kKC;
+        const int kk = wt ? e / RT : e % kKC;
+        wl[buf][kk * kStride + row] = wr[q];
+      }
+    };
+    if (nch > 0) {
+      load_w(kbeg);
+      load_b(kbeg);
     }
+    __syncthreads();  // the previous tile's readers of the LDS buffers are done
+    if (nch > 0) store_w(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      const int cur = ch & 1;
+      const int k0 = kbeg + ch * kKC;
+      double bc[NJ][S];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) bc[j][s2] = b[j][s2];
+      const bool more = ch + 1 < nch;
+      if (more) {
+        load_w(k0 + kKC);
+        load_b(k0 + kKC);
+      }
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        double a[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) a[j] = wl[cur][(4 * lg + j) * kStride + t * 16 + lr];
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            acc[t][s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bc[j][s2], acc[t][s2], 0, 0, 0);
+      }
+      if (more) store_w(cur ^ 1);
+      __syncthreads();
+    }
+    // epilogue: OUT = X + alpha acc, pairs of columns per lane
+    const bool ovec = ((o.ldo & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.OUT) & 15) == 0) &&
+                      (!o.X || (((o.ldx & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.X) & 15) == 0)));
     double sq = 0.0;
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < TR; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + t * 16 + 4 * v + lg;
-        if (row >= o.M) continue;
+        if (row >= M) continue;
+        double* orow = o.OUT + static_cast<int64_t>(row) * o.ldo;
+        const double* xrow = o.X ? o.X + static_cast<int64_t>(row) * o.ldx : nullptr;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          if (!cok[s]) continue;
-          double out = o.alpha * acc[t][s][v];
-          if (o.X) out = o.X[static_cast<int64_t>(row) * o.ldx + col[s]] + out;
-          o.OUT[static_cast<int64_t>(row) * o.ldo + col[s]] = out;
-          sq += out * out;
+        for (int p = 0; p < WN; ++p) {
+          const int c0 = col[2 * p];
+          double y0 = o.alpha * acc[t][2 * p][v];
+          double y1 = o.alpha * acc[t][2 * p + 1][v];
+          if (ovec && c0 + 1 < N) {
+            if (xrow) {
+              const double2 x = *reinterpret_cast<const double2*>(xrow + c0);
+              y0 = x.x + y0;
+              y1 = x.y + y1;
+            }
+            *reinterpret_cast<double2*>(orow + c0) = double2{y0, y1};
+            sq += y0 * y0 + y1 * y1;
+          } else {
+            if (c0 < N) {
+              if (xrow) y0 = xrow[c0] + y0;
+              orow[c0] = y0;
+              sq += y0 * y0;
+            }
+            if (c0 + 1 < N) {
+              if (xrow) y1 = xrow[c0 + 1] + y1;
+              orow[c0 + 1] = y1;
+              sq += y1 * y1;
+            }
+          }
         }
       }
     if (o.normp) {
       const double tot = block_sum(sq, red);
-      if (threadIdx.x == 0) o.normp[lt] = tot;
+      if (tid == 0) o.normp[lt] = tot;
     }
+  }
+}
+
+// Persistent FP64 product over a list of ops, one tile of 16 TR rows x 32 WN columns per
+// wave: each wave walks its own tiles with W and B loaded straight into registers (the
+// next chunk's while the current one is multiplied), no LDS and no barrier.  Lane (lr, lg)
+// and the k order as in gemm_kernel; its four W entries of a step are contiguous in a row
+// of W (one 32-byte read).  Ops with norm partials are not taken (gemm_kernel does those).
+template <int TR, int WN>
+__global__ __launch_bounds__(kPT) void gemm_wave_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
+                                                        const int* __restrict__ pntiles) {
+  constexpr int RT = 16 * TR;
+  constexpr int CT = 32 * WN;
+  constexpr int S = 2 * WN;
+  constexpr int NJ = kKC / 4;
+  static_assert(NJ == 4, "W reads assume four steps per chunk");
+  const int nops = *pnops, ntiles = *pntiles;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nwaves = gridDim.x * (kPT / 64);
+  for (int g = blockIdx.x * (kPT / 64) + wave; g < ntiles; g += nwaves) {
+    const GemmOp& o = ops[find_op(ops, nops, g)];
+    const int lt = g - o.tile0;
+    const int M = o.M, K = o.K, N = o.N;
+    const int m0 = (lt / o.tiles_n) * RT;
+    const int n0 = (lt % o.tiles_n) * CT;
+    const double* __restrict__ W = o.W;
+    const double* __restrict__ B = o.B;
+    const int64_t ldw = o.ldw, ldb = o.ldb;
+    const bool wt = o.wt != 0;
+    const bool bvec = ((ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    const bool wvec = !wt && ((ldw & 1) == 0) && ((reinterpret_cast<uintptr_t>(W) & 15) == 0);
+    int col[S];
+#pragma unroll
+    for (int s2 = 0; s2 < S; ++s2) col[s2] = n0 + 32 * (s2 >> 1) + 2 * lr + (s2 & 1);
+    int kbeg = 0;
+    if (o.kskip & 1) kbeg = max(kbeg, m0 - o.kband);
+    if (o.kskip & 2) kbeg = max(kbeg, n0 - o.kband);
+    kbeg = (kbeg / kKC) * kKC;
+    const int nch = kbeg < K ? (K - kbeg + kKC - 1) / kKC : 0;
+    doublex4 acc[TR][S];
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) acc[t][s2] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double b[NJ][S], w[TR][NJ];
+    auto load = [&](int k0) {
+      const int kl = k0 + 4 * lg;  // this lane's four k: kl .. kl + 3
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int k = kl + j;
+        const bool kok = k < K;
+        const double* row = B + static_cast<int64_t>(kok ? k : 0) * ldb;
+#pragma unroll
+        for (int p = 0; p < WN; ++p) {
+          const int c0 = col[2 * p];
+          if (bvec && kok && c0 + 1 < N) {
+            const double2 v = *reinterpret_cast<const double2*>(row + c0);
+            b[j][2 * p] = v.x;
+            b[j][2 * p + 1] = v.y;
+          } else {
+            b[j][2 * p] = (kok && c0 < N) ? row[c0] : 0.0;
+            b[j][2 * p + 1] = (kok && c0 + 1 < N) ? row[c0 + 1] : 0.0;
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int r = m0 + 16 * t + lr;
+        const bool rok = r < M;
+        if (wt) {
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) w[t][j] = (rok && kl + j < K) ? W[static_cast<int64_t>(kl + j) * ldw + r] : 0.0;
+        } else if (wvec && rok && kl + 3 < K) {
+          const double* wr = W + static_cast<int64_t>(r) * ldw + kl;
+          const double2 v0 = *reinterpret_cast<const double2*>(wr);
+          const double2 v1 = *reinterpret_cast<const double2*>(wr + 2);
+          w[t][0] = v0.x;
+          w[t][1] = v0.y;
+          w[t][2] = v1.x;
+          w[t][3] = v1.y;
+        } else {
+          const double* wr = W + static_cast<int64_t>(rok ? r : 0) * ldw;
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) w[t][j] = (rok && kl + j < K) ? wr[kl + j] : 0.0;
+        }
+      }
+    };
+    if (nch > 0) load(kbeg);
+    for (int ch = 0; ch < nch; ++ch) {
+      double bc[NJ][S], wc[TR][NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) bc[j][s2] = b[j][s2];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) wc[t][j] = w[t][j];
+      }
+      if (ch + 1 < nch) load(kbeg + (ch + 1) * kKC);
+#pragma unroll
+      for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            acc[t][s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[t][j], bc[j][s2], acc[t][s2], 0, 0, 0);
+    }
+    const bool ovec = ((o.ldo & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.OUT) & 15) == 0) &&
+                      (!o.X || (((o.ldx & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.X) & 15) == 0)));
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + t * 16 + 4 * v + lg;
+        if (row >= M) continue;
+        double* orow = o.OUT + static_cast<int64_t>(row) * o.ldo;
+        const double* xrow = o.X ? o.X + static_cast<int64_t>(row) * o.ldx : nullptr;
+#pragma unroll
+        for (int p = 0; p < WN; ++p) {
+          const int c0 = col[2 * p];
+          double y0 = o.alpha * acc[t][2 * p][v];
+          double y1 = o.alpha * acc[t][2 * p + 1][v];
+          if (ovec && c0 + 1 < N) {
+            if (xrow) {
+              const double2 x = *reinterpret_cast<const double2*>(xrow + c0);
+              y0 = x.x + y0;
+              y1 = x.y + y1;
+            }
+            *reinterpret_cast<double2*>(orow + c0) = double2{y0, y1};
+          } else {
+            if (c0 < N) orow[c0] = xrow ? xrow[c0] + y0 : y0;
+            if (c0 + 1 < N) orow[c0 + 1] = xrow ? xrow[c0 + 1] + y1 : y1;
+          }
+        }
+      }
   }
 }
 
@@ -499,8 +715,13 @@ size_t batch_plan_bytes(int count) {
 }
 
 namespace {
-Plan bind_plan(void* ws, int count) {
+Plan bind_plan(void* ws, int count, const int* shape_of_stage = nullptr) {
   Plan p;
+  for (int s = 0; s < kNumStages; ++s) {
+    const int sh = shape_of_stage ? shape_of_stage[s] : 1;
+    p.rt[s] = 16 * kShapes[sh].tr;
+    p.ct[s] = (kShapes[sh].wave ? 32 : 128) * kShapes[sh].wn;
+  }
   char* q = static_cast<char*>(ws);
   const size_t per = static_cast<size_t>(count) * kOpsPerMat;
   for (int s = 0; s < kNumStages; ++s) {
@@ -515,10 +736,38 @@ Plan bind_plan(void* ws, int count) {
   return p;
 }
 
-int gemm_stage(const Plan& p, int s, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(gemm_kernel, dim3(grid), dim3(kPT), 0, st, p.gemm[s], p.nops + s, p.ntiles + s);
+template <typename KERNEL>
+int gemm_launch(KERNEL kernel, int* per_cu, const Plan& p, int s, hipStream_t st) {
+  // persistent grid: as many workgroups as fit on the device at once
+  if (*per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kPT, 0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    *per_cu = std::min(nb, 8);
+  }
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  hipLaunchKernelGGL(kernel, dim3(*per_cu * dev.num_cus), dim3(kPT), 0, st, p.gemm[s], p.nops + s, p.ntiles + s);
   ICUR_HIP(hipGetLastError());
   return ICUR_OK;
+}
+
+int gemm_stage(const Plan& p, int s, int shape, hipStream_t st) {
+  static int per_cu[kGemmShapes] = {};
+  switch (shape) {
+    case 0: return gemm_launch(gemm_kernel<1, 1>, &per_cu[0], p, s, st);
+    case 1: return gemm_launch(gemm_kernel<2, 1>, &per_cu[1], p, s, st);
+    case 2: return gemm_launch(gemm_kernel<3, 1>, &per_cu[2], p, s, st);
+    case 3: return gemm_launch(gemm_kernel<4, 1>, &per_cu[3], p, s, st);
+    case 4: return gemm_launch(gemm_kernel<2, 2>, &per_cu[4], p, s, st);
+    case 5: return gemm_launch(gemm_kernel<4, 2>, &per_cu[5], p, s, st);
+    case 6: return gemm_launch(gemm_wave_kernel<2, 1>, &per_cu[6], p, s, st);
+    case 7: return gemm_launch(gemm_wave_kernel<1, 2>, &per_cu[7], p, s, st);
+    case 8: return gemm_launch(gemm_wave_kernel<2, 2>, &per_cu[8], p, s, st);
+    default: return arg_error("grouped product: unknown tile shape");
+  }
 }
 
 int gather_stage(const Plan& p, int s, int grid, hipStream_t st) {
@@ -535,9 +784,29 @@ double* batch_plan_bytes_ptr(void* plan_ws, int count) { return bind_plan(plan_w
 int batch_plan_stages() { return kNumStages; }
 int batch_plan_final_stage() { return kFin; }
 
+// Shape of each product stage: P1, P2, P3 and FIN as given; P4, whose tiles carry the
+// norm partials, always the one that fits c rows (so rho does not depend on the tuning).
+void stage_shapes(const GemmTiles& t, int c, int* out) {
+  for (int s = 0; s < kNumStages; ++s) out[s] = 1;
+  out[kP1] = t.p1;
+  out[kP2] = t.p2;
+  out[kP3] = t.p3;
+  out[kFin] = t.fin;
+  out[kP4] = c <= 16 ? 0 : c <= 32 ? 1 : c <= 48 ? 2 : 3;
+}
+
+int check_tiles(const GemmTiles& t) {
+  for (int v : {t.p1, t.p2, t.p3, t.fin})
+    if (v < 0 || v >= kGemmShapes) return arg_error("grouped product: tile shape out of range");
+  return ICUR_OK;
+}
+
 int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_cut, void* plan_ws, BatchRec* rec,
-                           int grid, hipStream_t st, hipEvent_t* ev) {
-  const Plan p = bind_plan(plan_ws, count);
+                           const GemmTiles& tiles, int grid, hipStream_t st, hipEvent_t* ev) {
+  ICUR_TRY(check_tiles(tiles));
+  int sh[kNumStages];
+  stage_shapes(tiles, c, sh);
+  const Plan p = bind_plan(plan_ws, count, sh);
   auto mark = [&](int k) -> int {
     if (ev) ICUR_HIP(hipEventRecord(ev[k], st));
     return ICUR_OK;
@@ -549,7 +818,7 @@ int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_c
   ICUR_HIP(hipGetLastError());
   ICUR_TRY(gather_stage(p, kGA, grid, st));
   ICUR_TRY(mark(4));
-  ICUR_TRY(gemm_stage(p, kP1, grid, st));
+  ICUR_TRY(gemm_stage(p, kP1, sh[kP1], st));
   ICUR_TRY(mark(5));
   ICUR_TRY(mark(2));
   ICUR_TRY(launch_batch_lupp(mats, count, true, row_cut, st));
@@ -560,13 +829,13 @@ int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_c
   hipLaunchKernelGGL(batch_inverse_kernel, dim3(count), dim3(256), 0, st, mats, count);
   ICUR_HIP(hipGetLastError());
   ICUR_TRY(mark(6));
-  ICUR_TRY(gemm_stage(p, kP2, grid, st));
+  ICUR_TRY(gemm_stage(p, kP2, sh[kP2], st));
   ICUR_TRY(mark(7));
   ICUR_TRY(mark(8));
-  ICUR_TRY(gemm_stage(p, kP3, grid, st));
+  ICUR_TRY(gemm_stage(p, kP3, sh[kP3], st));
   ICUR_TRY(mark(9));
   ICUR_TRY(mark(10));
-  ICUR_TRY(gemm_stage(p, kP4, grid, st));
+  ICUR_TRY(gemm_stage(p, kP4, sh[kP4], st));
   ICUR_TRY(mark(11));
   ICUR_TRY(gather_stage(p, kGC, grid, st));
   hipLaunchKernelGGL(batch_end_kernel, dim3(count), dim3(256), 0, st, mats, count, b, rec);
@@ -576,11 +845,15 @@ int launch_batch_iteration(BatchMat* mats, int count, int c, int b, double row_c
 
 // At the end of an iteration: the core A(I,J)^{-1} = Q^{-1} P^{-1} of every matrix that
 // stopped in it, into its LcT buffer (r x r, leading dimension r), one launch for all.
-int launch_batch_final(BatchMat* mats, int count, int c, int b, void* plan_ws, int grid, hipStream_t st) {
-  const Plan p = bind_plan(plan_ws, count);
+int launch_batch_final(BatchMat* mats, int count, int c, int b, void* plan_ws, const GemmTiles& tiles,
+                       hipStream_t st) {
+  ICUR_TRY(check_tiles(tiles));
+  int sh[kNumStages];
+  stage_shapes(tiles, c, sh);
+  const Plan p = bind_plan(plan_ws, count, sh);
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, mats, count, c, b, 2, p);
   ICUR_HIP(hipGetLastError());
-  return gemm_stage(p, kFin, grid, st);
+  return gemm_stage(p, kFin, sh[kFin], st);
 }
 
 }  // namespace icur

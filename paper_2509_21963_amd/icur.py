@@ -53,7 +53,8 @@ class Info(ctypes.Structure):
                 ("block_sizes", ctypes.c_int32 * 512),
                 ("ms_products", ctypes.c_double), ("product_bytes", ctypes.c_double),
                 ("product_launches", ctypes.c_int32), ("group_iterations", ctypes.c_int32),
-                ("ms_setup", ctypes.c_double), ("ms_results", ctypes.c_double)]
+                ("ms_setup", ctypes.c_double), ("ms_results", ctypes.c_double),
+                ("ms_stage", ctypes.c_double * 5), ("tiles", ctypes.c_int32 * 4)]
 
 
 _lib = None
@@ -212,9 +213,9 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
     offs[1:] = np.cumsum(cap)
     uoffs = np.zeros(count + 1, np.int64)
     uoffs[1:] = np.cumsum(cap * cap)
-    I = np.zeros(max(int(offs[-1]), 1), np.int64)
-    J = np.zeros(max(int(offs[-1]), 1), np.int64)
-    U = np.zeros(max(int(uoffs[-1]), 1), np.float64)
+    I = np.empty(max(int(offs[-1]), 1), np.int64)
+    J = np.empty(max(int(offs[-1]), 1), np.int64)
+    U = np.empty(max(int(uoffs[-1]), 1), np.float64)
     rank = np.zeros(max(count, 1), np.int64)
     est = np.zeros(max(count, 1), np.float64)
     status = np.zeros(max(count, 1), np.int32)
@@ -229,8 +230,9 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
     out = []
     for i in range(count):
         r = int(rank[i])
-        out.append({"I": I[offs[i]:offs[i] + r].copy(), "J": J[offs[i]:offs[i] + r].copy(),
-                    "U": U[uoffs[i]:uoffs[i] + r * r].reshape(r, r).copy(), "rank": r, "rho": float(est[i]),
+        # views into the pools (the pools live as long as any view does)
+        out.append({"I": I[offs[i]:offs[i] + r], "J": J[offs[i]:offs[i] + r],
+                    "U": U[uoffs[i]:uoffs[i] + r * r].reshape(r, r), "rank": r, "rho": float(est[i]),
                     "status": _STATUS_NAMES.get(int(status[i]), str(int(status[i])))})
     return out
 
@@ -238,7 +240,9 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
 def last_info():
     info = Info()
     load().icur_last_info(ctypes.byref(info))
-    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "block_sizes")}
+    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "block_sizes", "ms_stage", "tiles")}
+    d["ms_stage"] = list(info.ms_stage)
+    d["tiles"] = list(info.tiles)
     d["rho"] = list(info.rho[:info.n_rho])
     d["block_sizes"] = list(info.block_sizes[:info.n_rho])
     return d

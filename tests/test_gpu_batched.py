@@ -148,6 +148,26 @@ def test_grouped_growth_gives_the_same_results(icur, monkeypatch):
     assert max(g["rank"] for g in full) > 4 * 16  # beyond the smallest first capacity
 
 
+def test_tile_shapes_give_identical_results(icur, monkeypatch):
+    # the grouped products' tile shape (the autotuner's choice) changes no result: depth
+    # chunks start at fixed multiples, so every element's sum is the same
+    specs, mats = _batch(6, seed=7, m_range=(200, 900), r0_range=(10.0, 60.0))
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    ref = None
+    for v in range(9):
+        monkeypatch.setenv("ICUR_BATCH_TILES", "%d,%d,%d,%d" % (v, v, v, v))
+        got = icur.run_batched(dev, tols, 32, icur.GAUSSIAN)
+        assert icur.last_info()["tiles"] == [v, v, v, v]
+        if ref is None:
+            ref = got
+            continue
+        for a, b in zip(ref, got):
+            assert a["status"] == b["status"]
+            _same(a, b)
+    assert max(g["rank"] for g in ref) > 256  # wide enough for several tiles of every shape
+
+
 def test_batched_edge_cases(icur):
     # one zero matrix (rank 0), one capped by max_rank (maxrank), one wide matrix whose
     # column selection needs more candidates than a concurrent worker's share of the CUs
