@@ -428,7 +428,9 @@ size_t sketch_G_bytes(int kind, int64_t c, int64_t m, int64_t ldg) {
 
 int form_sketch(int kind, uint64_t seed, int64_t c, int64_t m, int64_t n, const float* A, int64_t lda, int zeta,
                 int terms, bool precise, uint16_t* G, int64_t ldg, double* S, double* partials, void* ws,
-                size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end) {
+                size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end,
+                bool* used_kernel) {
+  if (used_kernel) *used_kernel = false;
   const bool srtt = (kind == ICUR_SKETCH_SRTT);
   if (kind == ICUR_SKETCH_GAUSSIAN) {
     ICUR_TRY(launch_gaussian_G(seed, c, m, G, ldg, st));
@@ -444,7 +446,11 @@ int form_sketch(int kind, uint64_t seed, int64_t c, int64_t m, int64_t n, const 
   }
   int parts = 0;
   int sk = ICUR_ERR_UNSUPPORTED;
-  if (terms > 0)  if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
+  if (terms > 0)
+    sk = sketch_product(G, ldg, c, A, m, n, lda, terms, precise, S, n, partials, &parts, ws, ws_bytes, st, ev_begin,
+                        ev_end);
+  if (sk != ICUR_OK && sk != ICUR_ERR_UNSUPPORTED) return sk;
+  if (used_kernel) *used_kernel = (sk == ICUR_OK);
   if (sk == ICUR_ERR_UNSUPPORTED) {
     if (ev_begin) ICUR_HIP(hipEventRecord(ev_begin, st));
     WideGemm g{};
@@ -701,9 +707,11 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     // c > 160), not its split-K reduce; the general product is bracketed whole
     ICUR_TRY(tm.reserve(&ev_p0));
     ICUR_TRY(tm.reserve(&ev_p1));
+    bool used = false;
     ICUR_TRY(form_sketch(kind, seed, c, m, n, A, lda, zeta, sketch_terms, tol < kSketchChunkFlushBelow, G, ldg, S,
                          dnorm, pGemm, dc.buf[kGemmWs].bytes, &dscal->normsq_x0, st, tm.event(ev_p0),
-                         tm.event(ev_p1)));
+                         tm.event(ev_p1), &used));
+    t_info.sketch_kernel = used ? 1 : 0;
   }
   if (denom_a) {
     int parts = 0;
@@ -1170,6 +1178,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   t_info.ms_core = gstat.ms_final;
   t_info.ms_setup = gstat.ms_alloc;
   t_info.ms_results = gstat.ms_results;
+  t_info.sketch_kernel = gstat.sketch_kernel;
   for (int q = 0; q < 5; ++q) t_info.ms_stage[q] = gstat.ms_stage[q];
   for (int q = 0; q < 4; ++q) t_info.tiles[q] = gstat.tiles[q];
   t_info.iterations = static_cast<int32_t>(std::min<int64_t>(total_iters, INT32_MAX));

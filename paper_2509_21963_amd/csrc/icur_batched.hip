@@ -437,8 +437,10 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
     BatchMat& bm = hm[q];
     const int64_t m = bm.m, n = bm.n, ldg = (m + 7) / 8 * 8;
     const int terms = split ? (o.split_terms ? o.split_terms : terms_for_tol(a.tol[i])) : (o.sketch_fp32 ? 0 : 3);
+    bool used = false;
     err = form_sketch(a.kind, a.seed[i], c, m, n, bm.A, bm.lda, zeta, terms, a.tol[i] < kSketchChunkFlushBelow, G,
-                      ldg, bm.S, parts, ws, gemm_ws, norms_dev + 2 * q, s2, nullptr, nullptr);
+                      ldg, bm.S, parts, ws, gemm_ws, norms_dev + 2 * q, s2, nullptr, nullptr, &used);
+    a.sketch_kernel += used ? 1 : 0;
     if (err == ICUR_OK && denom_a) {
       int np = 0;
       err = launch_sumsq_f32(bm.A, m, n, bm.lda, parts, &np, s2);

@@ -135,10 +135,13 @@ size_t sketch_G_bytes(int kind, int64_t c, int64_t m, int64_t ldg);
 // leading dimension n) and ||X0||_F^2 into *normsq_dev (device).  terms: BF16 pieces of A
 // (1..3) or 0 for FP32 matrix cores; precise: FP64 flush every 32 rows.  partials holds
 // the norm partials (at least max(sketch_max_norm_partials, max_norm_partials)), ws the
-// product workspace.  ev_begin / ev_end (may be null) bracket the product kernel.
+// product workspace.  ev_begin / ev_end (may be null) bracket the product kernel;
+// *used_kernel (may be null) tells whether the dedicated sketch kernel ran (else the
+// general product).
 int form_sketch(int kind, uint64_t seed, int64_t c, int64_t m, int64_t n, const float* A, int64_t lda, int zeta,
                 int terms, bool precise, uint16_t* G, int64_t ldg, double* S, double* partials, void* ws,
-                size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end);
+                size_t ws_bytes, double* normsq_dev, hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end,
+                bool* used_kernel = nullptr);
 
 // ----- sparse input (icur_csr.hip) -----
 struct CsrMatrix {

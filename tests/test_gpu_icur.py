@@ -165,6 +165,22 @@ def test_fp32_matrix_core_sketch_option(icur):
     assert err <= 2e-5
 
 
+def test_dense_sketch_runs_on_the_sketch_kernel(icur):
+    # G A of the BF16-exact operators goes through the dedicated streaming kernel (not the
+    # general product) for row-aligned inputs, in both forms and in the grouped batch
+    g = torch.Generator(device="cuda").manual_seed(3)
+    A = torch.randn(2000, 1500, generator=g, device="cuda", dtype=torch.float32)
+    for kind in (0, 1):
+        for precision in (icur.FP32, icur.BF16_SPLIT):
+            icur.run(A, 1e-2, 50, kind, 0, precision=precision)
+            assert icur.last_info()["sketch_kernel"] == 1, (kind, precision)
+    icur.run(A, 1e-2, 50, icur.SRTT, 0)
+    assert icur.last_info()["sketch_kernel"] == 0  # the SRTT operator runs on the general product
+    mats = [A[:700, :600].contiguous(), A[:900, :1200].contiguous(), A[:520, :804].contiguous()]
+    icur.run_batched(mats, [1e-2] * 3, 32)
+    assert icur.last_info()["sketch_kernel"] == 3
+
+
 def test_schur_zeros_of_the_result(icur):
     A32, _ = W.to_f32(W.rbf(900, 700, 2))
     got = icur.run(torch.from_numpy(A32).cuda(), 1e-5, 16, 0, 7)
