@@ -107,7 +107,10 @@ def precision_runs(A, steps, warmup, b=128):
             runs[key] = {
                 "s": statistics.median(times), "rank": last["rank"], "rho": last["rho"],
                 "iterations": last["info"]["iterations"], "split_terms": last["info"]["split_terms"],
-                "sketch_ms": statistics.mean(o["info"]["ms_sketch_product"] for o in outs)}
+                "sketch_ms": statistics.mean(o["info"]["ms_sketch_product"] for o in outs),
+                "select_ms": statistics.mean(o["info"]["ms_select"] for o in outs),
+                "residual_ms": statistics.mean(o["info"]["ms_residual"] for o in outs),
+                "core_ms": statistics.mean(o["info"]["ms_core"] for o in outs)}
             print("precision form %s tol %g: %.2f ms, rank %d, rho %.3e" % (
                 form, tol, runs[key]["s"] * 1e3, last["rank"], last["rho"]), file=sys.stderr, flush=True)
     return runs

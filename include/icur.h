@@ -133,7 +133,9 @@ typedef struct icur_info {
   int32_t sketch_kernel;      /* 1 when G A ran on the dedicated sketch kernel, 0 when on the
                                  general product (SRTT, FP32 matrix cores, shapes outside
                                  the kernel's fast path); batched: the count of matrices */
-  int32_t pad2;
+  int32_t residual_terms;     /* BF16 pieces per operand of the residual products: -1 for
+                                 FP64 factors, 0 for FP32 factors on the FP32 matrix cores,
+                                 2 or 3 in the precision form */
 } icur_info;
 
 /*
@@ -186,7 +188,8 @@ int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals
  *   helper thread while the others go on.  Each matrix's arithmetic is its own (the
  *   result does not depend on the rest of the batch); its pivots are icur_run's
  *   wherever the selection is not decided by rounding, its core is A(I,J)^{-1} formed
- *   from the two block-triangular factors of A(I,J).
+ *   from the two block-triangular factors of A(I,J).  Its residual factors are FP64 in
+ *   both forms (the precision form changes only its sketch there).
  *   Worker form (batch_workers 1..16), and matrices the grouped form does not take: the
  *   matrices run concurrently, batch_workers (16 for the rest of a grouped call) at a
  *   time, each on a worker stream with its own cached workspace, largest first; each

@@ -51,7 +51,7 @@ namespace {
 enum Slot {
   kG, kRowsPat, kSignsPat, kX0, kS, kSrow, kCt, kR, kU, kY, kA12, kA21, kA22, kYt, kX0J, kW64,
   kWp, kColMask, kRowMask, kJk, kIk, kJall, kIall, kLupp, kGemmWs, kNormPart, kScal, kCoreWs,
-  kStepA, kStepB, kCsc, kQrcp, kNumSlots
+  kStepA, kStepB, kCsc, kQrcp, kUrk64, kNumSlots
 };
 
 struct Buf {
@@ -416,6 +416,12 @@ int terms_for_tol(double tol) {
   return 3;
 }
 
+// BF16 pieces per operand of the precision form's residual products (see run_impl).
+int residual_terms_for_tol(double tol) { return tol >= 1e-1 ? 2 : 3; }
+
+// The precision form runs FP32 factors from this tolerance up (see run_impl).
+constexpr double kSplitResidualMinTol = 1e-4;
+
 // G (c x m BF16, leading dimension ldg) drawn from (kind, seed, zeta), X0 = G A into S
 // (c x n FP64) and ||X0||_F^2 into *normsq_dev: the sketch kernel when the shape allows
 // (A split into `terms` BF16 pieces), else the general product.  ev_begin / ev_end (may
@@ -552,13 +558,25 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   // sketch pieces: the plain form forms every product exactly (three pieces of A times a
   // BF16-exact G) unless FP32 matrix cores are asked for
   const int sketch_terms = split ? T : (o.sketch_fp32 ? 0 : 3);
-  // Residual factors: FP64 on the FP64 matrix cores unless FP32 factors are asked for.
-  // With FP32 factors N_k^{-1} is rounded before it multiplies S(I_k,:), and its entries
-  // grow like cond(N_k) while Ur_k stays O(1): on smooth kernels (cond(N_k) ~ 1e6 within
-  // one block of 100) the estimate then carries an error near 1e-2 and the loop runs
-  // extra iterations.  The factors are a small part of the traffic, so FP64 is the default.
-  const bool res64 = o.residual_fp64 >= 0;
+  // Residual factors.  Plain form: FP64 factors on the FP64 matrix cores.  Precision
+  // form at tol >= 1e-4 (and residual_fp64 = -1): the factors LcT and Ur are stored in
+  // FP32 and the two large products of every iteration, the row residual at the new
+  // columns and the residual at the new rows, run on BF16 pieces of both operands (FP32
+  // matrix cores in the plain form) with FP32 chunk sums added in FP64.  N_k^{-1}
+  // S(I_k,:) stays FP64: N_k^{-1} grows like cond(N_k) while Ur_k stays O(1), so it must
+  // not be rounded before it multiplies; the column update S -= S(:,J_k) Ur_k and its
+  // norm use that FP64 Ur_k.  The residual form rebuilds A(I_k,:) from the factors and
+  // subtracts, so FP32 factors (and FP32 sums) leave an absolute error near 2^-24 of the
+  // entries of A in every residual; below tol 1e-4 that reaches the residual itself on
+  // slowly decaying spectra (the estimate then undershoots the error), so the precision
+  // form keeps FP64 factors there.  residual_fp64 = 1 forces FP64 factors in either form.
+  const bool res64 = o.residual_fp64 == 1 || (o.residual_fp64 == 0 && !(split && tol >= kSplitResidualMinTol));
   const size_t fsz = res64 ? 8 : 4;
+  // BF16 pieces of the FP32-factor products: their rounding enters the residual relative
+  // to the scale of A, and the next factors amplify it by the conditioning of the pivot
+  // blocks, so the residual needs more than the sketch: three pieces (FP32-exact
+  // operands) below tol 1e-1, two above; none on the plain form's FP32 matrix cores
+  const int Tres = split ? residual_terms_for_tol(tol) : 0;
   hipStream_t st = as_stream(o.stream);
 
   DeviceCache* dcp = nullptr;
@@ -591,7 +609,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   const int64_t ldg = (m + 7) / 8 * 8;  // 16-byte aligned rows of G for the sketch kernel
   ICUR_TRY(ensure(dc, kG, sparse ? csr_sketch_aux_bytes(m, c) : sketch_G_bytes(kind, c, m, ldg), &pG));
   ICUR_TRY(ensure(dc, kX0, static_cast<size_t>(c) * n * 8, &pX0));
-  ICUR_TRY(ensure(dc, kSrow, static_cast<size_t>(b) * n * fsz, &pSr));
+  ICUR_TRY(ensure(dc, kSrow, static_cast<size_t>(b) * n * 8, &pSr));  // FP64 in both forms
   ICUR_TRY(ensure(dc, kColMask, static_cast<size_t>(n), &pColMask));
   ICUR_TRY(ensure(dc, kRowMask, static_cast<size_t>(m), &pRowMask));
   ICUR_TRY(ensure(dc, kJk, static_cast<size_t>(b) * 8, &pJk));
@@ -610,6 +628,8 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
                                   csr_max_norm_partials(n));
   ICUR_TRY(ensure(dc, kNormPart, static_cast<size_t>(nparts_cap) * 8, &pNorm));
   ICUR_TRY(ensure(dc, kScal, sizeof(Scal), &pScal));
+  void* pUrk64 = nullptr;  // FP64 Ur_k of the FP32-factor path
+  if (!res64) ICUR_TRY(ensure(dc, kUrk64, static_cast<size_t>(b) * n * 8, &pUrk64));
   LuppWork lw;
   lupp_bind_workspace(pLupp, b, std::max(m, n), &lw);
   lw.max_groups = lupp_groups;
@@ -668,16 +688,16 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
       return product_f64(W64, K, M, K, static_cast<const double*>(X), ldx, static_cast<const double*>(B), ldb, N,
                          subtract, static_cast<double*>(OUT), ldo, norm ? dnorm : nullptr, parts, pGemm,
                          dc.buf[kGemmWs].bytes, st);
-    if (K > 0) ICUR_TRY(launch_split_f64(W64, M, K, K, false, T, pWp, K, M * K, st));
+    if (K > 0) ICUR_TRY(launch_split_f64(W64, M, K, K, false, Tres, pWp, K, M * K, st));
     WideGemm g{};
     g.X = X;
     g.ldx = ldx;
     g.W = pWp;
     g.ldw = K;
-    g.wterms = T;
+    g.wterms = Tres;
     g.B = B;
     g.ldb = ldb;
-    g.bterms = T;
+    g.bterms = Tres;
     g.M = M;
     g.K = K;
     g.N = N;
@@ -728,6 +748,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
   tm.add(ev_p0, ev_p1, &t_info.ms_sketch_product);
   t_info.threshold = thr;
   t_info.split_terms = T;
+  t_info.residual_terms = res64 ? -1 : Tres;
   // ||G A||_F^2 is read back with the first selection's status (one synchronisation
   // less); the selection on a zero or non-finite sketch is harmless and discarded.
   // Returns 1 when the call ends here (rank 0, or an error in *err).
@@ -833,32 +854,43 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
       status = ICUR_STALLED;
       break;
     }
-    // N_k = S^{(k-1)}(I_k, J_k) and its inverse (FP64)
-    ICUR_TRY(gather_w(Lk, m, nI, Ik, nI, true, Nblk, nI));
-    ICUR_TRY(launch_inorder_inverse(Nblk, nI, Nwork, &dscal->info, st));
-    // N_1 = A(I_1, J_1) exactly: its inverse is the core's first diagonal block inverse
-    if (r == 0) ICUR_HIP(hipMemcpyAsync(N1inv, Nblk, static_cast<size_t>(nI) * nI * 8, hipMemcpyDeviceToDevice, st));
-    // residual at the new rows: Sr = A(I_k,:) - Lc(I_k,:) Ur
-    if (sparse) {
-      if (res64)
-        ICUR_TRY(csr_gather_rows(*src.csr, Ik, nI, static_cast<double*>(Sr), n, st));
+    // N_k = S^{(k-1)}(I_k, J_k) and its inverse (FP64), and the residual at the new rows
+    // Sr = A(I_k,:) - Lc(I_k,:) Ur (FP64 in both forms).  With FP64 factors N_k is read
+    // from the row residual S^row; with FP32 factors it is read from Sr, the FP64 product
+    // that N_k^{-1} multiplies, so that Ur_k(:, J_k) is the identity to FP64 rounding (the
+    // FP32-stored S^row differs from Sr by its rounding, which cond(N_k) would amplify)
+    auto pivot_block = [&](const void* from_rows, bool from_sr) -> int {
+      if (from_sr)
+        ICUR_TRY(launch_gather_f64(static_cast<const double*>(from_rows), n, nullptr, nI, Jk, nI, false, Nblk, nI,
+                                   st));
       else
-        ICUR_TRY(csr_gather_rows(*src.csr, Ik, nI, static_cast<float*>(Sr), n, st));
-    } else if (res64) {
+        ICUR_TRY(gather_w(from_rows, m, nI, Ik, nI, true, Nblk, nI));
+      ICUR_TRY(launch_inorder_inverse(Nblk, nI, Nwork, &dscal->info, st));
+      // N_1 = A(I_1, J_1) exactly: its inverse is the core's first diagonal block inverse
+      if (r == 0)
+        ICUR_HIP(hipMemcpyAsync(N1inv, Nblk, static_cast<size_t>(nI) * nI * 8, hipMemcpyDeviceToDevice, st));
+      return ICUR_OK;
+    };
+    if (res64) ICUR_TRY(pivot_block(Lk, false));
+    if (sparse)
+      ICUR_TRY(csr_gather_rows(*src.csr, Ik, nI, static_cast<double*>(Sr), n, st));
+    else
       ICUR_TRY(launch_gather_rows(A, m, n, lda, Ik, nI, static_cast<double*>(Sr), n, st));
-    } else {
-      ICUR_TRY(launch_gather_rows(A, m, n, lda, Ik, nI, static_cast<float*>(Sr), n, st));
-    }
     if (r > 0) {
       ICUR_TRY(gather_w(LcT, m, r, Ik, nI, true, W64, r));  // Lc(I_k,:)
-      ICUR_TRY(product(W64, nI, r, Sr, n, Ur, n, n, true, Sr, n, false, false, &parts));
+      ICUR_TRY(product(W64, nI, r, Sr, n, Ur, n, n, true, Sr, n, false, true, &parts));
     }
-    // new row factors Ur_k = N_k^{-1} Sr
+    if (!res64) ICUR_TRY(pivot_block(Sr, true));
+    // new row factors Ur_k = N_k^{-1} Sr (FP64), then the column residual update
+    // S^col <- S^col - S^col(:,J_k) Ur_k and its norm (FP64)
     void* Urk = fp(Ur, r * n);
-    ICUR_TRY(product(Nblk, nI, nI, nullptr, n, Sr, n, n, false, Urk, n, false, false, &parts));
-    // column residual update S^col <- S^col - S^col(:,J_k) Ur_k, and its norm
+    double* Urk64 = res64 ? static_cast<double*>(Urk) : static_cast<double*>(pUrk64);
+    ICUR_TRY(product_f64(Nblk, nI, nI, nI, nullptr, n, static_cast<const double*>(Sr), n, n, false, Urk64, n, nullptr,
+                         &parts, pGemm, dc.buf[kGemmWs].bytes, st));
+    if (!res64) ICUR_TRY(convert_f64_f32_norm(Urk64, nI, n, static_cast<float*>(Urk), n, dnorm, nullptr, st));
     ICUR_TRY(launch_gather_f64(S, n, nullptr, c, Jk, nI, false, W64, nI, st));
-    ICUR_TRY(product(W64, c, nI, S, n, Urk, n, n, true, S, n, true, true, &parts));
+    ICUR_TRY(product_f64(W64, nI, c, nI, S, n, Urk64, n, n, true, S, n, dnorm, &parts, pGemm, dc.buf[kGemmWs].bytes,
+                         st));
     if (dc.host_pinned_dev) {
       // norm, commit and the scalar read-back in one launch
       const bool flag = dc.spin;

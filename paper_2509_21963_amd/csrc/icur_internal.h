@@ -128,6 +128,8 @@ int launch_reduce_partials(const double* partials, int n, double* out, hipStream
 constexpr double kSketchChunkFlushBelow = 1e-4;
 // BF16 pieces per FP32 operand of the split form for a tolerance (icur_api.hip).
 int terms_for_tol(double tol);
+// BF16 pieces per operand of the split form's FP32-factor residual products.
+int residual_terms_for_tol(double tol);
 // Bytes of the G buffer form_sketch needs (BF16 operators: c x ldg x 2; SRTT: the FP32
 // operator, its kept rows and m bytes of scratch).
 size_t sketch_G_bytes(int kind, int64_t c, int64_t m, int64_t ldg);

@@ -20,8 +20,8 @@ factor (1 + a_t)^2, a_t = t max|T| ||T(P,0:t)^{-1}||_1.)  The input perturbation
     the block: the oracle forms S^col = X0 - X0(:,J) A(I,J)^+ A(I,:), whose rounding
     grows with cond; the GPU's residual form does not, so the oracle's term dominates;
   row steps: (eta_row + 4 sqrt(r + 1) cond 2^-52) max|A| (the row residual involves no
-    sketch and both sides form it in FP64 from the same FP32 values; eta_row covers the
-    opt-in FP32 residual factors).
+    sketch; with FP64 factors both sides form it in FP64 from the same FP32 values, and
+    eta_row covers the rounding of FP32 factors, see residual_eta).
   With QRCP the compared values are residual 2-norms of K-vectors, so both bounds are
   multiplied by sqrt(K).
 """
@@ -47,6 +47,18 @@ def sketch_eta(terms, chunk=128, sparse=False):
         return 16 * 64 * EPS64
     trunc = 0.0 if terms in (0, 3) else 2.0 ** -(8 * terms + 1)
     return 16 * (trunc + math.sqrt(chunk) * EPS32)
+
+
+def residual_eta(terms):
+    """Rounding of the FP32-factor residual products relative to the scale of A, with a
+    factor 4 of headroom.
+
+    The factors are stored in FP32 (2^-24 relative) and both operands of the two large
+    products are cut into `terms` BF16 pieces (2^-(8 T + 1) relative each; T = 0 means FP32
+    matrix cores, no cut); FP32 sums over 32-deep chunks add about sqrt(32) 2^-24.
+    """
+    trunc = 0.0 if terms == 0 else 2.0 * 2.0 ** -(8 * terms + 1)
+    return 4 * (trunc + EPS32 + math.sqrt(32) * EPS32)
 
 
 def blocks_of(rank, b, max_rank=None, sizes=None):

@@ -23,7 +23,7 @@ torch = pytest.importorskip("torch")
 
 from oracle.icur import exact_relative_error, iterative_cur, pinv_svd   # noqa: E402
 from paper_2509_21963_amd import workloads as W               # noqa: E402
-from _replay import replay, sketch_eta                          # noqa: E402
+from _replay import residual_eta, replay, sketch_eta                          # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -52,6 +52,13 @@ def check_against_oracle(icur, A32, tol, b, kind, seed, precision=0, eta=None, e
     assert len(set(I)) == r and len(set(J)) == r
     if eta is None:
         eta = form_eta(got, tol, precision, kw.get("sketch_fp32", False))
+        # FP32 factors (the precision form's default, or residual_fp64 = -1): the residual
+        # products' rounding enters the row residual directly and the sketched residual
+        # through Ur_k
+        if got["info"]["residual_terms"] >= 0:
+            er = residual_eta(got["info"]["residual_terms"])
+            eta_row = max(eta_row, er)
+            eta = eta + 4 * er
     # every pivot of the GPU run, replayed through the oracle along the GPU's trajectory
     denominator = "A" if kw.get("denominator") == 1 else "GA"
     stats, rep = replay(A64, I, J, got["info"]["block_sizes"], tol, b, kind, seed, eta,
@@ -88,10 +95,9 @@ def test_residual_factor_precision_switch(icur, res64):
     # tol 1e-4 is well above the FP32 floor: both factor precisions meet it
     A, _ = W.planted_geometric(1200, 1000, 30.0, seed=6)
     A32, _ = W.to_f32(A)
-    # the opt-in FP32 factors round N_k^{-1} before it multiplies: the sketched and row
-    # residuals then carry about cond(N_k) 2^-24 of noise (eta 1e-3)
-    extra = {} if res64 == 1 else {"eta": 1e-3, "eta_row": 1e-4}
-    got, ora, err = check_against_oracle(icur, A32, 1e-4, 32, 0, 6, residual_fp64=res64, **extra)
+    # FP32 factors on the FP32 matrix cores (plain form, residual_fp64 = -1): the row
+    # residual carries their rounding; N_k^{-1} S(I_k,:) stays FP64
+    got, ora, err = check_against_oracle(icur, A32, 1e-4, 32, 0, 6, residual_fp64=res64)
     assert got["status"] == "ok" and err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
 
 
@@ -133,6 +139,7 @@ def test_bf16_split_form(icur, tol):
     assert got["status"] == "ok"
     assert err <= 2 * tol and 0.5 <= got["rho"] / err <= 2.0
     assert got["info"]["split_terms"] == (1 if tol >= 1e-1 else 2 if tol >= 5e-4 else 3)
+    assert got["info"]["residual_terms"] == (2 if tol >= 1e-1 else 3 if tol >= 1e-4 else -1)
 
 
 @pytest.mark.parametrize("kind", [0, 1])
