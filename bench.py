@@ -17,9 +17,10 @@ resident in HBM.  Beside it, in the same line:
                         (about 20 s of host time), scaled by count / drawn.
 Other workloads (--workload): rbf (40000 x 40000 RBF kernel, tol 1e-4, block 100,
 sparse-sign sketch, plain FP32), precision (the 60000 x 40000 form alone), csr (the
-200000 x 100000 sparse form), each printing its own line with the same fields.
+200000 x 100000 sparse form), x1 (the paper's 30000 x 30000 rank-2000 Low-Rank matrix,
+tol 1e-6, block 250), each printing its own line with the same fields.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--workload batched|rbf|precision|csr] [--count N] [--workers W]
+                       [--workload batched|rbf|precision|csr|x1] [--count N] [--workers W]
 """
 import argparse
 import hashlib
@@ -293,6 +294,79 @@ def bench_precision(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_x1(a):
+    """The paper's rank-adaptive Low-Rank matrix (§5.1): A = G1 G2^T, G_i 30000 x 2000
+    standard Gaussian, FP32, tol 1e-6, block 250, Gaussian sketch, plain form."""
+    import numpy as np
+    import torch
+    from paper_2509_21963_amd import icur
+    from paper_2509_21963_amd import workloads as W
+
+    icur.load()
+    m = n = 30000
+    rk, b, tol = 2000, 250, 1e-6
+    c = (11 * b) // 10
+    print("generating the %dx%d rank-%d matrix on the device" % (m, n, rk), file=sys.stderr, flush=True)
+    A = W.low_rank_device(m, n, rk, seed=0)
+    torch.cuda.synchronize()
+    for i in range(a.warmup):
+        icur.run(A, tol, b, icur.GAUSSIAN, seed=i)
+    torch.cuda.synchronize()
+    times, outs = [], []
+    for i in range(a.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        outs.append(out)
+        print("step %d: %.2f ms, rank %d, rho %.3e, %d iterations" % (
+            i, times[-1] * 1e3, out["rank"], out["rho"], out["info"]["iterations"]), file=sys.stderr, flush=True)
+    value = statistics.median(times)
+    last = outs[-1]
+    sk = statistics.mean(o["info"]["ms_sketch_product"] for o in outs)
+    # the sketch kernel: c = 275 rows run as two slices of G, each reading A once
+    slices = -(-c // 160)
+    alg_bytes = 4.0 * m * n * slices + 2.0 * c * m + 8.0 * c * n
+    achieved = alg_bytes / (sk * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": value * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": "Low-Rank (rank-adaptive experiment): A = G1 G2^T, G_i %dx%d standard Gaussian (device "
+                        "generator), FP32 %dx%d, tol %g, block %d, Gaussian sketch, plain form" % (m, rk, m, n, tol, b),
+            "rank": last["rank"], "rho": last["rho"], "iterations": last["info"]["iterations"],
+            "sketch_ms": sk, "select_ms": statistics.mean(o["info"]["ms_select"] for o in outs),
+            "residual_ms": statistics.mean(o["info"]["ms_residual"] for o in outs),
+            "core_ms": statistics.mean(o["info"]["ms_core"] for o in outs),
+            "paper_context": "the paper reports a 12 s median for IterativeCUR on this matrix on its CPU machine "
+                             "(48 cores); context, not the target",
+        },
+        "roofline": {
+            "kernel": "sketch product G A (sketch_kernel, 3 BF16 pieces of A, %d slices of G)" % slices,
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_ms": sk, "algorithmic_bytes": alg_bytes,
+        },
+    }
+    if not a.no_cpu:
+        from oracle.icur import iterative_cur
+        print("timing the CPU oracle on the same matrix", file=sys.stderr, flush=True)
+        A64 = A.cpu().numpy().astype(np.float64)
+        del A
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        ora = iterative_cur(A64, tol, b, kind=0, seed=0)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {
+            "value": dt, "unit": "s", "cores": int(oracle_threads()), "kind": "oracle",
+            "sample": "one FP64 NumPy oracle run on the full %dx%d matrix (copied from the device, widened to "
+                      "FP64): rank %d, rho %.2e" % (m, n, ora["rank"], ora["rho"])}
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
 def bench_csr(a):
     """The sparse form through icur_run_csr, BF16-split and plain FP32."""
     import numpy as np
@@ -379,7 +453,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--form", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--size", type=int, default=40000)
-    ap.add_argument("--workload", choices=["rbf", "batched", "precision", "csr"], default="batched")
+    ap.add_argument("--workload", choices=["rbf", "batched", "precision", "csr", "x1"], default="batched")
     ap.add_argument("--no-precision", action="store_true", help="batched: skip the precision-form comparison")
     ap.add_argument("--no-plain", action="store_true", help="batched: skip the plain loop (profiling runs)")
     ap.add_argument("--count", type=int, default=512)
@@ -394,7 +468,8 @@ def main():
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
             sys.exit(1)
-        return {"batched": bench_batched, "precision": bench_precision, "csr": bench_csr}[a.workload](a)
+        return {"batched": bench_batched, "precision": bench_precision, "csr": bench_csr,
+                "x1": bench_x1}[a.workload](a)
 
     import torch
     from paper_2509_21963_amd import icur

@@ -51,7 +51,7 @@ namespace {
 enum Slot {
   kG, kRowsPat, kSignsPat, kX0, kS, kSrow, kCt, kR, kU, kY, kA12, kA21, kA22, kYt, kX0J, kW64,
   kWp, kColMask, kRowMask, kJk, kIk, kJall, kIall, kLupp, kGemmWs, kNormPart, kScal, kCoreWs,
-  kStepA, kStepB, kCsc, kQrcp, kUrk64, kNumSlots
+  kStepA, kStepB, kCsc, kQrcp, kUrk64, kCoreRef, kNumSlots
 };
 
 struct Buf {
@@ -941,7 +941,7 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
 
   // ---- the core U = A(I,J)^{-1} in FP64 from the exact cross entries: block LU in the
   //      selection order (its diagonal blocks are the pivot blocks N_k of the row
-  //      selections), then block triangular solves on the identity
+  //      selections), block triangular solves on the identity, and one Newton step
   if (r > 0) {
     // the core starts where the last iteration ended, unless the loop stopped part-way
     size_t ec0 = iter_start, ec1;
@@ -960,7 +960,13 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     else
       ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
                                  false, M, r, st));
+    // the cross is kept for one refinement step of the block-LU inverse
+    void* pRef;
+    ICUR_TRY(ensure(dc, kCoreRef, (static_cast<size_t>(r) * r + core_refine_ws_doubles(r)) * 8, &pRef));
+    double* M0 = static_cast<double*>(pRef);
+    ICUR_TRY(dcopy2d(r, r, 1.0, M, r, M0, r, st));
     ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, nullptr, st, N1inv));
+    ICUR_TRY(core_refine(M0, U, r, M0 + static_cast<size_t>(r) * r, st));
     ICUR_TRY(tm.mark(&ec1));
     // the pivot-block flags and the results: through the pinned staging area in one
     // synchronisation when they fit, else the flags first and the results directly

@@ -10,6 +10,7 @@
 // notes the update alternative in §3.4).  N^-1 comes from Gauss-Jordan elimination with
 // partial pivoting in one workgroup.
 #include <algorithm>
+#include <cstring>
 
 #include <utility>
 
@@ -389,6 +390,16 @@ __global__ __launch_bounds__(256) void gj_inverse_inorder_kernel(double* __restr
   gj_inorder_tile(Ng, k, info);
 }
 
+// The same, leaving *info alone unless the block is singular (the blocked inverse runs
+// several and reports any failure).
+__global__ __launch_bounds__(256) void gj_inverse_inorder_sticky_kernel(double* __restrict__ Ng, int k,
+                                                                        int* __restrict__ info) {
+  __shared__ int flag;
+  gj_inorder_tile(Ng, k, &flag);
+  __syncthreads();
+  if (threadIdx.x == 0 && flag != 0) *info = 1;
+}
+
 }  // namespace
 
 namespace {
@@ -482,7 +493,29 @@ int launch_fill_f64_identity(double* U, int64_t r, hipStream_t st) {
   return ICUR_OK;
 }
 
-size_t small_inverse_work_bytes(int64_t k) { return static_cast<size_t>(k) * k * sizeof(double); }
+// max |R| over an r x r matrix into *out (zeroed by the caller): non-negative doubles
+// order as their bit patterns, so an integer atomic max of the bits is the maximum.
+__global__ __launch_bounds__(256) void maxabs_kernel(const double* __restrict__ R, int64_t total,
+                                                     unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * 256)
+    m = fmax(m, fabs(R[e]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(m)));
+}
+
+// U += T when the refinement converges (max |I - M U| below 1/2), else U is left alone.
+__global__ __launch_bounds__(256) void refine_apply_kernel(double* __restrict__ U, const double* __restrict__ T,
+                                                           int64_t total, const unsigned long long* __restrict__ rmax) {
+  if (__longlong_as_double(static_cast<long long>(*rmax)) >= 0.5) return;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * 256)
+    U[e] += T[e];
+}
+
+// The general kernel's work (k^2) and the blocked in-order inverse's (under 3 k^2).
+size_t small_inverse_work_bytes(int64_t k) { return 3 * static_cast<size_t>(k) * k * sizeof(double); }
 
 int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* norms,
                          hipStream_t st) {
@@ -503,13 +536,50 @@ int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* 
   return ICUR_OK;
 }
 
+// In-order inverse of a k x k block (rows in partial-pivoting order, ld k) for k > 128:
+// 2 x 2 block elimination on a leading block of 128 (the in-order Gauss-Jordan tile),
+// the trailing Schur complement S = D - C A^{-1} B inverted the same way (it is the next
+// stage of the same LU), and the four blocks of the inverse formed by FP64 products:
+// [A^{-1} + A^{-1} B S^{-1} C A^{-1}, -A^{-1} B S^{-1}; -S^{-1} C A^{-1}, S^{-1}].
+// work: under 3 k^2 doubles.  *info must be 0 on entry; set to 1 on a zero pivot.
+int blocked_inorder_inverse(double* N, int64_t k, double* work, int* info, hipStream_t st) {
+  constexpr int64_t h = 128;
+  const int64_t t = k - h;
+  double* Ai = work;         // h x h: A^{-1}
+  double* X = Ai + h * h;    // t x h: C A^{-1}
+  double* S = X + t * h;     // t x t: D - X B, then its inverse
+  double* Y = S + t * t;     // h x t: A^{-1} B
+  double* Z = Y + h * t;     // t x h: S^{-1} X
+  double* rest = Z + t * h;  // the trailing inverse's own work
+  ICUR_TRY(dcopy2d(h, h, 1.0, N, k, Ai, h, st));
+  hipLaunchKernelGGL(gj_inverse_inorder_sticky_kernel, dim3(1), dim3(256), 0, st, Ai, static_cast<int>(h), info);
+  ICUR_HIP(hipGetLastError());
+  ICUR_TRY(gemm_f64_native(t, h, h, 1.0, N + h * k, k, Ai, h, nullptr, 0, X, h, st));
+  ICUR_TRY(gemm_f64_native(t, t, h, -1.0, X, h, N + h, k, N + h * k + h, k, S, t, st));
+  if (t <= h) {
+    hipLaunchKernelGGL(gj_inverse_inorder_sticky_kernel, dim3(1), dim3(256), 0, st, S, static_cast<int>(t), info);
+    ICUR_HIP(hipGetLastError());
+  } else {
+    ICUR_TRY(blocked_inorder_inverse(S, t, rest, info, st));
+  }
+  ICUR_TRY(gemm_f64_native(h, t, h, 1.0, Ai, h, N + h, k, nullptr, 0, Y, t, st));
+  ICUR_TRY(gemm_f64_native(t, h, t, 1.0, S, t, X, h, nullptr, 0, Z, h, st));
+  ICUR_TRY(gemm_f64_native(h, h, t, 1.0, Y, t, Z, h, Ai, h, N, k, st));
+  ICUR_TRY(gemm_f64_native(h, t, t, -1.0, Y, t, S, t, nullptr, 0, N + h, k, st));
+  ICUR_TRY(dcopy2d(t, h, -1.0, Z, h, N + h * k, k, st));
+  ICUR_TRY(dcopy2d(t, t, 1.0, S, t, N + h * k + h, k, st));
+  return ICUR_OK;
+}
+
 int launch_inorder_inverse(double* N, int64_t k, double* work, int* info, hipStream_t st) {
   if (k >= 1 && k <= 128) {
     hipLaunchKernelGGL(gj_inverse_inorder_kernel, dim3(1), dim3(256), 0, st, N, static_cast<int>(k), info);
     ICUR_HIP(hipGetLastError());
     return ICUR_OK;
   }
-  return launch_small_inverse(N, k, work, info, nullptr, st);
+  if (k < 1 || k > 512) return arg_error("inverse: block size must be in 1..512");
+  ICUR_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(info), 1, 0u, st));
+  return blocked_inorder_inverse(N, k, work, info, st);
 }
 
 // U (ldu) grows from r x r to (r+k) x (r+k).  ws must hold k*k + 2*k*r + k*k doubles.
@@ -601,6 +671,44 @@ int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblo
   return ICUR_OK;
 }
 
-size_t core_inverse_ws_doubles(int64_t r, int64_t bmax) { return r * bmax + bmax * r + bmax * bmax; }
+// Newton steps on the core: U <- U + U (I - M U), M the cross A(I,J) (ld r).  The block
+// LU in selection order pivots only within the blocks, so on ill-conditioned crosses its
+// inverse can carry far more error than a fully pivoted one (the CUR error with it can
+// exceed the tolerance while A(I,J)^+ meets it).  The residual R = I - M U squares with
+// every step, down to its own rounding (near cond 2^-52).  Up to three steps, each taken
+// only while max |R| is below 1/2 (convergence), above 2^-40 (still worth a step) and at
+// most half the previous one (still shrinking); the host reads max |R| before each.
+// ws: 2 r^2 + 1 doubles.
+int core_refine(const double* M, double* U, int64_t r, double* ws, hipStream_t st) {
+  if (r <= 0) return ICUR_OK;
+  double* R = ws;
+  double* T = ws + r * r;
+  unsigned long long* rmax = reinterpret_cast<unsigned long long*>(T + r * r);
+  const int64_t total = r * r;
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 1024));
+  double prev = 1.0;
+  for (int step = 0; step < 3; ++step) {
+    ICUR_TRY(launch_fill_f64_identity(R, r, st));
+    ICUR_TRY(dgemm(r, r, r, -1.0, M, r, 1, U, r, 1, 1.0, R, r, st));
+    ICUR_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(rmax), 2, 0u, st));
+    hipLaunchKernelGGL(maxabs_kernel, dim3(blocks), dim3(256), 0, st, R, total, rmax);
+    ICUR_HIP(hipGetLastError());
+    unsigned long long bits = 0;
+    ICUR_HIP(hipMemcpyAsync(&bits, rmax, sizeof(bits), hipMemcpyDeviceToHost, st));
+    ICUR_HIP(hipStreamSynchronize(st));
+    double v;
+    std::memcpy(&v, &bits, sizeof(v));
+    if (!(v < 0.5) || v <= 0x1.0p-40 || v > 0.5 * prev) break;
+    prev = v;
+    ICUR_TRY(dgemm(r, r, r, 1.0, U, r, 1, R, r, 1, 0.0, T, r, st));
+    hipLaunchKernelGGL(refine_apply_kernel, dim3(blocks), dim3(256), 0, st, U, T, total, rmax);
+    ICUR_HIP(hipGetLastError());
+  }
+  return ICUR_OK;
+}
+
+size_t core_refine_ws_doubles(int64_t r) { return 2 * r * r + 1; }
+
+size_t core_inverse_ws_doubles(int64_t r, int64_t bmax) { return r * bmax + bmax * r + 3 * bmax * bmax; }
 
 }  // namespace icur

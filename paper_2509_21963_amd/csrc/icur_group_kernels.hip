@@ -15,6 +15,7 @@
 // loop forms Q^{-1} P^{-1}.
 #include <algorithm>
 #include <climits>
+#include <cstring>
 
 #include "icur_batched.h"
 #include "icur_gj.h"
@@ -318,186 +319,202 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Persistent FP64 product over a list of ops, tiles of 16 TR rows x 128 WN columns.  Lane
-// (lr, lg) of wave w, MFMA step j of a chunk starting at k0: A operand W[row lr][k0 + 4 lg
-// + j] (from LDS), B operand B[k0 + 4 lg + j][column], accumulator slot v = row 4 v + lg
-// (every shape and both kernels use this k order, so the sums are the same).  The wave owns 32 WN columns of
-// the tile in pairs: 16-column sub-tile s holds the columns n0 + 32 (s / 2) + 2 lr + s % 2,
-// so a lane reads the two columns of a pair of B (and of X and OUT) with one 16-byte
-// access.  The depth runs in chunks of kKC: W of the next chunk and B of the next chunk
-// are loaded into registers while the current one is multiplied, W through two LDS
-// buffers (one barrier per chunk).
+// FP64 products on workgroup tiles of 16 TR rows x 128 WN columns.  Lane (lr, lg) of wave
+// w, MFMA step j of a chunk starting at k0: A operand W[row lr][k0 + 4 lg + j] (from LDS),
+// B operand B[k0 + 4 lg + j][column], accumulator slot v = row 4 v + lg (every shape and
+// both tile kinds use this k order, so the sums are the same).  The wave owns 32 WN
+// columns of the tile in pairs: 16-column sub-tile s holds the columns n0 + 32 (s / 2) +
+// 2 lr + s % 2, so a lane reads the two columns of a pair of B (and of X and OUT) with one
+// 16-byte access.  The depth runs in chunks of kKC: W of the next chunk and B of the next
+// chunk are loaded into registers while the current one is multiplied, W through two LDS
+// buffers (one barrier per chunk).  gemm_wg_tile is one tile; gemm_kernel walks a list of
+// ops (persistent), gemm_one_kernel the tiles of one op.
 template <int TR, int WN>
-__global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
-                                                   const int* __restrict__ pntiles) {
+__device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*wl)[kKC * (16 * TR + 2)],
+                                             double* red) {
   constexpr int RT = 16 * TR;          // tile rows
   constexpr int CT = 128 * WN;         // tile columns
   constexpr int S = 2 * WN;            // 16-column sub-tiles per wave
   constexpr int kStride = RT + 2;      // LDS row stride of the transposed W chunk
   constexpr int WPT = RT * kKC / kPT;  // W entries per thread per chunk
   static_assert(WPT * kPT == RT * kKC, "W chunk must split evenly over the threads");
-  __shared__ double wl[2][kKC * kStride];
-  __shared__ double red[kPT / 64];
-  const int nops = *pnops, ntiles = *pntiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
+  const int M = o.M, K = o.K, N = o.N;
+  const int m0 = (lt / o.tiles_n) * RT;
+  const int n0t = (lt % o.tiles_n) * CT;
+  const int n0 = n0t + wave * 32 * WN;
+  const double* __restrict__ W = o.W;
+  const double* __restrict__ B = o.B;
+  const int64_t ldw = o.ldw, ldb = o.ldb;
+  const bool wt = o.wt != 0;
+  // 16-byte accesses where the pair is aligned: even leading dimension, aligned base
+  const bool bvec = ((ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+  int col[S];
+#pragma unroll
+  for (int s2 = 0; s2 < S; ++s2) col[s2] = n0 + 32 * (s2 >> 1) + 2 * lr + (s2 & 1);
+  // depth range: block-triangular operands are zero below kbeg for the whole tile; it
+  // starts at a chunk boundary so the grouping of the sums does not depend on the tile
+  int kbeg = 0;
+  if (o.kskip & 1) kbeg = max(kbeg, m0 - o.kband);
+  if (o.kskip & 2) kbeg = max(kbeg, n0t - o.kband);
+  kbeg = (kbeg / kKC) * kKC;
+  const int nch = kbeg < K ? (K - kbeg + kKC - 1) / kKC : 0;
+
+  doublex4 acc[TR][S];
+#pragma unroll
+  for (int t = 0; t < TR; ++t)
+#pragma unroll
+    for (int s2 = 0; s2 < S; ++s2) acc[t][s2] = doublex4{0.0, 0.0, 0.0, 0.0};
+  constexpr int NJ = kKC / 4;  // MFMA steps per chunk
+  double b[NJ][S];
+  double wr[WPT];
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int k = k0 + 4 * lg + j;
+      const bool kok = k < K;
+      const double* row = B + static_cast<int64_t>(kok ? k : 0) * ldb;
+#pragma unroll
+      for (int p = 0; p < WN; ++p) {
+        const int c0 = col[2 * p];
+        if (bvec && kok && c0 + 1 < N) {
+          const double2 v = *reinterpret_cast<const double2*>(row + c0);
+          b[j][2 * p] = v.x;
+          b[j][2 * p + 1] = v.y;
+        } else {
+          b[j][2 * p] = (kok && c0 < N) ? row[c0] : 0.0;
+          b[j][2 * p + 1] = (kok && c0 + 1 < N) ? row[c0 + 1] : 0.0;
+        }
+      }
+    }
+  };
+  auto load_w = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int e = tid + kPT * q;
+      int row, kk;
+      if (wt) {
+        kk = e / RT;
+        row = e % RT;
+      } else {
+        row = e / kKC;
+        kk = e % kKC;
+      }
+      const int gr = m0 + row, gk = k0 + kk;
+      const bool ok = gr < M && gk < K;
+      wr[q] = ok ? (wt ? W[static_cast<int64_t>(gk) * ldw + gr] : W[static_cast<int64_t>(gr) * ldw + gk]) : 0.0;
+    }
+  };
+  auto store_w = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int e = tid + kPT * q;
+      const int row = wt ? e % RT : e / kKC;
+      const int kk = wt ? e / RT : e % kKC;
+      wl[buf][kk * kStride + row] = wr[q];
+    }
+  };
+  if (nch > 0) {
+    load_w(kbeg);
+    load_b(kbeg);
+  }
+  __syncthreads();  // the previous tile's readers of the LDS buffers are done
+  if (nch > 0) store_w(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int cur = ch & 1;
+    const int k0 = kbeg + ch * kKC;
+    double bc[NJ][S];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) bc[j][s2] = b[j][s2];
+    const bool more = ch + 1 < nch;
+    if (more) {
+      load_w(k0 + kKC);
+      load_b(k0 + kKC);
+    }
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      double a[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) a[j] = wl[cur][(4 * lg + j) * kStride + t * 16 + lr];
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[t][s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bc[j][s2], acc[t][s2], 0, 0, 0);
+    }
+    if (more) store_w(cur ^ 1);
+    __syncthreads();
+  }
+  // epilogue: OUT = X + alpha acc, pairs of columns per lane
+  const bool ovec = ((o.ldo & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.OUT) & 15) == 0) &&
+                    (!o.X || (((o.ldx & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.X) & 15) == 0)));
+  double sq = 0.0;
+#pragma unroll
+  for (int t = 0; t < TR; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = m0 + t * 16 + 4 * v + lg;
+      if (row >= M) continue;
+      double* orow = o.OUT + static_cast<int64_t>(row) * o.ldo;
+      const double* xrow = o.X ? o.X + static_cast<int64_t>(row) * o.ldx : nullptr;
+#pragma unroll
+      for (int p = 0; p < WN; ++p) {
+        const int c0 = col[2 * p];
+        double y0 = o.alpha * acc[t][2 * p][v];
+        double y1 = o.alpha * acc[t][2 * p + 1][v];
+        if (ovec && c0 + 1 < N) {
+          if (xrow) {
+            const double2 x = *reinterpret_cast<const double2*>(xrow + c0);
+            y0 = x.x + y0;
+            y1 = x.y + y1;
+          }
+          *reinterpret_cast<double2*>(orow + c0) = double2{y0, y1};
+          sq += y0 * y0 + y1 * y1;
+        } else {
+          if (c0 < N) {
+            if (xrow) y0 = xrow[c0] + y0;
+            orow[c0] = y0;
+            sq += y0 * y0;
+          }
+          if (c0 + 1 < N) {
+            if (xrow) y1 = xrow[c0 + 1] + y1;
+            orow[c0 + 1] = y1;
+            sq += y1 * y1;
+          }
+        }
+      }
+    }
+  if (o.normp) {
+    const double tot = block_sum(sq, red);
+    if (tid == 0) o.normp[lt] = tot;
+  }
+}
+
+template <int TR, int WN>
+__global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
+                                                   const int* __restrict__ pntiles) {
+  __shared__ double wl[2][kKC * (16 * TR + 2)];
+  __shared__ double red[kPT / 64];
+  const int nops = *pnops, ntiles = *pntiles;
   for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
     const GemmOp& o = ops[find_op(ops, nops, g)];
-    const int lt = g - o.tile0;
-    const int M = o.M, K = o.K, N = o.N;
-    const int m0 = (lt / o.tiles_n) * RT;
-    const int n0t = (lt % o.tiles_n) * CT;
-    const int n0 = n0t + wave * 32 * WN;
-    const double* __restrict__ W = o.W;
-    const double* __restrict__ B = o.B;
-    const int64_t ldw = o.ldw, ldb = o.ldb;
-    const bool wt = o.wt != 0;
-    // 16-byte accesses where the pair is aligned: even leading dimension, aligned base
-    const bool bvec = ((ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
-    int col[S];
-#pragma unroll
-    for (int s2 = 0; s2 < S; ++s2) col[s2] = n0 + 32 * (s2 >> 1) + 2 * lr + (s2 & 1);
-    // depth range: block-triangular operands are zero below kbeg for the whole tile; it
-    // starts at a chunk boundary so the grouping of the sums does not depend on the tile
-    int kbeg = 0;
-    if (o.kskip & 1) kbeg = max(kbeg, m0 - o.kband);
-    if (o.kskip & 2) kbeg = max(kbeg, n0t - o.kband);
-    kbeg = (kbeg / kKC) * kKC;
-    const int nch = kbeg < K ? (K - kbeg + kKC - 1) / kKC : 0;
-
-    doublex4 acc[TR][S];
-#pragma unroll
-    for (int t = 0; t < TR; ++t)
-#pragma unroll
-      for (int s2 = 0; s2 < S; ++s2) acc[t][s2] = doublex4{0.0, 0.0, 0.0, 0.0};
-    constexpr int NJ = kKC / 4;  // MFMA steps per chunk
-    double b[NJ][S];
-    double wr[WPT];
-    auto load_b = [&](int k0) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int k = k0 + 4 * lg + j;
-        const bool kok = k < K;
-        const double* row = B + static_cast<int64_t>(kok ? k : 0) * ldb;
-#pragma unroll
-        for (int p = 0; p < WN; ++p) {
-          const int c0 = col[2 * p];
-          if (bvec && kok && c0 + 1 < N) {
-            const double2 v = *reinterpret_cast<const double2*>(row + c0);
-            b[j][2 * p] = v.x;
-            b[j][2 * p + 1] = v.y;
-          } else {
-            b[j][2 * p] = (kok && c0 < N) ? row[c0] : 0.0;
-            b[j][2 * p + 1] = (kok && c0 + 1 < N) ? row[c0 + 1] : 0.0;
-          }
-        }
-      }
-    };
-    auto load_w = [&](int k0) {
-#pragma unroll
-      for (int q = 0; q < WPT; ++q) {
-        const int e = tid + kPT * q;
-        int row, kk;
-        if (wt) {
-          kk = e / RT;
-          row = e % RT;
-        } else {
-          row = e / kKC;
-          kk = e % kKC;
-        }
-        const int gr = m0 + row, gk = k0 + kk;
-        const bool ok = gr < M && gk < K;
-        wr[q] = ok ? (wt ? W[static_cast<int64_t>(gk) * ldw + gr] : W[static_cast<int64_t>(gr) * ldw + gk]) : 0.0;
-      }
-    };
-    auto store_w = [&](int buf) {
-#pragma unroll
-      for (int q = 0; q < WPT; ++q) {
-        const int e = tid + kPT * q;
-        const int row = wt ? e % RT : e / kKC;
-        const int kk = wt ? e / RT : e % kKC;
-        wl[buf][kk * kStride + row] = wr[q];
-      }
-    };
-    if (nch > 0) {
-      load_w(kbeg);
-      load_b(kbeg);
-    }
-    __syncthreads();  // the previous tile's readers of the LDS buffers are done
-    if (nch > 0) store_w(0);
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-      const int cur = ch & 1;
-      const int k0 = kbeg + ch * kKC;
-      double bc[NJ][S];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-#pragma unroll
-        for (int s2 = 0; s2 < S; ++s2) bc[j][s2] = b[j][s2];
-      const bool more = ch + 1 < nch;
-      if (more) {
-        load_w(k0 + kKC);
-        load_b(k0 + kKC);
-      }
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        double a[NJ];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) a[j] = wl[cur][(4 * lg + j) * kStride + t * 16 + lr];
-#pragma unroll
-        for (int s2 = 0; s2 < S; ++s2)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j)
-            acc[t][s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bc[j][s2], acc[t][s2], 0, 0, 0);
-      }
-      if (more) store_w(cur ^ 1);
-      __syncthreads();
-    }
-    // epilogue: OUT = X + alpha acc, pairs of columns per lane
-    const bool ovec = ((o.ldo & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.OUT) & 15) == 0) &&
-                      (!o.X || (((o.ldx & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.X) & 15) == 0)));
-    double sq = 0.0;
-#pragma unroll
-    for (int t = 0; t < TR; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + t * 16 + 4 * v + lg;
-        if (row >= M) continue;
-        double* orow = o.OUT + static_cast<int64_t>(row) * o.ldo;
-        const double* xrow = o.X ? o.X + static_cast<int64_t>(row) * o.ldx : nullptr;
-#pragma unroll
-        for (int p = 0; p < WN; ++p) {
-          const int c0 = col[2 * p];
-          double y0 = o.alpha * acc[t][2 * p][v];
-          double y1 = o.alpha * acc[t][2 * p + 1][v];
-          if (ovec && c0 + 1 < N) {
-            if (xrow) {
-              const double2 x = *reinterpret_cast<const double2*>(xrow + c0);
-              y0 = x.x + y0;
-              y1 = x.y + y1;
-            }
-            *reinterpret_cast<double2*>(orow + c0) = double2{y0, y1};
-            sq += y0 * y0 + y1 * y1;
-          } else {
-            if (c0 < N) {
-              if (xrow) y0 = xrow[c0] + y0;
-              orow[c0] = y0;
-              sq += y0 * y0;
-            }
-            if (c0 + 1 < N) {
-              if (xrow) y1 = xrow[c0 + 1] + y1;
-              orow[c0 + 1] = y1;
-              sq += y1 * y1;
-            }
-          }
-        }
-      }
-    if (o.normp) {
-      const double tot = block_sum(sq, red);
-      if (tid == 0) o.normp[lt] = tot;
-    }
+    gemm_wg_tile<TR, WN>(o, g - o.tile0, wl, red);
   }
+}
+
+// One product OUT = X + alpha W B (the op passed by value; tiles_n set by the caller),
+// persistent over its tiles.
+template <int TR, int WN>
+__global__ __launch_bounds__(kPT) void gemm_one_kernel(const GemmOp o) {
+  __shared__ double wl[2][kKC * (16 * TR + 2)];
+  __shared__ double red[kPT / 64];
+  const int ntiles = ((o.M + 16 * TR - 1) / (16 * TR)) * o.tiles_n;
+  for (int g = blockIdx.x; g < ntiles; g += gridDim.x) gemm_wg_tile<TR, WN>(o, g, wl, red);
 }
 
 // Persistent FP64 product over a list of ops, one tile of 16 TR rows x 32 WN columns per
@@ -770,6 +787,26 @@ int gemm_stage(const Plan& p, int s, int shape, hipStream_t st) {
   }
 }
 
+// One product on the workgroup tiles of 32 x 128: persistent grid over its tiles.
+int gemm_one(const GemmOp& o, hipStream_t st) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_one_kernel<2, 1>, kPT, 0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    per_cu = std::min(nb, 8);
+  }
+  DeviceInfo dev;
+  ICUR_TRY(device_info(&dev));
+  const int64_t tiles = ((o.M + 31) / 32) * static_cast<int64_t>(o.tiles_n);
+  const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tiles, per_cu * dev.num_cus)));
+  hipLaunchKernelGGL((gemm_one_kernel<2, 1>), dim3(grid), dim3(kPT), 0, st, o);
+  ICUR_HIP(hipGetLastError());
+  return ICUR_OK;
+}
+
 int gather_stage(const Plan& p, int s, int grid, hipStream_t st) {
   hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(kPT), 0, st, p.gather[s], p.nops + s, p.ntiles + s);
   ICUR_HIP(hipGetLastError());
@@ -782,6 +819,31 @@ int gather_stage(const Plan& p, int s, int grid, hipStream_t st) {
 double* batch_plan_bytes_ptr(void* plan_ws, int count) { return bind_plan(plan_ws, count).bytes; }
 
 int batch_plan_stages() { return kNumStages; }
+
+// OUT (M x N, ld ldo) = X + alpha W B (X may be null, or equal to OUT with ldx == ldo), all
+// FP64 row-major, on the FP64 matrix cores (the grouped product's workgroup tile).
+int gemm_f64_native(int64_t M, int64_t N, int64_t K, double alpha, const double* W, int64_t ldw, const double* B,
+                    int64_t ldb, const double* X, int64_t ldx, double* OUT, int64_t ldo, hipStream_t st) {
+  if (M < 0 || N < 0 || K < 0 || M > INT_MAX || N > INT_MAX || K > INT_MAX)
+    return arg_error("native product: sizes out of range");
+  if (M == 0 || N == 0) return ICUR_OK;
+  GemmOp o;
+  std::memset(&o, 0, sizeof(o));
+  o.X = X;
+  o.ldx = ldx;
+  o.W = W;
+  o.ldw = ldw;
+  o.B = B;
+  o.ldb = ldb;
+  o.OUT = OUT;
+  o.ldo = ldo;
+  o.M = static_cast<int>(M);
+  o.K = static_cast<int>(K);
+  o.N = static_cast<int>(N);
+  o.tiles_n = static_cast<int>((N + 127) / 128);
+  o.alpha = alpha;
+  return gemm_one(o, st);
+}
 int batch_plan_final_stage() { return kFin; }
 
 // Shape of each product stage: P1, P2, P3 and FIN as given; P4, whose tiles carry the

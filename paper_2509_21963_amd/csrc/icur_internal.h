@@ -275,6 +275,10 @@ int launch_small_inverse(double* N, int64_t k, double* work, int* info, double* 
 // the diagonal without a pivot search (k <= 128; larger k use launch_small_inverse).
 int launch_inorder_inverse(double* N, int64_t k, double* work, int* info, hipStream_t st);
 size_t small_inverse_work_bytes(int64_t k);
+// OUT (M x N, ld ldo) = X + alpha W B (X may be null, or equal to OUT with ldx == ldo), all
+// FP64 row-major, on the FP64 matrix cores (icur_group_kernels.hip).
+int gemm_f64_native(int64_t M, int64_t N, int64_t K, double alpha, const double* W, int64_t ldw, const double* B,
+                    int64_t ldb, const double* X, int64_t ldx, double* OUT, int64_t ldo, hipStream_t st);
 int dcopy2d(int64_t M, int64_t N, double alpha, const double* src, int64_t lds, double* dst,
             int64_t ldd, hipStream_t st);
 // Grow the core inverse U (ld ldu) from r x r to (r+k) x (r+k) by the block inverse of
@@ -293,6 +297,11 @@ size_t core_update_ws_doubles(int64_t r, int64_t k);
 int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblocks, int64_t bmax, double* U,
                        double* ws, int* info, double* norms, hipStream_t st, const double* D0inv = nullptr);
 size_t core_inverse_ws_doubles(int64_t r, int64_t bmax);
+// Newton steps U <- U + U (I - M U) on the core (M = A(I,J), r x r, ld r): up to three,
+// while max |I - M U| converges (read by the host before each).  ws:
+// core_refine_ws_doubles(r) doubles.
+int core_refine(const double* M, double* U, int64_t r, double* ws, hipStream_t st);
+size_t core_refine_ws_doubles(int64_t r);
 int launch_fill_f64_identity(double* U, int64_t r, hipStream_t st);
 
 }  // namespace icur

@@ -159,6 +159,28 @@ def precision_form_device(m=60000, n=40000, K=4096, seed=0, noise_rel=1e-9, devi
     return A
 
 
+def low_rank_device(m=30000, n=30000, r=2000, seed=0, device="cuda"):
+    """The rank-adaptive Low-Rank matrix of the paper's first experiment (§5.1):
+    A = G1 G2^T with G1 (m x r) and G2 (n x r) standard Gaussian, drawn by the device's
+    own generator (seeded).  The paper's matrix is exactly rank r in FP64; stored in FP32
+    a product of unrounded Gaussians would carry a full-rank rounding term of about 2^-24
+    of its entries, which the cross amplifies past a 1e-6 tolerance at this size.  So the
+    Gaussians are rounded to multiples of 1/8 (each entry's law stays N(0,1) to within that
+    grid): every product entry is then a multiple of 1/64 below 2^18 in magnitude, exact in
+    FP32, and A is exactly rank r as stored."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) * 2 + 104729)
+    G1 = torch.round(8.0 * torch.randn((m, r), generator=gen, dtype=torch.float64, device=device)) / 8.0
+    G2 = torch.round(8.0 * torch.randn((n, r), generator=gen, dtype=torch.float64, device=device)) / 8.0
+    A = torch.empty((m, n), dtype=torch.float32, device=device)
+    for r0 in range(0, m, 4096):
+        r1 = min(m, r0 + 4096)
+        A[r0:r1] = (G1[r0:r1] @ G2.T).float()
+    del G1, G2
+    return A
+
+
 def batch_specs(count=512, seed=0, m_range=(500, 8000), r0_range=(10.0, 400.0),
                 logtol_range=(-6.0, -2.0)):
     """Per-matrix (m, n, r0, tol, K) for the uneven batch: m, n uniform integers,

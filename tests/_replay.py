@@ -98,33 +98,41 @@ def growth(T, piv):
 
 def lupp_steps_with_noise(T, piv, exclude, d0):
     """For each step t of LUPP on T (N x K) with the given pivots: the step-t Schur
-    complements v_i of every eligible candidate (first-order formula, not the replay's
-    elimination) and their noise bounds n_i = d0 (1 + ||x_i||_1) (1 + ||y||_1) with
-    x_i = T(i, 0:t) T(P, 0:t)^{-1}, y = T(P, 0:t)^{-1} T(P, t).  Yields
-    (eligible indices, |v|, n) per step."""
+    complements v_i of every eligible candidate and their noise bounds
+    n_i = d0 (1 + ||x_i||_1) (1 + ||y||_1) with x_i = T(i, 0:t) T(P, 0:t)^{-1},
+    y = T(P, 0:t)^{-1} T(P, t).  Yields (eligible indices, |v|, n) per step.
+
+    v comes from right-looking elimination along the given pivots (rounding near
+    t 2^-52 max|T|, whatever the conditioning of T(P, 0:t)); x and y, which only size the
+    noise, come from solves with T(P, 0:t)."""
     T = np.asarray(T, dtype=np.float64)
     N = T.shape[0]
     elig = np.ones(N, dtype=bool)
     ex = np.asarray(list(exclude), dtype=np.int64)
     if ex.size:
         elig[ex] = False
+    S = T.copy()  # Schur complements, columns t.. current
     P = []
     for t in range(len(piv)):
         if t == 0:
-            v = T[:, 0].copy()
             xn = np.zeros(N)
             yn = 0.0
         else:
             B = T[np.ix_(P, list(range(t)))]
-            Binv = np.linalg.inv(B)
-            y = Binv @ T[P, t]
-            X = T[:, :t] @ Binv
-            v = T[:, t] - X @ T[P, t]
+            try:
+                y = np.linalg.solve(B, T[P, t])
+                X = np.linalg.solve(B.T, T[:, :t].T).T
+            except np.linalg.LinAlgError:
+                y = np.full(t, np.inf)
+                X = np.full((N, t), np.inf)
             xn = np.abs(X).sum(axis=1)
             yn = float(np.abs(y).sum())
         idx = np.nonzero(elig)[0]
-        yield idx, np.abs(v[idx]), d0 * (1.0 + xn[idx]) * (1.0 + yn)
+        yield idx, np.abs(S[idx, t]), d0 * (1.0 + xn[idx]) * (1.0 + yn)
         p = int(piv[t])
+        if t + 1 < S.shape[1] and S[p, t] != 0.0:
+            f = S[:, t] / S[p, t]
+            S[:, t + 1:] -= np.outer(f, S[p, t + 1:])
         elig[p] = False
         P.append(p)
 

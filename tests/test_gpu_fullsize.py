@@ -165,3 +165,40 @@ def test_csr_200000x100000_full_size(icur):
     AS = A[S].toarray()
     E = AS - (A[S][:, J].toarray() @ U) @ R
     assert np.linalg.norm(E) <= 2 * tol * np.linalg.norm(AS)
+
+
+def test_low_rank_30000_rank_2000(icur):
+    # the paper's rank-adaptive Low-Rank matrix A = G1 G2^T (G_i 30000 x 2000 Gaussian),
+    # tol 1e-6, b = 250: exactly rank 2000 up to its FP32 rounding, so the loop must stop
+    # at rank 2000 after 8 blocks with the estimate and the exact error far below tol.
+    # The oracle's full run is checked through the first blocks (LUPP replays on the
+    # oracle's X0 = G A and on A(:, J_1)) and the exact error on 1000 sampled rows.
+    from oracle.rng import make_G
+    m = n = 30000
+    rk, b, tol = 2000, 250, 1e-6
+    A = W.low_rank_device(m, n, rk, seed=0)
+    torch.cuda.synchronize()
+    got = icur.run(A, tol, b, icur.GAUSSIAN, seed=0)
+    A64 = A.cpu().numpy().astype(np.float64)
+    del A
+    torch.cuda.empty_cache()
+    I, J, U = got["I"].tolist(), got["J"].tolist(), got["U"]
+    assert got["status"] == "ok" and got["rank"] == rk and got["info"]["iterations"] == rk // b
+    assert got["rho"] <= tol and len(set(I)) == rk and len(set(J)) == rk
+    X0 = make_G(0, (11 * b) // 10, m, 0) @ A64
+    noise = sketch_eta(3, 32) * np.abs(X0).max()
+    pinned = [0, 0]
+    for side, recs, nz in ((0, lupp_replay(X0.T, J[:b]), noise),
+                           (1, lupp_replay(A64[:, J[:b]], I[:b]), 4 * 2.0 ** -52 * np.abs(A64).max())):
+        for rec in recs:
+            lim = rec["best_value"] - 2 * nz
+            assert rec["value"] >= lim, (side, rec)
+            pinned[side] += rec["second_value"] < lim
+    print("first-block pivots pinned (columns, rows):", pinned)
+    assert pinned[0] > 0 and pinned[1] > 0
+    S = np.random.default_rng(1).choice(m, 1000, replace=False)
+    R = U @ A64[I, :]
+    AS = A64[S]
+    err = np.linalg.norm(AS - AS[:, J] @ R) / np.linalg.norm(AS)
+    print("sampled relative error %.3e, rho %.3e" % (err, got["rho"]))
+    assert err <= tol

@@ -188,6 +188,18 @@ def test_dense_sketch_runs_on_the_sketch_kernel(icur):
     assert icur.last_info()["sketch_kernel"] == 3
 
 
+@pytest.mark.parametrize("b", [129, 250, 512])
+def test_large_blocks_blocked_pivot_inverse(icur, b):
+    # blocks above 128 invert their pivot blocks (and the core's diagonal blocks) by 2 x 2
+    # block elimination over 128-wide in-order Gauss-Jordan tiles: every pivot replayed,
+    # and U against the oracle's pseudo-inverse of the cross (check_against_oracle)
+    A, _ = W.planted_geometric(1800, 1400, 45.0, seed=11)
+    A32, _ = W.to_f32(A)
+    got, ora, err = check_against_oracle(icur, A32, 1e-6, b, 0, 5)
+    assert got["status"] == "ok" and got["rank"] >= b
+    assert err <= 2e-6 and got["rho"] <= 1e-6
+
+
 def test_schur_zeros_of_the_result(icur):
     A32, _ = W.to_f32(W.rbf(900, 700, 2))
     got = icur.run(torch.from_numpy(A32).cuda(), 1e-5, 16, 0, 7)
