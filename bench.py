@@ -11,8 +11,9 @@ resident in HBM.  Beside it, in the same line:
   precision_form        the 60000 x 40000 precision-form matrix (block 128, Gaussian
                         sketch) at tol 1e-3 and 1e-5, BF16-split against plain FP32.
   roofline              the grouped FP64 product kernel of the batched loop (the kernel
-                        with the most device time), algorithmic bytes over its duration
-                        from device events inside the timed calls, against HBM;
+                        with the most device time: its P1-P3 launches), algorithmic bytes
+                        over its duration from device events inside the timed calls,
+                        against HBM;
   cpu_baseline          the FP64 NumPy oracle on randomly drawn matrices of the batch
                         (about 20 s of host time), scaled by count / drawn.
 Other workloads (--workload): rbf (40000 x 40000 RBF kernel, tol 1e-4, block 100,
@@ -172,10 +173,14 @@ def bench_batched(a):
     same_idx = sum(1 for g, p in zip(got, plain) if np.array_equal(g["I"], p["I"]) and np.array_equal(g["J"], p["J"]))
     value = statistics.median(tb)
     inf = infos[-1]
-    # roofline of the grouped FP64 product kernel: algorithmic bytes over its device time
-    # (events around every product launch of the timed call)
-    prod_ms = statistics.mean(i["ms_products"] for i in infos)
-    prod_bytes = statistics.mean(i["product_bytes"] for i in infos)
+    # roofline of the loop's large FP64 products (stages P1-P3: the row residual, the
+    # new-row residual with the (Q^-1)^T block row, the row factors with the P^-1 block
+    # row; one gemm_kernel launch each per iteration): algorithmic bytes over their device
+    # time, from events around every launch of the timed calls
+    shapes = ["16x128", "32x128", "48x128", "64x128", "32x256", "64x256", "w32x32", "w16x64", "w32x64"]
+    prod_ms = statistics.mean(sum(i["ms_stage"][:3]) for i in infos)
+    prod_bytes = statistics.mean(sum(i["stage_bytes"][:3]) for i in infos)
+    launches = 3 * inf["group_iterations"]
     achieved = prod_bytes / (prod_ms * 1e-3) / 1e9 if prod_ms > 0 else None
     line = {
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -194,14 +199,18 @@ def bench_batched(a):
             "select_ms": inf["ms_select"], "products_ms": inf["ms_products"],
             "buffer_setup_ms": inf["ms_setup"], "iterations_host_ms": inf["ms_residual"],
             "core_products_ms": inf["ms_core"], "results_copy_ms": inf["ms_results"],
+            "stage_ms": dict(zip(("P1", "P2", "P3", "P4", "FIN"), inf["ms_stage"])),
+            "stage_gbytes": dict(zip(("P1", "P2", "P3", "P4", "FIN"), [x / 1e9 for x in inf["stage_bytes"]])),
+            "tiles": dict(zip(("P1", "P2", "P3", "FIN"), [shapes[t] for t in inf["tiles"]])),
         },
         "roofline": {
-            "kernel": "grouped FP64 product kernel of the batched loop (gemm_kernel: residual-form products and "
-                      "the bordered core, %d launches per call)" % inf["product_launches"],
+            "kernel": "grouped FP64 product kernel of the batched loop, stages P1-P3 (gemm_kernel<%s>: row "
+                      "residual, new-row residual and the two inverses' block rows; %d launches per call)"
+                      % (shapes[inf["tiles"][0]], launches),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-            "avg_ms": prod_ms / max(inf["product_launches"], 1),
-            "algorithmic_bytes": prod_bytes / max(inf["product_launches"], 1),
+            "avg_ms": prod_ms / max(launches, 1),
+            "algorithmic_bytes": prod_bytes / max(launches, 1),
         },
     }
     cpu = None

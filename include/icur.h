@@ -136,6 +136,9 @@ typedef struct icur_info {
   int32_t residual_terms;     /* BF16 pieces per operand of the residual products: -1 for
                                  FP64 factors, 0 for FP32 factors on the FP32 matrix cores,
                                  2 or 3 in the precision form */
+  double  stage_bytes[5];     /* grouped batched call: algorithmic bytes of the product stages
+                                 of ms_stage (nonzero operand parts read once, output written
+                                 once) */
 } icur_info;
 
 /*

@@ -960,13 +960,17 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     else
       ICUR_TRY(launch_gather_f64(A, lda, static_cast<const int64_t*>(pIall), r, static_cast<const int64_t*>(pJall), r,
                                  false, M, r, st));
-    // the cross is kept for one refinement step of the block-LU inverse
-    void* pRef;
-    ICUR_TRY(ensure(dc, kCoreRef, (static_cast<size_t>(r) * r + core_refine_ws_doubles(r)) * 8, &pRef));
-    double* M0 = static_cast<double*>(pRef);
-    ICUR_TRY(dcopy2d(r, r, 1.0, M, r, M0, r, st));
+    // with more than one block the cross is kept for the refinement of the block-LU
+    // inverse (one block is the pivot block's in-order inverse: LU with partial pivoting)
+    double* M0 = nullptr;
+    if (nb > 1) {
+      void* pRef;
+      ICUR_TRY(ensure(dc, kCoreRef, (static_cast<size_t>(r) * r + core_refine_ws_doubles(r)) * 8, &pRef));
+      M0 = static_cast<double*>(pRef);
+      ICUR_TRY(dcopy2d(r, r, 1.0, M, r, M0, r, st));
+    }
     ICUR_TRY(core_block_inverse(M, r, blocks.data(), nb, b, U, static_cast<double*>(pCore), infos, nullptr, st, N1inv));
-    ICUR_TRY(core_refine(M0, U, r, M0 + static_cast<size_t>(r) * r, st));
+    if (M0) ICUR_TRY(core_refine(M0, U, r, 1e-2 * tol, M0 + static_cast<size_t>(r) * r, st));
     ICUR_TRY(tm.mark(&ec1));
     // the pivot-block flags and the results: through the pinned staging area in one
     // synchronisation when they fit, else the flags first and the results directly
@@ -1218,6 +1222,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   t_info.ms_results = gstat.ms_results;
   t_info.sketch_kernel = gstat.sketch_kernel;
   for (int q = 0; q < 5; ++q) t_info.ms_stage[q] = gstat.ms_stage[q];
+  for (int q = 0; q < 5; ++q) t_info.stage_bytes[q] = gstat.stage_bytes[q];
   for (int q = 0; q < 4; ++q) t_info.tiles[q] = gstat.tiles[q];
   t_info.iterations = static_cast<int32_t>(std::min<int64_t>(total_iters, INT32_MAX));
   t_info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -146,6 +146,8 @@ struct BatchedCall {
   double ms_loop;         // out: host clock of the grouped iterations
   double ms_final;        // out: device time of the closing core products Q^{-1} P^{-1}
   double ms_stage[5];     // out: device time of the product stages P1, P2, P3, P4, FIN
+  double stage_bytes[5];  // out: their algorithmic bytes (nonzero operand parts read once,
+                          // output written once)
   int tiles[4];           // out: tile shapes used for P1, P2, P3, FIN
   int sketch_kernel;      // out: matrices whose G A ran on the dedicated sketch kernel
   double ms_results;      // out: host clock of the copies to the caller's pools

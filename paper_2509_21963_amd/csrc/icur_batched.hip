@@ -42,6 +42,7 @@ size_t batch_plan_bytes(int count);
 double* batch_plan_bytes_ptr(void* plan_ws, int count);
 int batch_plan_stages();
 int batch_plan_final_stage();
+std::vector<int> batch_plan_product_stages();
 
 namespace {
 
@@ -746,6 +747,10 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   a.product_bytes = 0.0;
   for (int q = 0; q < batch_plan_stages(); ++q)
     if (q != batch_plan_final_stage()) a.product_bytes += stage_bytes[q];
+  {
+    int k = 0;
+    for (int q : batch_plan_product_stages()) a.stage_bytes[k++] = stage_bytes[q];
+  }
   a.ms_results = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_res0).count();
   return ICUR_OK;
 }

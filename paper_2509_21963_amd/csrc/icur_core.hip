@@ -676,10 +676,10 @@ int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblo
 // inverse can carry far more error than a fully pivoted one (the CUR error with it can
 // exceed the tolerance while A(I,J)^+ meets it).  The residual R = I - M U squares with
 // every step, down to its own rounding (near cond 2^-52).  Up to three steps, each taken
-// only while max |R| is below 1/2 (convergence), above 2^-40 (still worth a step) and at
-// most half the previous one (still shrinking); the host reads max |R| before each.
-// ws: 2 r^2 + 1 doubles.
-int core_refine(const double* M, double* U, int64_t r, double* ws, hipStream_t st) {
+// only while max |R| is below 1/2 (convergence), above `floor` (still worth a step: the
+// CUR error it can add is about max |R| relative) and at most half the previous one
+// (still shrinking); the host reads max |R| before each.  ws: 2 r^2 + 1 doubles.
+int core_refine(const double* M, double* U, int64_t r, double floor, double* ws, hipStream_t st) {
   if (r <= 0) return ICUR_OK;
   double* R = ws;
   double* T = ws + r * r;
@@ -698,7 +698,7 @@ int core_refine(const double* M, double* U, int64_t r, double* ws, hipStream_t s
     ICUR_HIP(hipStreamSynchronize(st));
     double v;
     std::memcpy(&v, &bits, sizeof(v));
-    if (!(v < 0.5) || v <= 0x1.0p-40 || v > 0.5 * prev) break;
+    if (!(v < 0.5) || v <= floor || v > 0.5 * prev) break;
     prev = v;
     ICUR_TRY(dgemm(r, r, r, 1.0, U, r, 1, R, r, 1, 0.0, T, r, st));
     hipLaunchKernelGGL(refine_apply_kernel, dim3(blocks), dim3(256), 0, st, U, T, total, rmax);

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <vector>
 
 #include "icur_batched.h"
 #include "icur_gj.h"
@@ -495,7 +496,9 @@ __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*w
   }
 }
 
-template <int TR, int WN>
+// ROLE only names the instance (0: the loop's products, 1: the closing core products), so
+// that a kernel trace tells the two apart.
+template <int TR, int WN, int ROLE = 0>
 __global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
                                                    const int* __restrict__ pntiles) {
   __shared__ double wl[2][kKC * (16 * TR + 2)];
@@ -522,7 +525,7 @@ __global__ __launch_bounds__(kPT) void gemm_one_kernel(const GemmOp o) {
 // next chunk's while the current one is multiplied), no LDS and no barrier.  Lane (lr, lg)
 // and the k order as in gemm_kernel; its four W entries of a step are contiguous in a row
 // of W (one 32-byte read).  Ops with norm partials are not taken (gemm_kernel does those).
-template <int TR, int WN>
+template <int TR, int WN, int ROLE = 0>
 __global__ __launch_bounds__(kPT) void gemm_wave_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
                                                         const int* __restrict__ pntiles) {
   constexpr int RT = 16 * TR;
@@ -771,20 +774,25 @@ int gemm_launch(KERNEL kernel, int* per_cu, const Plan& p, int s, hipStream_t st
   return ICUR_OK;
 }
 
-int gemm_stage(const Plan& p, int s, int shape, hipStream_t st) {
+template <int ROLE>
+int gemm_stage_role(const Plan& p, int s, int shape, hipStream_t st) {
   static int per_cu[kGemmShapes] = {};
   switch (shape) {
-    case 0: return gemm_launch(gemm_kernel<1, 1>, &per_cu[0], p, s, st);
-    case 1: return gemm_launch(gemm_kernel<2, 1>, &per_cu[1], p, s, st);
-    case 2: return gemm_launch(gemm_kernel<3, 1>, &per_cu[2], p, s, st);
-    case 3: return gemm_launch(gemm_kernel<4, 1>, &per_cu[3], p, s, st);
-    case 4: return gemm_launch(gemm_kernel<2, 2>, &per_cu[4], p, s, st);
-    case 5: return gemm_launch(gemm_kernel<4, 2>, &per_cu[5], p, s, st);
-    case 6: return gemm_launch(gemm_wave_kernel<2, 1>, &per_cu[6], p, s, st);
-    case 7: return gemm_launch(gemm_wave_kernel<1, 2>, &per_cu[7], p, s, st);
-    case 8: return gemm_launch(gemm_wave_kernel<2, 2>, &per_cu[8], p, s, st);
+    case 0: return gemm_launch(gemm_kernel<1, 1, ROLE>, &per_cu[0], p, s, st);
+    case 1: return gemm_launch(gemm_kernel<2, 1, ROLE>, &per_cu[1], p, s, st);
+    case 2: return gemm_launch(gemm_kernel<3, 1, ROLE>, &per_cu[2], p, s, st);
+    case 3: return gemm_launch(gemm_kernel<4, 1, ROLE>, &per_cu[3], p, s, st);
+    case 4: return gemm_launch(gemm_kernel<2, 2, ROLE>, &per_cu[4], p, s, st);
+    case 5: return gemm_launch(gemm_kernel<4, 2, ROLE>, &per_cu[5], p, s, st);
+    case 6: return gemm_launch(gemm_wave_kernel<2, 1, ROLE>, &per_cu[6], p, s, st);
+    case 7: return gemm_launch(gemm_wave_kernel<1, 2, ROLE>, &per_cu[7], p, s, st);
+    case 8: return gemm_launch(gemm_wave_kernel<2, 2, ROLE>, &per_cu[8], p, s, st);
     default: return arg_error("grouped product: unknown tile shape");
   }
+}
+
+int gemm_stage(const Plan& p, int s, int shape, hipStream_t st) {
+  return s == kFin ? gemm_stage_role<1>(p, s, shape, st) : gemm_stage_role<0>(p, s, shape, st);
 }
 
 // One product on the workgroup tiles of 32 x 128: persistent grid over its tiles.
@@ -845,6 +853,7 @@ int gemm_f64_native(int64_t M, int64_t N, int64_t K, double alpha, const double*
   return gemm_one(o, st);
 }
 int batch_plan_final_stage() { return kFin; }
+std::vector<int> batch_plan_product_stages() { return {kP1, kP2, kP3, kP4, kFin}; }
 
 // Shape of each product stage: P1, P2, P3 and FIN as given; P4, whose tiles carry the
 // norm partials, always the one that fits c rows (so rho does not depend on the tuning).

@@ -298,9 +298,9 @@ int core_block_inverse(double* M, int64_t r, const int64_t* blocks, int64_t nblo
                        double* ws, int* info, double* norms, hipStream_t st, const double* D0inv = nullptr);
 size_t core_inverse_ws_doubles(int64_t r, int64_t bmax);
 // Newton steps U <- U + U (I - M U) on the core (M = A(I,J), r x r, ld r): up to three,
-// while max |I - M U| converges (read by the host before each).  ws:
+// while max |I - M U| converges and exceeds floor (read by the host before each).  ws:
 // core_refine_ws_doubles(r) doubles.
-int core_refine(const double* M, double* U, int64_t r, double* ws, hipStream_t st);
+int core_refine(const double* M, double* U, int64_t r, double floor, double* ws, hipStream_t st);
 size_t core_refine_ws_doubles(int64_t r);
 int launch_fill_f64_identity(double* U, int64_t r, hipStream_t st);
 

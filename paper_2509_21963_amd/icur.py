@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
                 ("product_launches", ctypes.c_int32), ("group_iterations", ctypes.c_int32),
                 ("ms_setup", ctypes.c_double), ("ms_results", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 5), ("tiles", ctypes.c_int32 * 4),
-                ("sketch_kernel", ctypes.c_int32), ("residual_terms", ctypes.c_int32)]
+                ("sketch_kernel", ctypes.c_int32), ("residual_terms", ctypes.c_int32),
+                ("stage_bytes", ctypes.c_double * 5)]
 
 
 _lib = None
@@ -241,8 +242,9 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
 def last_info():
     info = Info()
     load().icur_last_info(ctypes.byref(info))
-    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "block_sizes", "ms_stage", "tiles")}
+    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "block_sizes", "ms_stage", "tiles", "stage_bytes")}
     d["ms_stage"] = list(info.ms_stage)
+    d["stage_bytes"] = list(info.stage_bytes)
     d["tiles"] = list(info.tiles)
     d["rho"] = list(info.rho[:info.n_rho])
     d["block_sizes"] = list(info.block_sizes[:info.n_rho])

@@ -45,7 +45,7 @@ def test_struct_layouts_match_header():
     # icur_opts: 2 x int32, int64, pointer, 2 x double, 6 x int32
     assert ctypes.sizeof(icur.Opts) == 64
     # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles, 512 x int32, 2 doubles, 2 x int32
-    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8 + 512 * 4 + 16 + 8 + 16 + 40 + 16 + 8
+    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8 + 512 * 4 + 16 + 8 + 16 + 40 + 16 + 8 + 40
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation precedes device work
