@@ -177,7 +177,8 @@ def bench_batched(a):
     # new-row residual with the (Q^-1)^T block row, the row factors with the P^-1 block
     # row; one gemm_kernel launch each per iteration): algorithmic bytes over their device
     # time, from events around every launch of the timed calls
-    shapes = ["16x128", "32x128", "48x128", "64x128", "32x256", "64x256", "w32x32", "w16x64", "w32x64"]
+    shapes = ["16x128", "32x128", "48x128", "64x128", "32x256", "64x256", "w32x32", "w16x64", "w32x64",
+              "32x128/2", "64x128/2", "32x128/3"]
     prod_ms = statistics.mean(sum(i["ms_stage"][:3]) for i in infos)
     prod_bytes = statistics.mean(sum(i["stage_bytes"][:3]) for i in infos)
     launches = 3 * inf["group_iterations"]

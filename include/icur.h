@@ -129,7 +129,8 @@ typedef struct icur_info {
                                  (P3), column update (P4), core products (FIN) */
   int32_t tiles[4];           /* tile shapes used for P1, P2, P3, FIN (0..5: workgroup tiles
                                  16x128, 32x128, 48x128, 64x128, 32x256, 64x256; 6..8: wave
-                                 tiles 32x32, 16x64, 32x64) */
+                                 tiles 32x32, 16x64, 32x64; 9..11: workgroup tiles with more
+                                 chunks in flight, 32x128 (2), 64x128 (2), 32x128 (3)) */
   int32_t sketch_kernel;      /* 1 when G A ran on the dedicated sketch kernel, 0 when on the
                                  general product (SRTT, FP32 matrix cores, shapes outside
                                  the kernel's fast path); batched: the count of matrices */

@@ -21,7 +21,8 @@ import os
 import sys
 import time
 
-SHAPES = ["16x128", "32x128", "48x128", "64x128", "32x256", "64x256", "w32x32", "w16x64", "w32x64"]
+SHAPES = ["16x128", "32x128", "48x128", "64x128", "32x256", "64x256", "w32x32", "w16x64", "w32x64",
+          "32x128/2", "64x128/2", "32x128/3"]
 STAGES = ["p1", "p2", "p3", "p4", "fin"]
 
 

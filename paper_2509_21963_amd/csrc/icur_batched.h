@@ -15,9 +15,10 @@ constexpr int kGMaxN = 8192;     // candidates per selection (one workgroup hold
 constexpr int kGMaxSteps = 64;   // pivots per selection (so block <= 64, c <= 70)
 
 // ----- the grouped FP64 product
-constexpr int kGemmShapes = 9;     // tile shapes (rows x columns): workgroup tiles 16x128,
+constexpr int kGemmShapes = 12;    // tile shapes (rows x columns): workgroup tiles 16x128,
                                    // 32x128, 48x128, 64x128, 32x256, 64x256; wave tiles
-                                   // 32x32, 16x64, 32x64
+                                   // 32x32, 16x64, 32x64; workgroup tiles with two or three
+                                   // chunks in flight 32x128/2, 64x128/2, 32x128/3
 constexpr int kGemmMaxCols = 256;  // widest tile
 constexpr int kGemmKChunk = 16;    // depth chunk; chunks start at multiples of it, so an
                                    // element's sum does not depend on the tile shape
@@ -99,7 +100,7 @@ int launch_batch_lupp(BatchMat* mats_dev, int count, bool rows, double rel_cut, 
 // block P3, and the core products FIN.  The column update's shape follows c.  Every
 // choice gives the same results: only the speed differs.
 struct GemmTiles {
-  int p1 = 1, p2 = 1, p3 = 1, fin = 1;
+  int p1 = 9, p2 = 9, p3 = 9, fin = 9;
 };
 
 // The tile shapes for block size b: defaults, the tune file's entry for b, and the

@@ -242,7 +242,8 @@ class ResultCopier {
 }  // namespace
 
 // ---- tile shapes of the grouped products
-// Defaults: row tiles that hold a block (P1 - P3), 32 x 128 for the core products.  A tune
+// Defaults: row tiles that hold a block (P1 - P3), 32 x 128 with two chunks in flight for
+// the core products.  A tune
 // file written by the package's autotuner (measured per stage on the device) overrides
 // them for the block sizes it lists; ICUR_BATCH_TILES="p1,p2,p3,fin" overrides both (the
 // autotuner's own runs use it).  The file is ICUR_TUNE_FILE, else tune_gfx950.json beside
@@ -297,9 +298,11 @@ int json_int(const std::string& text, size_t from, size_t to, const std::string&
 
 GemmTiles batch_tiles(int b) {
   GemmTiles t;
-  const int rows = b <= 16 ? 0 : b <= 32 ? 1 : b <= 48 ? 2 : 3;
+  // a block of up to 32 rows: 32 x 128 tiles with two chunks in flight; else the tile
+  // that holds the block
+  const int rows = b <= 16 ? 0 : b <= 32 ? 9 : b <= 48 ? 2 : 10;
   t.p1 = t.p2 = t.p3 = rows;
-  t.fin = 1;
+  t.fin = 9;
   // tune file: "batched_tiles": { "<b>": {"p1": .., "p2": .., "p3": .., "fin": ..}, ... }
   const std::string& txt = tune_text();
   const size_t sec = txt.find("\"batched_tiles\"");

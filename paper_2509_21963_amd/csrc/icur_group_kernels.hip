@@ -71,11 +71,13 @@ constexpr int kOpsPerMat = 4;
 // (wave = 0): rows 16 TR, columns 128 WN, four waves of 32 WN columns sharing W through
 // LDS.  Wave tiles (wave = 1): rows 16 TR, columns 32 WN, each wave on its own tile with
 // W and B straight to registers (no LDS, no barrier).
+// pd: chunks in flight ahead of the one being multiplied (workgroup tiles).
 struct TileShape {
-  int tr, wn, wave;
+  int tr, wn, wave, pd;
 };
-constexpr TileShape kShapes[kGemmShapes] = {{1, 1, 0}, {2, 1, 0}, {3, 1, 0}, {4, 1, 0}, {2, 2, 0},
-                                            {4, 2, 0}, {2, 1, 1}, {1, 2, 1}, {2, 2, 1}};
+constexpr TileShape kShapes[kGemmShapes] = {{1, 1, 0, 1}, {2, 1, 0, 1}, {3, 1, 0, 1}, {4, 1, 0, 1},
+                                            {2, 2, 0, 1}, {4, 2, 0, 1}, {2, 1, 1, 1}, {1, 2, 1, 1},
+                                            {2, 2, 1, 1}, {2, 1, 0, 2}, {4, 1, 0, 2}, {2, 1, 0, 3}};
 
 struct Plan {
   GemmOp* gemm[kNumStages];
@@ -330,7 +332,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // chunk are loaded into registers while the current one is multiplied, W through two LDS
 // buffers (one barrier per chunk).  gemm_wg_tile is one tile; gemm_kernel walks a list of
 // ops (persistent), gemm_one_kernel the tiles of one op.
-template <int TR, int WN>
+template <int TR, int WN, int PD = 1>
 __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*wl)[kKC * (16 * TR + 2)],
                                              double* red) {
   constexpr int RT = 16 * TR;          // tile rows
@@ -369,9 +371,10 @@ __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*w
 #pragma unroll
     for (int s2 = 0; s2 < S; ++s2) acc[t][s2] = doublex4{0.0, 0.0, 0.0, 0.0};
   constexpr int NJ = kKC / 4;  // MFMA steps per chunk
-  double b[NJ][S];
-  double wr[WPT];
-  auto load_b = [&](int k0) {
+  constexpr int NS = PD + 1;   // register slots: the chunk being multiplied and PD in flight
+  double b[NS][NJ][S];
+  double wr[NS][WPT];
+  auto load_b = [&](double (&bb)[NJ][S], int k0) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int k = k0 + 4 * lg + j;
@@ -382,16 +385,16 @@ __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*w
         const int c0 = col[2 * p];
         if (bvec && kok && c0 + 1 < N) {
           const double2 v = *reinterpret_cast<const double2*>(row + c0);
-          b[j][2 * p] = v.x;
-          b[j][2 * p + 1] = v.y;
+          bb[j][2 * p] = v.x;
+          bb[j][2 * p + 1] = v.y;
         } else {
-          b[j][2 * p] = (kok && c0 < N) ? row[c0] : 0.0;
-          b[j][2 * p + 1] = (kok && c0 + 1 < N) ? row[c0 + 1] : 0.0;
+          bb[j][2 * p] = (kok && c0 < N) ? row[c0] : 0.0;
+          bb[j][2 * p + 1] = (kok && c0 + 1 < N) ? row[c0 + 1] : 0.0;
         }
       }
     }
   };
-  auto load_w = [&](int k0) {
+  auto load_w = [&](double (&ww)[WPT], int k0) {
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
       const int e = tid + kPT * q;
@@ -405,51 +408,58 @@ __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*w
       }
       const int gr = m0 + row, gk = k0 + kk;
       const bool ok = gr < M && gk < K;
-      wr[q] = ok ? (wt ? W[static_cast<int64_t>(gk) * ldw + gr] : W[static_cast<int64_t>(gr) * ldw + gk]) : 0.0;
+      ww[q] = ok ? (wt ? W[static_cast<int64_t>(gk) * ldw + gr] : W[static_cast<int64_t>(gr) * ldw + gk]) : 0.0;
     }
   };
-  auto store_w = [&](int buf) {
+  auto store_w = [&](const double (&ww)[WPT], int buf) {
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
       const int e = tid + kPT * q;
       const int row = wt ? e % RT : e / kKC;
       const int kk = wt ? e / RT : e % kKC;
-      wl[buf][kk * kStride + row] = wr[q];
+      wl[buf][kk * kStride + row] = ww[q];
     }
   };
-  if (nch > 0) {
-    load_w(kbeg);
-    load_b(kbeg);
-  }
-  __syncthreads();  // the previous tile's readers of the LDS buffers are done
-  if (nch > 0) store_w(0);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int cur = ch & 1;
-    const int k0 = kbeg + ch * kKC;
-    double bc[NJ][S];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-      for (int s2 = 0; s2 < S; ++s2) bc[j][s2] = b[j][s2];
-    const bool more = ch + 1 < nch;
-    if (more) {
-      load_w(k0 + kKC);
-      load_b(k0 + kKC);
-    }
+  auto multiply = [&](const double (&bb)[NJ][S], int buf) {
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
       double a[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) a[j] = wl[cur][(4 * lg + j) * kStride + t * 16 + lr];
+      for (int j = 0; j < NJ; ++j) a[j] = wl[buf][(4 * lg + j) * kStride + t * 16 + lr];
 #pragma unroll
       for (int s2 = 0; s2 < S; ++s2)
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
-          acc[t][s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bc[j][s2], acc[t][s2], 0, 0, 0);
+          acc[t][s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], bb[j][s2], acc[t][s2], 0, 0, 0);
     }
-    if (more) store_w(cur ^ 1);
-    __syncthreads();
+  };
+  // prologue: chunks 0 .. PD-1 into register slots 0 .. PD-1, chunk 0's W into LDS
+  gj_static_for<PD>([&](auto q_) __attribute__((always_inline)) {
+    constexpr int q = decltype(q_)::value;
+    if (q < nch) {
+      load_w(wr[q], kbeg + q * kKC);
+      load_b(b[q], kbeg + q * kKC);
+    }
+  });
+  __syncthreads();  // the previous tile's readers of the LDS buffers are done
+  if (nch > 0) store_w(wr[0], 0);
+  __syncthreads();
+  // chunk ch sits in slot ch % NS; the loop is unrolled by NS so every slot index is static
+  for (int base = 0; base < nch; base += NS) {
+    gj_static_for<NS>([&](auto s_) __attribute__((always_inline)) {
+      constexpr int sl = decltype(s_)::value;
+      const int ch = base + sl;
+      if (ch >= nch) return;  // uniform over the workgroup
+      constexpr int ahead = (sl + PD) % NS;
+      constexpr int next = (sl + 1) % NS;
+      if (ch + PD < nch) {
+        load_w(wr[ahead], kbeg + (ch + PD) * kKC);
+        load_b(b[ahead], kbeg + (ch + PD) * kKC);
+      }
+      multiply(b[sl], ch & 1);
+      if (ch + 1 < nch) store_w(wr[next], (ch + 1) & 1);
+      __syncthreads();
+    });
   }
   // epilogue: OUT = X + alpha acc, pairs of columns per lane
   const bool ovec = ((o.ldo & 1) == 0) && ((reinterpret_cast<uintptr_t>(o.OUT) & 15) == 0) &&
@@ -498,7 +508,7 @@ __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*w
 
 // ROLE only names the instance (0: the loop's products, 1: the closing core products), so
 // that a kernel trace tells the two apart.
-template <int TR, int WN, int ROLE = 0>
+template <int TR, int WN, int ROLE = 0, int PD = 1>
 __global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
                                                    const int* __restrict__ pntiles) {
   __shared__ double wl[2][kKC * (16 * TR + 2)];
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ op
   const int nops = *pnops, ntiles = *pntiles;
   for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
     const GemmOp& o = ops[find_op(ops, nops, g)];
-    gemm_wg_tile<TR, WN>(o, g - o.tile0, wl, red);
+    gemm_wg_tile<TR, WN, PD>(o, g - o.tile0, wl, red);
   }
 }
 
@@ -787,6 +797,9 @@ int gemm_stage_role(const Plan& p, int s, int shape, hipStream_t st) {
     case 6: return gemm_launch(gemm_wave_kernel<2, 1, ROLE>, &per_cu[6], p, s, st);
     case 7: return gemm_launch(gemm_wave_kernel<1, 2, ROLE>, &per_cu[7], p, s, st);
     case 8: return gemm_launch(gemm_wave_kernel<2, 2, ROLE>, &per_cu[8], p, s, st);
+    case 9: return gemm_launch(gemm_kernel<2, 1, ROLE, 2>, &per_cu[9], p, s, st);
+    case 10: return gemm_launch(gemm_kernel<4, 1, ROLE, 2>, &per_cu[10], p, s, st);
+    case 11: return gemm_launch(gemm_kernel<2, 1, ROLE, 3>, &per_cu[11], p, s, st);
     default: return arg_error("grouped product: unknown tile shape");
   }
 }

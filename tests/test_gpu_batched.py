@@ -155,7 +155,7 @@ def test_tile_shapes_give_identical_results(icur, monkeypatch):
     dev = [torch.from_numpy(A).cuda() for A in mats]
     tols = [sp["tol"] for sp in specs]
     ref = None
-    for v in range(9):
+    for v in range(12):
         monkeypatch.setenv("ICUR_BATCH_TILES", "%d,%d,%d,%d" % (v, v, v, v))
         got = icur.run_batched(dev, tols, 32, icur.GAUSSIAN)
         assert icur.last_info()["tiles"] == [v, v, v, v]
