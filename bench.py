@@ -94,13 +94,13 @@ def precision_runs(A, steps, warmup, b=128):
     for tol in (1e-3, 1e-5):
         for form, prec in (("bf16", icur.BF16_SPLIT), ("fp32", icur.FP32)):
             for i in range(warmup):
-                icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
+                icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec, device_outputs=True)
             torch.cuda.synchronize()
             times, outs = [], []
             for i in range(steps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec)
+                out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i, precision=prec, device_outputs=True)
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - t0)
                 outs.append(out)
@@ -142,31 +142,51 @@ def bench_batched(a):
     tols = [sp["tol"] for sp in specs]
     seeds = list(range(a.count))
     elems = float(sum(sp["m"] * sp["n"] for sp in specs))
+    # the timed calls write their indices and cores to device pools (inputs and outputs
+    # resident in HBM); one more call with host pools gives the rate with the results
+    # copied over PCIe
+    got = None
     for w in range(a.warmup):
-        icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
+        got = None
+        got = icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False,
+                               device_outputs=True)
         print("batched warm-up %d done" % w, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tb, infos = [], []
     for s in range(a.steps):
+        got = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        got = icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
+        got = icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False,
+                               device_outputs=True)
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t0)
         infos.append(icur.last_info())
         print("batched step %d: %.3f s" % (s, tb[-1]), file=sys.stderr, flush=True)
+    got = [{"I": g["I"].cpu().numpy(), "J": g["J"].cpu().numpy(), "rank": g["rank"], "status": g["status"]}
+           for g in got]
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hp = icur.run_batched(As, tols, b, icur.GAUSSIAN, seeds, workers=a.workers, check=False)
+    t_host = time.perf_counter() - t0
+    host_info = icur.last_info()
+    same_host = sum(1 for g, h in zip(got, hp) if np.array_equal(g["I"], h["I"]) and np.array_equal(g["J"], h["J"]))
+    del hp
+    print("batched, host pools: %.3f s" % t_host, file=sys.stderr, flush=True)
     # the plain FP32 loop: one icur_run per matrix, once (its workspace is sized by a first
     # call on the largest matrix)
     if a.no_plain:
         plain, t_plain = got, float("nan")
     else:
         big = max(range(a.count), key=lambda i: specs[i]["m"] * specs[i]["n"])
-        icur.run(As[big], tols[big], b, icur.GAUSSIAN, seeds[big])
+        icur.run(As[big], tols[big], b, icur.GAUSSIAN, seeds[big], device_outputs=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plain = [icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i]) for i in range(a.count)]
+        plain = [icur.run(As[i], tols[i], b, icur.GAUSSIAN, seeds[i], device_outputs=True) for i in range(a.count)]
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
+        plain = [{"I": p["I"].cpu().numpy(), "J": p["J"].cpu().numpy(), "rank": p["rank"]} for p in plain]
         print("plain loop: %.3f s" % t_plain, file=sys.stderr, flush=True)
     ranks = [g["rank"] for g in got]
     same_rank = sum(1 for g, p in zip(got, plain) if g["rank"] == p["rank"])
@@ -192,7 +212,10 @@ def bench_batched(a):
                         "r0 ~ U[10,400], tol ~ 10^U[-6,-2], block 32, Gaussian sketch; grouped batched form "
                         "(every matrix advanced together) against one icur_run per matrix" % a.count,
             "count": a.count, "elements": elems, "block": b, "form": "grouped" if not a.workers else "workers",
+            "outputs": "device pools (indices and cores stay in HBM)",
             "plain_loop_s": t_plain, "speedup_vs_plain_loop": t_plain / value,
+            "host_pools_s": t_host, "host_pools_results_copy_ms": host_info["ms_results"],
+            "same_indices_host_vs_device_pools": same_host,
             "same_rank_as_plain_loop": same_rank, "same_indices_as_plain_loop": same_idx,
             "rank_min": min(ranks), "rank_median": statistics.median(ranks), "rank_max": max(ranks),
             "statuses": {k: sum(1 for g in got if g["status"] == k) for k in set(g["status"] for g in got)},
@@ -320,13 +343,13 @@ def bench_x1(a):
     A = W.low_rank_device(m, n, rk, seed=0)
     torch.cuda.synchronize()
     for i in range(a.warmup):
-        icur.run(A, tol, b, icur.GAUSSIAN, seed=i)
+        icur.run(A, tol, b, icur.GAUSSIAN, seed=i, device_outputs=True)
     torch.cuda.synchronize()
     times, outs = [], []
     for i in range(a.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i)
+        out = icur.run(A, tol, b, icur.GAUSSIAN, seed=i, device_outputs=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         outs.append(out)
@@ -395,13 +418,13 @@ def bench_csr(a):
     runs = {}
     for form, prec in (("bf16", icur.BF16_SPLIT), ("fp32", icur.FP32)):
         for i in range(a.warmup):
-            icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=i, precision=prec)
+            icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=i, precision=prec, device_outputs=True)
         torch.cuda.synchronize()
         times, outs = [], []
         for i in range(a.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            out = icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=i, precision=prec)
+            out = icur.run_csr(*d, (m, n), tol, b, icur.SPARSE_SIGN, seed=i, precision=prec, device_outputs=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             outs.append(out)
@@ -498,7 +521,7 @@ def main():
 
     results = []
     for i in range(a.warmup):
-        icur.run(A, tol, b, kind, seed=i, precision=precision, zeta=zeta)
+        icur.run(A, tol, b, kind, seed=i, precision=precision, zeta=zeta, device_outputs=True)
         print("warmup %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     times, sketch_ms = [], []
@@ -506,7 +529,7 @@ def main():
     for i in range(a.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = icur.run(A, tol, b, kind, seed=i, precision=precision, zeta=zeta)
+        out = icur.run(A, tol, b, kind, seed=i, precision=precision, zeta=zeta, device_outputs=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         sketch_ms.append(out["info"]["ms_sketch_product"])

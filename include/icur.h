@@ -84,6 +84,11 @@ typedef struct icur_opts {
                            for the sparse-sign G); costs one extra read of A */
   int32_t selection;    /* index selection of both steps: ICUR_SELECT_LUPP (0, default) or
                            ICUR_SELECT_QRCP (1), Alg. 1's alternative (§5.3) */
+  int32_t device_outputs; /* 0 (default): the index and core outputs (I, J, U, or the
+                             batched call's pools) are host memory; 1: device memory of the
+                             current device, written in stream order (no copy over PCIe).
+                             rank, est_err and status stay host memory either way */
+  int32_t pad_opts;
 } icur_opts;
 
 enum icur_selection {
@@ -140,6 +145,11 @@ typedef struct icur_info {
   double  stage_bytes[5];     /* grouped batched call: algorithmic bytes of the product stages
                                  of ms_stage (nonzero operand parts read once, output written
                                  once) */
+  int32_t graph_iterations;   /* grouped batched call: iterations run as a replay of the
+                                 captured hipGraph of one iteration (all but the first with
+                                 ICUR_BATCH_GRAPH=1, else none; the stage times above are
+                                 not measured in replays) */
+  int32_t pad3;
 } icur_info;
 
 /*
@@ -149,9 +159,11 @@ typedef struct icur_info {
  *   block    b, 1 <= b <= min(m, n) and b <= 512; c = (11 b) / 10 sketch rows.
  *   sketch_kind, seed: G of icur_sketch_kind drawn from Philox4x32-10 keyed by seed.
  *   opts     may be NULL (all defaults).
- *   I, J     host, capacity max_rank each: selected row / column indices in selection
- *            order (block by block, pivot order within a block).
- *   U        host, capacity max_rank * max_rank doubles: the rank x rank core
+ *   I, J     host (device with opts->device_outputs), capacity max_rank each: selected
+ *            row / column indices in selection order (block by block, pivot order
+ *            within a block).
+ *   U        host (device with opts->device_outputs), capacity max_rank * max_rank
+ *            doubles: the rank x rank core
  *            A(I,J)^{-1} (row-major, leading dimension rank), so A ~ A(:,J) U A(I,:).
  *   rank     host: |I| = |J|.
  *   est_err  host: the final rho.
@@ -208,8 +220,10 @@ int icur_run_csr(const int64_t* rowptr, const int32_t* colind, const float* vals
  *   cap_offsets  host, count + 1 nondecreasing entries, cap_offsets[0] = 0.  Matrix i
  *                owns I_pool / J_pool entries cap_offsets[i] .. cap_offsets[i+1]-1; this
  *                capacity must be at least min(m[i], n[i], max_rank).
- *   I_pool, J_pool  host int64, cap_offsets[count] entries each.
- *   U_pool       host doubles, sum of cap_i^2 entries: matrix i's core (rank_i x rank_i,
+ *   I_pool, J_pool  host int64 (device with opts->device_outputs), cap_offsets[count]
+ *                entries each.
+ *   U_pool       host doubles (device with opts->device_outputs), sum of cap_i^2
+ *                entries: matrix i's core (rank_i x rank_i,
  *                leading dimension rank_i) starts at sum_{j<i} cap_j^2.
  *   rank, est_err, status  host arrays of count entries: per-matrix rank, final rho and
  *                return code of that matrix's run.

@@ -396,6 +396,7 @@ int check_run_args(bool sparse, const float* A, int64_t m, int64_t n, int64_t ld
   if (o->batch_workers < 0 || o->batch_workers > 16) return arg_error("batch_workers must be 0..16");
   if (o->denominator != ICUR_DENOM_GA && o->denominator != ICUR_DENOM_A) return arg_error("unknown denominator");
   if (o->selection != ICUR_SELECT_LUPP && o->selection != ICUR_SELECT_QRCP) return arg_error("unknown selection");
+  if (o->device_outputs != 0 && o->device_outputs != 1) return arg_error("device_outputs must be 0 or 1");
   // the Corollary of §3.3 is stated for a Gaussian G
   if (o->alpha != 0.0 && kind != ICUR_SKETCH_GAUSSIAN)
     return arg_error("risk-aware stopping needs the Gaussian sketch (the §3.3 Corollary's hypothesis)");
@@ -978,16 +979,21 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
     const size_t ij_bytes = static_cast<size_t>(r) * 8;
     const size_t u_bytes = static_cast<size_t>(r) * r * 8;
     char* stage = static_cast<char*>(dc.host_pinned) + kStageOffset;
-    const bool staged = info_bytes + 2 * ij_bytes + u_bytes <= kStageBytes;
+    const bool dev_out = o.device_outputs != 0;
+    const size_t out_bytes = dev_out ? 0 : 2 * ij_bytes + u_bytes;
+    const bool staged = info_bytes + out_bytes <= kStageBytes;
     std::vector<int> hinfo(nb);
     if (staged) {
       HostSegs h{};
       const int64_t so = static_cast<int64_t>(kStageOffset);
       h.seg[0] = HostSeg{infos, static_cast<int64_t>(nb * sizeof(int)), so};
-      h.seg[1] = HostSeg{pIall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes)};
-      h.seg[2] = HostSeg{pJall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes + ij_bytes)};
-      h.seg[3] = HostSeg{U, static_cast<int64_t>(u_bytes), so + static_cast<int64_t>(info_bytes + 2 * ij_bytes)};
-      h.n = 4;
+      h.n = 1;
+      if (!dev_out) {
+        h.seg[1] = HostSeg{pIall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes)};
+        h.seg[2] = HostSeg{pJall, static_cast<int64_t>(ij_bytes), so + static_cast<int64_t>(info_bytes + ij_bytes)};
+        h.seg[3] = HostSeg{U, static_cast<int64_t>(u_bytes), so + static_cast<int64_t>(info_bytes + 2 * ij_bytes)};
+        h.n = 4;
+      }
       ICUR_TRY(read_back(dc, h, st, false));
       std::memcpy(hinfo.data(), stage, nb * sizeof(int));
     } else {
@@ -1000,7 +1006,11 @@ int run_impl(const Source& src, int64_t m, int64_t n, double tol, int32_t block,
         return ICUR_ERR_HIP;
       }
     tm.add(ec0, ec1, &t_info.ms_core);
-    if (staged) {
+    if (dev_out) {
+      ICUR_HIP(hipMemcpyAsync(I_out, pIall, r * 8, hipMemcpyDeviceToDevice, st));
+      ICUR_HIP(hipMemcpyAsync(J_out, pJall, r * 8, hipMemcpyDeviceToDevice, st));
+      ICUR_HIP(hipMemcpyAsync(U_out, U, r * r * 8, hipMemcpyDeviceToDevice, st));
+    } else if (staged) {
       std::memcpy(I_out, stage + info_bytes, ij_bytes);
       std::memcpy(J_out, stage + info_bytes + ij_bytes, ij_bytes);
       std::memcpy(U_out, stage + info_bytes + 2 * ij_bytes, u_bytes);
@@ -1221,6 +1231,7 @@ int icur_run_batched(int32_t count, const float* const* A, const int64_t* m, con
   t_info.ms_setup = gstat.ms_alloc;
   t_info.ms_results = gstat.ms_results;
   t_info.sketch_kernel = gstat.sketch_kernel;
+  t_info.graph_iterations = gstat.graph_iterations;
   for (int q = 0; q < 5; ++q) t_info.ms_stage[q] = gstat.ms_stage[q];
   for (int q = 0; q < 5; ++q) t_info.stage_bytes[q] = gstat.stage_bytes[q];
   for (int q = 0; q < 4; ++q) t_info.tiles[q] = gstat.tiles[q];

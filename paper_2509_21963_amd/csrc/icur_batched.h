@@ -151,6 +151,7 @@ struct BatchedCall {
                           // output written once)
   int tiles[4];           // out: tile shapes used for P1, P2, P3, FIN
   int sketch_kernel;      // out: matrices whose G A ran on the dedicated sketch kernel
+  int graph_iterations;   // out: iterations run as a replay of the captured iteration graph
   double ms_results;      // out: host clock of the copies to the caller's pools
 };
 

@@ -177,8 +177,9 @@ struct ArenaHold {
   ~ArenaHold() { put_arena(device, a); }
 };
 
-// A host thread that copies finished matrices' results to the caller's (pageable) pools
-// on a stream of its own while the loop goes on.
+// A host thread that copies finished matrices' results to the caller's pools (pageable host
+// memory, or device memory with device_outputs) on a stream of its own while the loop goes
+// on.
 class ResultCopier {
  public:
   struct Job {
@@ -186,7 +187,7 @@ class ResultCopier {
     const void* src[3];
     size_t bytes[3];
   };
-  explicit ResultCopier(int device) : th_([this, device] { run(device); }) {}
+  ResultCopier(int device, hipMemcpyKind kind) : kind_(kind), th_([this, device] { run(device); }) {}
   ~ResultCopier() { finish(); }
   void push(const Job& j) {
     {
@@ -225,7 +226,7 @@ class ResultCopier {
       if (!cs || !err_.empty()) continue;
       hipError_t e = hipSuccess;
       for (int k = 0; k < 3 && e == hipSuccess; ++k)
-        if (j.bytes[k]) e = hipMemcpyAsync(j.dst[k], j.src[k], j.bytes[k], hipMemcpyDeviceToHost, cs);
+        if (j.bytes[k]) e = hipMemcpyAsync(j.dst[k], j.src[k], j.bytes[k], kind_, cs);
       if (e == hipSuccess) e = hipStreamSynchronize(cs);
       if (e != hipSuccess) err_ = std::string("copy of the results: ") + hipGetErrorString(e);
     }
@@ -236,6 +237,7 @@ class ResultCopier {
   std::deque<Job> q_;
   bool done_ = false;
   std::string err_;
+  const hipMemcpyKind kind_;
   std::thread th_;
 };
 
@@ -344,8 +346,10 @@ void release_batch_arenas() {
   (void)hipSetDevice(dev0);
 }
 
-// Runs the matrices listed in `which` (all with max(m, n) <= kGMaxN, block <= kGMaxSteps).
-int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream_t st) {
+namespace {
+
+// The grouped call on its own stream st (see run_batched_grouped).
+int run_grouped_on(const std::vector<int>& which, BatchedCall& a, hipStream_t st) {
   const int count = static_cast<int>(which.size());
   if (count == 0) return ICUR_OK;
   const icur_opts& o = *a.opts;
@@ -602,7 +606,7 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
 
   // a matrix that stops: its results to the copy thread (its core was multiplied out by
   // the same iteration's closing launch)
-  ResultCopier copier(dev.device);
+  ResultCopier copier(dev.device, a.opts->device_outputs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
   auto settle = [&](int q) {
     const int i = which[q];
     const BatchMat& bm = hm[q];
@@ -636,16 +640,43 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   int iters = 0;
   const auto t_loop0 = std::chrono::steady_clock::now();
   int err_loop = ICUR_OK;
+  // One iteration's launches (the selections, plan, gathers, products, end kernel and
+  // the core products of the matrices that stop), with device events for the timings.
+  // With ICUR_BATCH_GRAPH=1 they run from the second iteration on as one captured graph
+  // (the configuration of every launch depends only on the batch size and the device, and
+  // all state lives in device memory).  Plain launches are the default: an iteration is
+  // about ten milliseconds of device work against tens of microseconds of launches, so the
+  // replay gains nothing, and the event nodes of a replayed graph do not time the stages.
+  auto enqueue_iteration = [&]() -> int {
+    ICUR_TRY(launch_batch_iteration(dmats, count, static_cast<int>(c), static_cast<int>(b), a.row_cut, plan.p, drec,
+                                    tiles, grid, st, ev));
+    ICUR_HIP(hipEventRecord(ev[12], st));
+    ICUR_TRY(launch_batch_final(dmats, count, static_cast<int>(c), static_cast<int>(b), plan.p, tiles, st));
+    ICUR_HIP(hipEventRecord(ev[13], st));
+    return ICUR_OK;
+  };
+  const char* genv = std::getenv("ICUR_BATCH_GRAPH");
+  const bool use_graph = genv && genv[0] == '1';
+  struct GraphHold {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~GraphHold() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gh;
+  a.graph_iterations = 0;
   while (any && err_loop == ICUR_OK) {
-    err_loop = launch_batch_iteration(dmats, count, static_cast<int>(c), static_cast<int>(b), a.row_cut, plan.p, drec,
-                                      tiles, grid, st, ev);
-    if (err_loop != ICUR_OK) break;
-    if (hipEventRecord(ev[12], st) != hipSuccess ||
-        (err_loop = launch_batch_final(dmats, count, static_cast<int>(c), static_cast<int>(b), plan.p, tiles, st)) !=
-            ICUR_OK ||
-        hipEventRecord(ev[13], st) != hipSuccess) {
-      if (err_loop == ICUR_OK) err_loop = hip_error(hipGetLastError(), "batched: event record");
-      break;
+    if (gh.x) {
+      const hipError_t le = hipGraphLaunch(gh.x, st);
+      if (le != hipSuccess) {
+        err_loop = hip_error(le, "batched: iteration graph launch");
+        break;
+      }
+      ++a.graph_iterations;
+    } else {
+      err_loop = enqueue_iteration();
+      if (err_loop != ICUR_OK) break;
     }
     const hipError_t se = hipStreamSynchronize(st);
     if (se != hipSuccess) {
@@ -732,6 +763,32 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
       const hipError_t e = hipMemcpyAsync(dmats, hm.data(), sizeof(BatchMat) * count, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) err_loop = hip_error(e, "batched: state upload");
     }
+    if (use_graph && !gh.x && any && err_loop == ICUR_OK) {
+      // capture the next iteration (every lazily initialised launch parameter is set by now)
+      const hipError_t be = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (be != hipSuccess) {
+        err_loop = hip_error(be, "batched: begin capture");
+        break;
+      }
+      const int qe = enqueue_iteration();
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(st, &g);
+      gh.g = g;
+      if (qe != ICUR_OK) {
+        err_loop = qe;
+        break;
+      }
+      if (ce != hipSuccess || !g) {
+        err_loop = hip_error(ce, "batched: iteration capture");
+        break;
+      }
+      const hipError_t ie = hipGraphInstantiate(&gh.x, g, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        gh.x = nullptr;
+        err_loop = hip_error(ie, "batched: iteration graph");
+        break;
+      }
+    }
   }
   a.ms_loop = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_loop0).count();
   const auto t_res0 = std::chrono::steady_clock::now();
@@ -756,6 +813,36 @@ int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream
   }
   a.ms_results = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_res0).count();
   return ICUR_OK;
+}
+
+}  // namespace
+
+// Runs the matrices listed in `which` (all with max(m, n) <= kGMaxN, block <= kGMaxSteps)
+// on a stream of its own (a graph cannot be captured on the legacy default stream), after
+// the caller's stream; the caller's stream then waits for it.
+int run_batched_grouped(const std::vector<int>& which, BatchedCall& a, hipStream_t caller) {
+  hipStream_t ps = nullptr;
+  ICUR_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+  struct StreamFree {
+    hipStream_t s;
+    ~StreamFree() { (void)hipStreamDestroy(s); }
+  } sf{ps};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ICUR_HIP(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
+  struct EventFree {
+    hipEvent_t* e[2];
+    ~EventFree() {
+      for (hipEvent_t* q : e)
+        if (*q) (void)hipEventDestroy(*q);
+    }
+  } ef{{&e0, &e1}};
+  ICUR_HIP(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+  ICUR_HIP(hipEventRecord(e0, caller));
+  ICUR_HIP(hipStreamWaitEvent(ps, e0, 0));
+  const int rc = run_grouped_on(which, a, ps);
+  ICUR_HIP(hipEventRecord(e1, ps));
+  ICUR_HIP(hipStreamWaitEvent(caller, e1, 0));
+  return rc;
 }
 
 }  // namespace icur

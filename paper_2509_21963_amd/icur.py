@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("delta", ctypes.c_double),
                 ("split_terms", ctypes.c_int32), ("sketch_fp32", ctypes.c_int32),
                 ("residual_fp64", ctypes.c_int32), ("batch_workers", ctypes.c_int32),
-                ("denominator", ctypes.c_int32), ("selection", ctypes.c_int32)]
+                ("denominator", ctypes.c_int32), ("selection", ctypes.c_int32),
+                ("device_outputs", ctypes.c_int32), ("pad_opts", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +57,8 @@ class Info(ctypes.Structure):
                 ("ms_setup", ctypes.c_double), ("ms_results", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 5), ("tiles", ctypes.c_int32 * 4),
                 ("sketch_kernel", ctypes.c_int32), ("residual_terms", ctypes.c_int32),
-                ("stage_bytes", ctypes.c_double * 5)]
+                ("stage_bytes", ctypes.c_double * 5), ("graph_iterations", ctypes.c_int32),
+                ("pad3", ctypes.c_int32)]
 
 
 _lib = None
@@ -127,38 +129,54 @@ def _require(t, dtype, name):
         raise ValueError("%s must be row-major with unit column stride" % name)
 
 
+def _outputs(rmax, device_outputs, device):
+    """I, J and U buffers of a single call: numpy arrays, or device tensors."""
+    import torch
+    if device_outputs:
+        return (torch.empty(max(rmax, 1), dtype=torch.int64, device=device),
+                torch.empty(max(rmax, 1), dtype=torch.int64, device=device),
+                torch.empty(max(rmax * rmax, 1), dtype=torch.float64, device=device))
+    return np.zeros(rmax, np.int64), np.zeros(rmax, np.int64), np.zeros(rmax * rmax, np.float64)
+
+
+def _addr(x):
+    return ctypes.c_void_p(x.data_ptr()) if hasattr(x, "data_ptr") else x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _single_result(I, J, U, r, rho, st):
+    return {"I": I[:r].clone() if hasattr(I, "clone") else I[:r].copy(),
+            "J": J[:r].clone() if hasattr(J, "clone") else J[:r].copy(),
+            "U": U[:r * r].reshape(r, r).clone() if hasattr(U, "clone") else U[:r * r].reshape(r, r).copy(),
+            "rank": r, "rho": rho, "status": _STATUS_NAMES[st], "info": last_info()}
+
+
 def run(A, tol, block, sketch_kind=GAUSSIAN, seed=0, precision=FP32, zeta=0, max_rank=0,
         alpha=0.0, delta=0.0, split_terms=0, sketch_fp32=False, residual_fp64=0, denominator=DENOM_GA,
-        selection=LUPP):
+        selection=LUPP, device_outputs=False):
     """icur_run on the m x n FP32 device tensor A.  Returns a dict with I, J (int64
     numpy arrays, selection order), U (rank x rank float64 numpy array), rank, rho
     (final estimate), status ("ok", "maxrank" or "stalled") and info (per-call
-    statistics)."""
+    statistics).  With device_outputs, I, J and U are device tensors on A's device."""
     import torch
     lib = load()
     _require(A, torch.float32, "A")
     m, n = A.shape
     rmax = min(m, n) if max_rank == 0 else min(int(max_rank), m, n)
-    I = np.zeros(rmax, np.int64)
-    J = np.zeros(rmax, np.int64)
-    U = np.zeros(rmax * rmax, np.float64)
+    I, J, U = _outputs(rmax, device_outputs, A.device)
     rank = ctypes.c_int64(0)
     rho = ctypes.c_double(0.0)
     o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 1 if sketch_fp32 else 0,
-             int(residual_fp64), 0, int(denominator), int(selection))
+             int(residual_fp64), 0, int(denominator), int(selection), 1 if device_outputs else 0)
     st = lib.icur_run(_ptr(A), m, n, A.stride(0), float(tol), int(block), int(sketch_kind),
                       ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
-                      I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
-                      U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
+                      _addr(I), _addr(J), _addr(U), ctypes.byref(rank), ctypes.byref(rho))
     _check(st, allow_warnings=True)
-    r = rank.value
-    return {"I": I[:r].copy(), "J": J[:r].copy(), "U": U[:r * r].reshape(r, r).copy(),
-            "rank": r, "rho": rho.value, "status": _STATUS_NAMES[st], "info": last_info()}
+    return _single_result(I, J, U, rank.value, rho.value, st)
 
 
 def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, seed=0, precision=FP32,
             zeta=0, max_rank=0, alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, denominator=DENOM_GA,
-            selection=LUPP):
+            selection=LUPP, device_outputs=False):
     """icur_run_csr on device CSR arrays (rowptr int64, colind int32, vals float32) of an
     m x n matrix.  Returns the same dict as run()."""
     import torch
@@ -171,29 +189,26 @@ def run_csr(rowptr, colind, vals, shape, tol, block, sketch_kind=SPARSE_SIGN, se
             raise ValueError("%s must be a contiguous device tensor" % name)
     nnz = colind.numel()
     rmax = min(m, n) if max_rank == 0 else min(int(max_rank), m, n)
-    I = np.zeros(rmax, np.int64)
-    J = np.zeros(rmax, np.int64)
-    U = np.zeros(rmax * rmax, np.float64)
+    I, J, U = _outputs(rmax, device_outputs, vals.device)
     rank = ctypes.c_int64(0)
     rho = ctypes.c_double(0.0)
     o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), 0,
-             int(denominator), int(selection))
+             int(denominator), int(selection), 1 if device_outputs else 0)
     st = lib.icur_run_csr(_ptr(rowptr), _ptr(colind), _ptr(vals), m, n, nnz, float(tol), int(block),
                           int(sketch_kind), ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
-                          I.ctypes.data_as(ctypes.c_void_p), J.ctypes.data_as(ctypes.c_void_p),
-                          U.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rank), ctypes.byref(rho))
+                          _addr(I), _addr(J), _addr(U), ctypes.byref(rank), ctypes.byref(rho))
     _check(st, allow_warnings=True)
-    r = rank.value
-    return {"I": I[:r].copy(), "J": J[:r].copy(), "U": U[:r * r].reshape(r, r).copy(),
-            "rank": r, "rho": rho.value, "status": _STATUS_NAMES[st], "info": last_info()}
+    return _single_result(I, J, U, rank.value, rho.value, st)
 
 
 def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP32, zeta=0, max_rank=0,
                 alpha=0.0, delta=0.0, split_terms=0, residual_fp64=0, workers=0, check=True,
-                denominator=DENOM_GA):
+                denominator=DENOM_GA, device_outputs=False):
     """icur_run_batched on a list of m_i x n_i FP32 device tensors with per-matrix tolerances
     (and seeds, default 0..count-1).  Returns a list of dicts like run() (without info), each
-    with its own "status"; raises on a failed matrix when check is True."""
+    with its own "status"; raises on a failed matrix when check is True.  With
+    device_outputs the pools (and so I, J, U) are device tensors on the first matrix's
+    device."""
     import torch
     lib = load()
     count = len(As)
@@ -215,17 +230,23 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
     offs[1:] = np.cumsum(cap)
     uoffs = np.zeros(count + 1, np.int64)
     uoffs[1:] = np.cumsum(cap * cap)
-    I = np.empty(max(int(offs[-1]), 1), np.int64)
-    J = np.empty(max(int(offs[-1]), 1), np.int64)
-    U = np.empty(max(int(uoffs[-1]), 1), np.float64)
+    if device_outputs and count:
+        dev = As[0].device
+        I = torch.empty(max(int(offs[-1]), 1), dtype=torch.int64, device=dev)
+        J = torch.empty(max(int(offs[-1]), 1), dtype=torch.int64, device=dev)
+        U = torch.empty(max(int(uoffs[-1]), 1), dtype=torch.float64, device=dev)
+    else:
+        I = np.empty(max(int(offs[-1]), 1), np.int64)
+        J = np.empty(max(int(offs[-1]), 1), np.int64)
+        U = np.empty(max(int(uoffs[-1]), 1), np.float64)
     rank = np.zeros(max(count, 1), np.int64)
     est = np.zeros(max(count, 1), np.float64)
     status = np.zeros(max(count, 1), np.int32)
     o = Opts(precision, zeta, max_rank, _stream(), alpha, delta, split_terms, 0, int(residual_fp64), int(workers),
-             int(denominator))
+             int(denominator), LUPP, 1 if device_outputs else 0)
     c_ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     st = lib.icur_run_batched(count, ptrs, c_ptr(m), c_ptr(n), c_ptr(lda), c_ptr(tol), int(block), int(sketch_kind),
-                              c_ptr(sd), ctypes.byref(o), c_ptr(I), c_ptr(J), c_ptr(U), c_ptr(offs), c_ptr(rank),
+                              c_ptr(sd), ctypes.byref(o), _addr(I), _addr(J), _addr(U), c_ptr(offs), c_ptr(rank),
                               c_ptr(est), c_ptr(status))
     if check:
         _check(st)
@@ -242,7 +263,7 @@ def run_batched(As, tols, block, sketch_kind=GAUSSIAN, seeds=None, precision=FP3
 def last_info():
     info = Info()
     load().icur_last_info(ctypes.byref(info))
-    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "block_sizes", "ms_stage", "tiles", "stage_bytes")}
+    d = {k: getattr(info, k) for k, _ in Info._fields_ if k not in ("rho", "pad", "pad3", "block_sizes", "ms_stage", "tiles", "stage_bytes")}
     d["ms_stage"] = list(info.ms_stage)
     d["stage_bytes"] = list(info.stage_bytes)
     d["tiles"] = list(info.tiles)

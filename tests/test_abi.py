@@ -40,12 +40,31 @@ def test_library_exports_every_declared_symbol():
     assert set(icur.EXPORTS) == set(declared_functions())
 
 
-def test_struct_layouts_match_header():
+def _c_layout(struct, fields):
+    """sizeof and field offsets of a header struct, from a C program built with gcc."""
+    import subprocess
+    import tempfile
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "icur.h"', 'int main(void) {',
+             '  printf("%%zu\\n", sizeof(%s));' % struct]
+    lines += ['  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields]
+    lines += ['  return 0;', '}']
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("struct,cls", [("icur_opts", "Opts"), ("icur_info", "Info")])
+def test_struct_layouts_match_header(struct, cls):
+    # the binding's ctypes mirrors are laid out as the C compiler lays out the header's
     icur, _ = _lib()
-    # icur_opts: 2 x int32, int64, pointer, 2 x double, 6 x int32
-    assert ctypes.sizeof(icur.Opts) == 64
-    # icur_info: 2 x int32, 8 doubles, 2 x int32, 512 doubles, 512 x int32, 2 doubles, 2 x int32
-    assert ctypes.sizeof(icur.Info) == 8 + 8 * 8 + 8 + 512 * 8 + 512 * 4 + 16 + 8 + 16 + 40 + 16 + 8 + 40
+    C = getattr(icur, cls)
+    names = [f[0] for f in C._fields_]
+    size, offs = _c_layout(struct, names)
+    assert ctypes.sizeof(C) == size
+    assert [getattr(C, f).offset for f in names] == offs
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation precedes device work
@@ -81,7 +100,7 @@ def test_run_rejects_bad_options():
               icur.Opts(max_rank=-1), icur.Opts(alpha=1e-10),     # c = 2 < -4 ln(alpha)
               icur.Opts(residual_fp64=2), icur.Opts(zeta=-1), icur.Opts(batch_workers=17),
               icur.Opts(batch_workers=-1), icur.Opts(denominator=2), icur.Opts(denominator=-1),
-              icur.Opts(selection=2), icur.Opts(selection=-1)):
+              icur.Opts(selection=2), icur.Opts(selection=-1), icur.Opts(device_outputs=2)):
         st, _ = _run_args(lib, opts=ctypes.byref(o))
         assert st == icur.ERR_ARG, (o.precision, o.zeta)
     # the SRTT operator needs c <= m

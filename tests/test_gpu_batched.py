@@ -148,6 +148,46 @@ def test_grouped_growth_gives_the_same_results(icur, monkeypatch):
     assert max(g["rank"] for g in full) > 4 * 16  # beyond the smallest first capacity
 
 
+def test_iteration_graph_gives_the_same_results(icur, monkeypatch):
+    # with ICUR_BATCH_GRAPH=1 the grouped loop replays a captured graph of one iteration
+    # from the second iteration on; plain launches (the default) give identical results,
+    # also where rank-sized buffers grow between replays
+    specs, mats = _batch(8, seed=6, m_range=(200, 800), r0_range=(10.0, 50.0))
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    for limit in (None, 1 << 20):
+        if limit is not None:
+            monkeypatch.setenv("ICUR_BATCH_MEMORY_LIMIT", str(limit))
+        monkeypatch.setenv("ICUR_BATCH_GRAPH", "1")
+        graph = icur.run_batched(dev, tols, 16, icur.GAUSSIAN)
+        gi = icur.last_info()
+        assert gi["group_iterations"] > 2
+        assert gi["graph_iterations"] == gi["group_iterations"] - 1
+        monkeypatch.delenv("ICUR_BATCH_GRAPH")
+        plain = icur.run_batched(dev, tols, 16, icur.GAUSSIAN)
+        pi = icur.last_info()
+        assert pi["graph_iterations"] == 0 and pi["group_iterations"] == gi["group_iterations"]
+        assert pi["ms_stage"][0] > 0.0
+        for a, b in zip(plain, graph):
+            assert a["status"] == b["status"]
+            _same(a, b)
+
+
+@pytest.mark.parametrize("workers", [0, 4])
+def test_batched_device_outputs(icur, workers):
+    # device_outputs = 1: the pools are device memory (no copies over PCIe); the same
+    # indices, cores and estimates as host pools, in the grouped and the worker form
+    specs, mats = _batch(6, seed=8, m_range=(200, 900), r0_range=(10.0, 60.0))
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    tols = [sp["tol"] for sp in specs]
+    h = icur.run_batched(dev, tols, 32, icur.GAUSSIAN, workers=workers)
+    d = icur.run_batched(dev, tols, 32, icur.GAUSSIAN, workers=workers, device_outputs=True)
+    for a, b in zip(h, d):
+        assert b["U"].is_cuda and a["status"] == b["status"]
+        _same(a, {"rank": b["rank"], "rho": b["rho"], "I": b["I"].cpu().numpy(), "J": b["J"].cpu().numpy(),
+                  "U": b["U"].cpu().numpy()})
+
+
 def test_tile_shapes_give_identical_results(icur, monkeypatch):
     # the grouped products' tile shape (the autotuner's choice) changes no result: depth
     # chunks start at fixed multiples, so every element's sum is the same

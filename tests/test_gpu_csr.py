@@ -118,3 +118,15 @@ def test_non_canonical_csr_is_rejected(icur, defect):
     with pytest.raises(icur.IcurError) as e:
         icur.run_csr(*dev_csr(rowptr, colind, vals), (3, 4), 1e-3, 2)
     assert e.value.status == icur.ERR_ARG
+
+
+def test_sparse_device_outputs(icur):
+    # device_outputs = 1: the same I, J and U, written to device memory
+    A = W.sparse_lowrank(2000, 1500, r=40, q_per_row=40, seed=4, decay=1.0 / 20)
+    rowptr, colind, vals = W.csr_to_f32(A)
+    args = dev_csr(rowptr, colind, vals)
+    h = icur.run_csr(*args, A.shape, 1e-4, 8, 1, 9)
+    d = icur.run_csr(*args, A.shape, 1e-4, 8, 1, 9, device_outputs=True)
+    assert d["U"].is_cuda and h["rank"] == d["rank"] and h["rho"] == d["rho"]
+    assert np.array_equal(h["I"], d["I"].cpu().numpy()) and np.array_equal(h["J"], d["J"].cpu().numpy())
+    assert np.array_equal(h["U"], d["U"].cpu().numpy())

@@ -293,3 +293,20 @@ def test_deep_products_on_the_library_gemm(icur):
     assert got["rank"] >= 512 and got["info"]["iterations"] >= 4
     assert got["status"] == "ok" and err <= 2e-6 and 0.5 <= got["rho"] / err <= 2.0
     assert abs(got["rank"] - ora["rank"]) <= 128
+
+
+@pytest.mark.parametrize("shape,tol,b", [((400, 300), 1e-3, 8), ((2000, 1500), 1e-6, 64)])
+def test_device_outputs_equal_host_outputs(icur, shape, tol, b):
+    # device_outputs = 1 writes I, J and U to device memory instead of the host (the small
+    # case goes through the pinned staging area on the host path, the large one past it);
+    # the values are the same bytes
+    A32, _ = W.to_f32(W.planted_geometric(shape[0], shape[1], 40.0 if shape[0] < 1000 else 100.0, seed=2)[0])
+    A = torch.from_numpy(A32).cuda()
+    h = icur.run(A, tol, b, 0, 5)
+    d = icur.run(A, tol, b, 0, 5, device_outputs=True)
+    assert d["U"].is_cuda and d["I"].is_cuda
+    assert h["rank"] == d["rank"] and h["rho"] == d["rho"] and h["status"] == d["status"]
+    assert np.array_equal(h["I"], d["I"].cpu().numpy()) and np.array_equal(h["J"], d["J"].cpu().numpy())
+    assert np.array_equal(h["U"], d["U"].cpu().numpy())
+    if shape[0] == 2000:
+        assert h["rank"] * h["rank"] * 8 > 2 << 20
