@@ -18,11 +18,14 @@
 //   panel kernel (one persistent grid, <= one workgroup per CU)  the 16 pivot steps on
 //       P held in registers, R rows per thread:
 //         local argmax (DPP within waves, LDS across them)  ->  the owner publishes
-//         (|value|, index, panel row) into its workgroup's slot with device-coherent
-//         stores, waits for them to complete and arrives at the grid barrier  ->  every
-//         workgroup reads all slots (device-coherent loads) and reduces them itself  ->
-//         rank-one update.  One grid-wide exchange per step, and no L2 write-back or
-//         invalidation: only the slot words cross workgroups inside the kernel.
+//         (|value|, index, panel row) into its workgroup's slot for this step with
+//         device-coherent stores  ->  every workgroup polls all slots of the step
+//         (device-coherent loads) until each word it needs has arrived, and reduces them
+//         itself  ->  rank-one update.  A slot word holds the bitwise complement of its
+//         value and the slots are cleared to zero before the panel, so a nonzero word
+//         is a complete, current value: the exchange needs no counter, no ordering of
+//         the stores and no L2 write-back or invalidation, and a step costs the stores'
+//         trip to the coherence point plus one polling round trip.
 //       The multipliers replace the consumed panel entries in registers and are
 //       written to L once, at the end of the panel.
 // The panel grid is an ordinary dispatch (a cooperative launch costs about 10 us more
@@ -49,13 +52,15 @@ constexpr int kLC = 64;          // pivot-row multipliers staged in LDS per roun
 constexpr int kMaxSteps = 1024;  // LDS of the prep kernel holds (t0 + 64) x 16 doubles
 constexpr int kMaxGroups = 256;  // panel-kernel workgroups (one per CU at most)
 constexpr unsigned kSpinLimit = 1u << 22;
-constexpr size_t kCtlBytes = 256;  // barrier (word 0), status words (byte 128), first pivot (byte 192)
+constexpr size_t kCtlBytes = 256;  // status words (byte 128), first pivot (byte 192)
 
-struct Slot {
-  double val;  // |best entry| of the workgroup, 0 if it has no candidate with a nonzero entry
-  long long idx;
-  double row[kPW];
-};
+// Exchange slot of one workgroup at one panel step: kSlotWords 64-bit words, each the
+// bitwise complement of its value (zero = not yet written; no value published here has
+// all bits set): the key of the workgroup's best |entry| (0 if it has no candidate with
+// a nonzero entry), its index (INT_MAX if none), then the pivot-row candidate's panel
+// entries (those before the step are not read).  Slots are laid out [step][workgroup].
+constexpr int kSlotWords = 2 + kPW;
+constexpr size_t kSlotBytes = static_cast<size_t>(kPW) * kMaxGroups * kSlotWords * sizeof(unsigned long long);
 
 // Device view of the workspace.
 struct Work {
@@ -63,8 +68,9 @@ struct Work {
   double* P;        // kPW x N: the current panel with all previous updates applied
   double* U;        // steps x steps: row k = pivot row of step k at the columns after its panel
   uint8_t* chosen;  // N: 1 once the candidate has been chosen as a pivot
-  Slot* slots;      // 2 x kMaxGroups, by step parity
-  unsigned* bar;    // grid barrier counter: G arrivals per step
+  unsigned long long* xs;  // exchange slots, kPW x groups x kSlotWords words
+  int groups;       // workgroups of the panel grid
+  unsigned* ctl;    // control words
   int* status;      // [0] pivots found, [1] fault flag, [2] ended early
   unsigned long long* ref;  // |first pivot| of the call (bit pattern), set by panel 0
   int64_t* piv;     // steps
@@ -117,10 +123,17 @@ __device__ __forceinline__ void load_l16(const double* L, int N, int k0, int64_t
 
 template <typename InT>
 __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
+  // clear this panel's exchange slots (the previous panel kernel has finished with them;
+  // the end of this kernel makes the zeros visible to every workgroup of the next one)
+  if (a.w.groups > 1) {
+    const int words = kPW * a.w.groups * kSlotWords;
+    for (int e = static_cast<int>(blockIdx.x) * kPT + threadIdx.x; e < words; e += static_cast<int>(gridDim.x) * kPT)
+      a.w.xs[e] = 0ull;
+  }
   if (a.t0 == 0) {
-    // first panel of a call: clear the control words (barrier counter, status, first
-    // pivot) for the panel kernels that follow on the stream
-    if (blockIdx.x == 0 && threadIdx.x < kCtlBytes / sizeof(unsigned)) a.w.bar[threadIdx.x] = 0u;
+    // first panel of a call: clear the control words (status, first pivot) for the
+    // panel kernels that follow on the stream
+    if (blockIdx.x == 0 && threadIdx.x < kCtlBytes / sizeof(unsigned)) a.w.ctl[threadIdx.x] = 0u;
   } else if (a.w.status[1] != 0 || a.w.status[2] != 0) {
     return;  // fault, or no pivots left
   }
@@ -236,8 +249,9 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
   // of one step use different sets, so neither needs an extra barrier before reuse
   __shared__ Red red[2][LT / 64];
   __shared__ double rows_sh[kMaxGroups * kPW];  // published panel rows of all workgroups
+  __shared__ unsigned long long key_sh[kMaxGroups];
+  __shared__ int idx_sh[kMaxGroups];
   __shared__ long long piv_sh[kPW];
-  __shared__ int flag;
 
   // A previous panel ended the factorization (or faulted): every workgroup reads the
   // same values, so the whole grid leaves together.
@@ -327,67 +341,68 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
         accept();
       } else {
         // (b) the owner (or thread 0 when the workgroup has no candidate) publishes the
-        // slot and arrives at the grid barrier.
-        Slot* slot = a.w.slots + (t & 1) * kMaxGroups + blockIdx.x;
-        if (owner) {
+        // workgroup's slot of this step: header and the row from column tt on
+        unsigned long long* xs = a.w.xs + static_cast<size_t>(tt) * G * kSlotWords;
+        if (owner || (gk == 0ull && tid == 0)) {
           unsigned long long pub[kPW];
-          owner_row(pub);
+          if (owner) {
+            owner_row(pub);
+          } else {
+#pragma unroll
+            for (int jj = tt; jj < kPW; ++jj) pub[jj] = 0ull;
+          }
+          unsigned long long* mine = xs + static_cast<size_t>(blockIdx.x) * kSlotWords;
+          __hip_atomic_store(mine, ~gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(mine + 1, ~static_cast<unsigned long long>(owner ? gi : INT_MAX), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
           for (int jj = tt; jj < kPW; ++jj)
-            __hip_atomic_store(&slot->row[jj], __longlong_as_double(static_cast<long long>(pub[jj])), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&slot->val, __longlong_as_double(static_cast<long long>(gk)), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&slot->idx, static_cast<long long>(gi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (gk == 0ull && tid == 0) {
-          __hip_atomic_store(&slot->val, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&slot->idx, static_cast<long long>(INT_MAX), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(mine + 2 + jj, ~pub[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (owner || (gk == 0ull && tid == 0)) {
-          // The slot words are device-coherent stores; waiting for their completion
-          // before the arrival orders them without a release fence, which would write
-          // back this XCD's whole L2 at every step.
-          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-          __hip_atomic_fetch_add(a.w.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // (c) wait for every workgroup's arrival (thread 0 polls, bounded)
-        if (tid == 0) {
-          const unsigned target = static_cast<unsigned>(t + 1) * static_cast<unsigned>(G);
+        // (c) every word of every slot this step reads, polled until it has arrived
+        // (bounded; a fault anywhere ends every workgroup's wait)
+        bool ok = true;
+        const int per = kSlotWords - tt;  // header and row entries tt .. kPW-1
+        for (int e = tid; e < G * per && ok; e += LT) {
+          const int g = e / per, w = e % per;
+          const int word = w < 2 ? w : w + tt;
+          const unsigned long long* src = xs + static_cast<size_t>(g) * kSlotWords + word;
+          unsigned long long v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           unsigned spins = 0;
-          int ok = 1;
-          while (__hip_atomic_load(a.w.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          while (v == 0ull) {
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 255u) == 0 &&
                 __hip_atomic_load(a.w.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-              ok = 0;
+              ok = false;
               break;
             }
             if (spins > kSpinLimit) {
               atomicExch(a.w.status + 1, 1);
-              ok = 0;
+              ok = false;
               break;
             }
+            v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
-          // no acquire fence: every slot word is read with device-coherent loads, issued
-          // after the counter was seen complete (and after the block barrier below)
-          flag = ok;
+          v = ~v;
+          if (w == 0)
+            key_sh[g] = v;
+          else if (w == 1)
+            idx_sh[g] = static_cast<int>(v);
+          else
+            rows_sh[g * kPW + word - 2] = __longlong_as_double(static_cast<long long>(v));
         }
-        __syncthreads();
-        if (!flag) {
+        if (__syncthreads_or(ok ? 0 : 1)) {
           stop = true;
         } else {
-          // (d) read every slot (header and row in one round trip) and reduce
-          const Slot* sl = a.w.slots + (t & 1) * kMaxGroups;
-          for (int e = tid; e < G * kPW; e += LT)
-            rows_sh[e] = __hip_atomic_load(&sl[e / kPW].row[e % kPW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // (d) reduce the slots
           unsigned long long ck = 0ull;
           int ci = INT_MAX, cw = -1;
           if (tid < G) {
-            ck = cand_key(__hip_atomic_load(&sl[tid].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            ci = static_cast<int>(__hip_atomic_load(&sl[tid].idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            ck = key_sh[tid];
+            ci = idx_sh[tid];
             cw = tid;
           }
-          block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);  // its barrier also publishes rows_sh
+          block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);
           accept();
         }
       }
@@ -420,9 +435,9 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
           }
         }
       }
-      // rows_sh, flag and red[1] are rewritten by the next step only after the barrier
-      // inside its first block_argmax, which every thread reaches after finishing this
-      // update; red[0] only after the barrier of (c)
+      // rows_sh, key_sh, idx_sh and red[1] are rewritten by the next step only after the
+      // barrier inside its first block_argmax, which every thread reaches after finishing
+      // this update; red[0] only after the barrier of (c)
     }
   });
 
@@ -474,8 +489,8 @@ size_t lupp_workspace_bytes(int64_t steps, int64_t N) {
          align256(static_cast<size_t>(kPW) * N * sizeof(double)) +        // P
          align256(static_cast<size_t>(steps) * steps * sizeof(double)) +  // U
          align256(static_cast<size_t>(N)) +                               // chosen
-         align256(2 * kMaxGroups * sizeof(Slot)) +                        // slots
-         kCtlBytes;                                                       // barrier, status
+         align256(kSlotBytes) +                                           // exchange slots
+         kCtlBytes;                                                       // status
 }
 
 int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w) {
@@ -489,9 +504,8 @@ int lupp_bind_workspace(void* base, int64_t steps, int64_t N, LuppWork* w) {
   w->chosen = reinterpret_cast<uint8_t*>(p);
   p += align256(static_cast<size_t>(N));
   w->slots = p;
-  p += align256(2 * kMaxGroups * sizeof(Slot));
-  // control words, cleared by every call: the barrier counter, then (in another cache
-  // line) the status words
+  p += align256(kSlotBytes);
+  // control words, cleared by every call: the status words and the first pivot
   w->ctl = reinterpret_cast<unsigned*>(p);
   w->status = reinterpret_cast<int*>(p + 128);
   w->ref = reinterpret_cast<unsigned long long*>(p + 192);
@@ -535,15 +549,17 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
     return ICUR_ERR_UNSUPPORTED;
   }
   const int groups = static_cast<int>((N + per_group - 1) / per_group);
-  // the control words (barrier and status) are cleared by the first prep launch
+  // the control words are cleared by the first prep launch, the exchange slots by every
+  // prep launch
 
   Work wk;
   wk.L = w.L;
   wk.P = w.P;
   wk.U = w.U;
   wk.chosen = w.chosen;
-  wk.slots = static_cast<Slot*>(w.slots);
-  wk.bar = w.ctl;
+  wk.xs = static_cast<unsigned long long*>(w.slots);
+  wk.groups = groups;
+  wk.ctl = w.ctl;
   wk.ref = w.ref;
   wk.status = w.status;
   wk.piv = piv;
