@@ -111,6 +111,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
+__device__ __forceinline__ bool better_key(unsigned long long k, int i, unsigned long long bk, int bi) {
+  return k > bk || (k == bk && i < bi);
+}
 
 // ---------------------------------------------------------------------------------
 // prep kernel
@@ -244,10 +247,7 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
 
 template <int R, int LT>
 __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
-  static_assert(LT >= kMaxGroups, "one thread per slot in the slot reduction");
-  // two sets of reduction scratch: the workgroup argmax (a) and the slot reduction (d)
-  // of one step use different sets, so neither needs an extra barrier before reuse
-  __shared__ Red red[2][LT / 64];
+  __shared__ Red red[LT / 64];  // workgroup argmax scratch
   __shared__ double rows_sh[kMaxGroups * kPW];  // published panel rows of all workgroups
   __shared__ unsigned long long key_sh[kMaxGroups];
   __shared__ int idx_sh[kMaxGroups];
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
       }
       unsigned long long gk;
       int gi, gw;
-      block_argmax<LT>(cand_key(bv), bi, 0, red[0], &gk, &gi, &gw);
+      block_argmax<LT>(cand_key(bv), bi, 0, red, &gk, &gi, &gw);
       const bool owner = gk != 0ull && br >= 0 && bi == gi;
       // the owner's row from column tt on, selected with bit masks (a read x[br] with a
       // run-time index would force x into scratch memory)
@@ -394,15 +394,18 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
         if (__syncthreads_or(ok ? 0 : 1)) {
           stop = true;
         } else {
-          // (d) reduce the slots
+          // (d) reduce the slots: every wave on its own (the same keys give every wave the
+          // same winner), so no further barrier
           unsigned long long ck = 0ull;
           int ci = INT_MAX, cw = -1;
-          if (tid < G) {
-            ck = key_sh[tid];
-            ci = idx_sh[tid];
-            cw = tid;
+          for (int g = tid & 63; g < G; g += 64) {
+            if (better_key(key_sh[g], idx_sh[g], ck, ci)) {
+              ck = key_sh[g];
+              ci = idx_sh[g];
+              cw = g;
+            }
           }
-          block_argmax<LT>(ck, ci, cw, red[1], &gk, &gi, &gw);
+          wave_argmax(ck, ci, cw, &gk, &gi, &gw);
           accept();
         }
       }
@@ -435,9 +438,9 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
           }
         }
       }
-      // rows_sh, key_sh, idx_sh and red[1] are rewritten by the next step only after the
-      // barrier inside its first block_argmax, which every thread reaches after finishing
-      // this update; red[0] only after the barrier of (c)
+      // rows_sh, key_sh and idx_sh are rewritten by the next step only after the barrier
+      // inside its first block_argmax, which every thread reaches after finishing this
+      // update and its slot reduction; red only after the barrier of (c)
     }
   });
 
