@@ -35,6 +35,7 @@
 // with an error instead of a hang.
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <utility>
 
 #include "icur_internal.h"
@@ -534,15 +535,20 @@ int lupp_launch(const void* X, bool x64, int64_t K, int64_t N, int64_t ldx, int 
   DeviceInfo dev;
   ICUR_TRY(device_info(&dev));
   // Rows per workgroup: up to 2048 candidates fit one workgroup, which needs no grid
-  // exchange; beyond that the per-step exchange costs more with more workgroups, so pack
-  // more candidates per workgroup and aim for about 16 of them.
+  // exchange.  Beyond that a step's exchange grows slowly with the workgroup count (about
+  // 1.1 us at 8 workgroups, 1.7 us at 30) while its argmax and update shrink with fewer
+  // rows per thread: the smallest shape that needs at most 64 workgroups (measured best
+  // of 16, 32, 64, 128 on 30000 and 40000 candidates).
   const int max_groups = std::min(std::min(dev.num_cus, kMaxGroups), w.max_groups > 0 ? w.max_groups : kMaxGroups);
   int sh = 0;
   if (N <= static_cast<int64_t>(kShape[kShapes - 1].R) * kShape[kShapes - 1].LT) {
     // one workgroup holds them all: no grid exchange at all (the pivot row goes through LDS)
     while (static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT < N) ++sh;
   } else {
-    while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * 16 < N) ++sh;
+    // ICUR_LUPP_GROUPS: the workgroup count aimed for (default 64)
+    int target = 64;
+    if (const char* e = std::getenv("ICUR_LUPP_GROUPS")) target = std::max(1, std::atoi(e));
+    while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * target < N) ++sh;
     // under a workgroup cap (concurrent selections), larger shapes until the grid fits
     while (sh + 1 < kShapes && static_cast<int64_t>(kShape[sh].R) * kShape[sh].LT * max_groups < N) ++sh;
   }

@@ -120,6 +120,7 @@ LUPP_CASES = [
     (40, 6000, 40, 0.0, 9),       # two rows per thread
     (48, 12000, 48, 0.05, 10),    # four rows per thread, 256 threads
     (64, 70000, 64, 0.0, 5),      # four rows per thread, 512 threads
+    (40, 30000, 40, 0.02, 12),    # two rows per thread, 256 threads, 59 workgroups
     (70, 200000, 64, 0.001, 6),
     (20, 300000, 20, 0.0, 7),
     (130, 5000, 128, 0.2, 8),     # 8 panels
