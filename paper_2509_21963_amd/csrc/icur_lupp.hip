@@ -119,12 +119,6 @@ __device__ __forceinline__ bool better_key(unsigned long long k, int i, unsigned
 // ---------------------------------------------------------------------------------
 // prep kernel
 // ---------------------------------------------------------------------------------
-// Multipliers of candidate `row` at steps k0 .. k0+15 (coalesced across threads).
-__device__ __forceinline__ void load_l16(const double* L, int N, int k0, int64_t row, double* out) {
-#pragma unroll
-  for (int u = 0; u < kPW; ++u) out[u] = L[static_cast<int64_t>(k0 + u) * N + row];
-}
-
 template <typename InT>
 __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
   // clear this panel's exchange slots (the previous panel kernel has finished with them;
@@ -203,11 +197,14 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
   if (!cand) return;
 
   // (3) candidate rows: the panel entries with all t0 previous updates, in step order.
-  // Two threads per row, eight panel columns each; multipliers are fetched two blocks of
-  // 16 steps ahead of their use (t0 is a multiple of 16).
+  // Two neighbouring lanes per row, eight panel columns each.  Of each block of 16 steps'
+  // multipliers each lane loads every other one and takes the rest from its partner (a
+  // DPP exchange), so the multipliers are read from memory once; they are fetched two
+  // blocks ahead of their use (t0 is a multiple of 16).
   constexpr int kHalf = kPW / 2;
-  const int h = tid / kRowsPrep;
-  const int i = static_cast<int>(blockIdx.x) * kRowsPrep + tid % kRowsPrep;
+  const int h = tid & 1;
+  const int i = static_cast<int>(blockIdx.x) * kRowsPrep + (tid >> 1);
+  // both lanes of a pair hold the same row, so they leave (or stay) together
   if (i >= N) return;
   if (t0 == 0 && h == 0) a.w.chosen[i] = 0;
   if ((a.excl && a.excl[i]) || (t0 > 0 && a.w.chosen[i])) return;
@@ -218,24 +215,37 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
     const int jj = kHalf * h + j2;
     x[j2] = jj < pw ? static_cast<double>(X[static_cast<int64_t>(t0 + jj) * a.ldx + i]) : 0.0;
   }
-  double l0[kPW], l1[kPW], l2[kPW];
-  if (t0 > 0) load_l16(a.w.L, N, 0, i, l0);
-  if (t0 > kPW) load_l16(a.w.L, N, kPW, i, l1);
+  // this lane's half of the multipliers of steps k0 .. k0+15: steps k0 + 2q + h
+  auto load_half = [&](int k0, double (&out)[kHalf]) {
+#pragma unroll
+    for (int q = 0; q < kHalf; ++q) out[q] = a.w.L[static_cast<int64_t>(k0 + 2 * q + h) * N + i];
+  };
+  double l0[kHalf], l1[kHalf], l2[kHalf];
+  if (t0 > 0) load_half(0, l0);
+  if (t0 > kPW) load_half(kPW, l1);
   for (int kb = 0; kb < t0; kb += kPW) {
-    if (kb + 2 * kPW < t0) load_l16(a.w.L, N, kb + 2 * kPW, i, l2);
+    if (kb + 2 * kPW < t0) load_half(kb + 2 * kPW, l2);
+    double l[kPW];
+#pragma unroll
+    for (int q = 0; q < kHalf; ++q) {
+      const double other = __longlong_as_double(static_cast<long long>(
+          dpp_u64<0xB1>(static_cast<unsigned long long>(__double_as_longlong(l0[q])))));  // quad_perm [1,0,3,2]
+      l[2 * q] = h ? other : l0[q];
+      l[2 * q + 1] = h ? l0[q] : other;
+    }
     const double* up = Upan + kb * kPW + kHalf * h;
 #pragma unroll
     for (int u = 0; u < kPW; ++u) {
 #pragma unroll
       for (int j2 = 0; j2 < kHalf; ++j2) {
-        const double prod = l0[u] * up[u * kPW + j2];
+        const double prod = l[u] * up[u * kPW + j2];
         x[j2] = x[j2] - prod;
       }
     }
 #pragma unroll
-    for (int u = 0; u < kPW; ++u) {
-      l0[u] = l1[u];
-      l1[u] = l2[u];
+    for (int q = 0; q < kHalf; ++q) {
+      l0[q] = l1[q];
+      l1[q] = l2[q];
     }
   }
 #pragma unroll
