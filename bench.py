@@ -38,23 +38,28 @@ METRIC = "time-to-tol (s) + sketch TFLOP/s|GB/s, BF16-split/batched vs FP32 plai
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_source_hash():
+SKETCH_SOURCES = ("icur_sketch.hip", "icur_wide_kernel.h")
+GROUPED_SOURCES = ("icur_group_kernels.hip", "icur_batched.h")
+
+
+def kernel_source_hash(files=SKETCH_SOURCES):
     h = hashlib.sha256()
-    for f in ("icur_sketch.hip", "icur_wide_kernel.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2509_21963_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key):
-    """HBM bytes per launch of the sketch product from committed rocprofv3 counter runs,
-    if they were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "sketch_product_%s_traffic.json" % workload_key)
+def measured_traffic(name, files=SKETCH_SOURCES):
+    """HBM bytes per launch of a kernel from committed rocprofv3 counter runs
+    (profiles/<name>_traffic.json), if they were taken on the current source of the
+    kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "%s_traffic.json" % name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash(files):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -232,7 +237,8 @@ def bench_batched(a):
                       "residual, new-row residual and the two inverses' block rows; %d launches per call)"
                       % (shapes[inf["tiles"][0]], launches),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": measured_traffic("batched_products_uneven%d" % a.count, GROUPED_SOURCES),
             "avg_ms": prod_ms / max(launches, 1),
             "algorithmic_bytes": prod_bytes / max(launches, 1),
         },
@@ -546,7 +552,7 @@ def main():
     alg_bytes = 4.0 * m * n + 2.0 * c * m + 8.0 * c * n
     avg_ms = statistics.mean(sketch_ms)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
-    traffic = measured_traffic("rbf%d" % m)
+    traffic = measured_traffic("sketch_product_rbf%d" % m)
     info = last["info"]
     line = {
         "metric": METRIC,
