@@ -284,6 +284,18 @@ def test_smooth_kernel_estimate_matches_oracle(icur):
     assert err <= 2e-4 and 0.5 <= got["rho"] / err <= 2.0
 
 
+def test_deep_products_on_the_native_gemm(icur, monkeypatch):
+    # ICUR_NATIVE_GEMM=1 runs the deep residual products and the core's block products on
+    # the library's own FP64 matrix-core kernel instead of rocBLAS: the same parity bar
+    monkeypatch.setenv("ICUR_NATIVE_GEMM", "1")
+    A, _ = W.planted_geometric(3000, 2500, 80.0, seed=4)
+    A32, _ = W.to_f32(A)
+    got, ora, err = check_against_oracle(icur, A32, 1e-6, 128, 0, 3)
+    assert got["rank"] >= 512 and got["info"]["iterations"] >= 4
+    assert got["status"] == "ok" and err <= 2e-6 and 0.5 <= got["rho"] / err <= 2.0
+    assert abs(got["rank"] - ora["rank"]) <= 128
+
+
 def test_deep_products_on_the_library_gemm(icur):
     # blocks of 128 rows and ranks past 256: the row residual and the residual at the new
     # rows run as library FP64 GEMMs (depth >= 256), the others on the short-M kernel
