@@ -61,6 +61,7 @@ constexpr size_t kCtlBytes = 256;  // status words (byte 128), first pivot (byte
 // a nonzero entry), its index (INT_MAX if none), then the pivot-row candidate's panel
 // entries (those before the step are not read).  Slots are laid out [step][workgroup].
 constexpr int kSlotWords = 2 + kPW;
+constexpr int kPoll = 8;  // slot words a thread loads together
 constexpr size_t kSlotBytes = static_cast<size_t>(kPW) * kMaxGroups * kSlotWords * sizeof(unsigned long long);
 
 // Device view of the workspace.
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
   __shared__ Red red[LT / 64];  // workgroup argmax scratch
   __shared__ double rows_sh[kMaxGroups * kPW];  // published panel rows of all workgroups
   __shared__ unsigned long long key_sh[kMaxGroups];
+  __shared__ unsigned long long pub_sh[kSlotWords];  // the slot being published
   __shared__ int idx_sh[kMaxGroups];
   __shared__ long long piv_sh[kPW];
 
@@ -352,35 +354,61 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
         accept();
       } else {
         // (b) the owner (or thread 0 when the workgroup has no candidate) publishes the
-        // workgroup's slot of this step: header and the row from column tt on
+        // workgroup's slot of this step, header and the row from column tt on: it stages
+        // the words in LDS and its wave stores them with one vector store, so they travel
+        // together instead of as 2 + 16 - tt stores of one thread
         unsigned long long* xs = a.w.xs + static_cast<size_t>(tt) * G * kSlotWords;
-        if (owner || (gk == 0ull && tid == 0)) {
-          unsigned long long pub[kPW];
-          if (owner) {
-            owner_row(pub);
-          } else {
+        const bool writer = owner || (gk == 0ull && tid == 0);
+        if (__ballot(writer) != 0ull) {  // the writer's wave (uniform within it)
+          if (writer) {
+            unsigned long long pub[kPW];
+            if (owner) {
+              owner_row(pub);
+            } else {
 #pragma unroll
-            for (int jj = tt; jj < kPW; ++jj) pub[jj] = 0ull;
+              for (int jj = tt; jj < kPW; ++jj) pub[jj] = 0ull;
+            }
+            pub_sh[0] = ~gk;
+            pub_sh[1] = ~static_cast<unsigned long long>(owner ? gi : INT_MAX);
+#pragma unroll
+            for (int jj = tt; jj < kPW; ++jj) pub_sh[2 + jj] = ~pub[jj];
           }
-          unsigned long long* mine = xs + static_cast<size_t>(blockIdx.x) * kSlotWords;
-          __hip_atomic_store(mine, ~gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(mine + 1, ~static_cast<unsigned long long>(owner ? gi : INT_MAX), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-          for (int jj = tt; jj < kPW; ++jj)
-            __hip_atomic_store(mine + 2 + jj, ~pub[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // the words were written by one lane of this wave and are read by the others
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const int ln = tid & 63;
+          if (ln < kSlotWords && (ln < 2 || ln - 2 >= tt))
+            __hip_atomic_store(xs + static_cast<size_t>(blockIdx.x) * kSlotWords + ln, pub_sh[ln], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        // (c) every word of every slot this step reads, polled until it has arrived
-        // (bounded; a fault anywhere ends every workgroup's wait)
+        // (c) every word of every slot this step reads.  A thread's words are loaded
+        // kPoll at a time, all in flight together, and the ones that had not arrived are
+        // loaded again, again all together (bounded; a fault anywhere ends every
+        // workgroup's wait): one round trip when the slots are complete, one more per
+        // round of late words.
         bool ok = true;
         const int per = kSlotWords - tt;  // header and row entries tt .. kPW-1
-        for (int e = tid; e < G * per && ok; e += LT) {
-          const int g = e / per, w = e % per;
-          const int word = w < 2 ? w : w + tt;
-          const unsigned long long* src = xs + static_cast<size_t>(g) * kSlotWords + word;
-          unsigned long long v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int total = G * per;
+        for (int base = 0; base < total && ok; base += LT * kPoll) {
+          const unsigned long long* src[kPoll];
+          unsigned long long v[kPoll];
+#pragma unroll
+          for (int q = 0; q < kPoll; ++q) {
+            const int e = base + q * LT + tid;
+            src[q] = nullptr;
+            v[q] = 1ull;  // no word here: nothing to wait for
+            if (e < total) {
+              const int g = e / per, w = e % per;
+              src[q] = xs + static_cast<size_t>(g) * kSlotWords + (w < 2 ? w : w + tt);
+              v[q] = __hip_atomic_load(src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
           unsigned spins = 0;
-          while (v == 0ull) {
+          for (;;) {
+            bool missing = false;
+#pragma unroll
+            for (int q = 0; q < kPoll; ++q) missing |= (v[q] == 0ull);
+            if (!missing) break;
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 255u) == 0 &&
                 __hip_atomic_load(a.w.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
@@ -392,15 +420,23 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
               ok = false;
               break;
             }
-            v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int q = 0; q < kPoll; ++q)
+              if (v[q] == 0ull) v[q] = __hip_atomic_load(src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
-          v = ~v;
-          if (w == 0)
-            key_sh[g] = v;
-          else if (w == 1)
-            idx_sh[g] = static_cast<int>(v);
-          else
-            rows_sh[g * kPW + word - 2] = __longlong_as_double(static_cast<long long>(v));
+#pragma unroll
+          for (int q = 0; q < kPoll; ++q) {
+            const int e = base + q * LT + tid;
+            if (e >= total) continue;
+            const int g = e / per, w = e % per;
+            const unsigned long long x = ~v[q];
+            if (w == 0)
+              key_sh[g] = x;
+            else if (w == 1)
+              idx_sh[g] = static_cast<int>(x);
+            else
+              rows_sh[g * kPW + w + tt - 2] = __longlong_as_double(static_cast<long long>(x));
+          }
         }
         if (__syncthreads_or(ok ? 0 : 1)) {
           stop = true;
@@ -449,9 +485,9 @@ __global__ __launch_bounds__(LT, 1) void lupp_panel(const PanelArgs a) {
           }
         }
       }
-      // rows_sh, key_sh and idx_sh are rewritten by the next step only after the barrier
-      // inside its first block_argmax, which every thread reaches after finishing this
-      // update and its slot reduction; red only after the barrier of (c)
+      // rows_sh, key_sh, idx_sh and pub_sh are rewritten by the next step only after the
+      // barrier inside its first block_argmax, which every thread reaches after finishing
+      // this update and its slot reduction; red only after the barrier of (c)
     }
   });
 
