@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
   // (3) candidate rows: the panel entries with all t0 previous updates, in step order.
   // Two neighbouring lanes per row, eight panel columns each.  Of each block of 16 steps'
   // multipliers each lane loads every other one and takes the rest from its partner (a
-  // DPP exchange), so the multipliers are read from memory once; they are fetched two
+  // DPP exchange), so the multipliers are read from memory once; they are fetched three
   // blocks ahead of their use (t0 is a multiple of 16).
   constexpr int kHalf = kPW / 2;
   const int h = tid & 1;
@@ -221,11 +221,13 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
 #pragma unroll
     for (int q = 0; q < kHalf; ++q) out[q] = a.w.L[static_cast<int64_t>(k0 + 2 * q + h) * N + i];
   };
-  double l0[kHalf], l1[kHalf], l2[kHalf];
+  // blocks kb .. kb + 3 of multipliers in flight (l0 is the block being applied)
+  double l0[kHalf], l1[kHalf], l2[kHalf], l3[kHalf];
   if (t0 > 0) load_half(0, l0);
   if (t0 > kPW) load_half(kPW, l1);
+  if (t0 > 2 * kPW) load_half(2 * kPW, l2);
   for (int kb = 0; kb < t0; kb += kPW) {
-    if (kb + 2 * kPW < t0) load_half(kb + 2 * kPW, l2);
+    if (kb + 3 * kPW < t0) load_half(kb + 3 * kPW, l3);
     double l[kPW];
 #pragma unroll
     for (int q = 0; q < kHalf; ++q) {
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(kPT) void lupp_prep(const PrepArgs a) {
     for (int q = 0; q < kHalf; ++q) {
       l0[q] = l1[q];
       l1[q] = l2[q];
+      l2[q] = l3[q];
     }
   }
 #pragma unroll
