@@ -83,7 +83,7 @@ struct Plan {
   GemmOp* gemm[kNumStages];
   GatherOp* gather[kNumStages];
   int* nops;      // per stage
-  int* ntiles;    // per stage
+  int* ntiles;    // per stage, followed by the per-stage tile counters of gemm_kernel
   double* bytes;  // per stage: algorithmic bytes of the products so far (the call's total)
   int rt[kNumStages], ct[kNumStages];  // product tile rows / columns of each stage
 };
@@ -183,6 +183,7 @@ __device__ void scan_tiles(OP* ops, int n, int* total, int* nops, int* warp_sums
   if (tid == 0) {
     *total = carry;
     *nops = n;
+    total[kNumStages] = 0;  // the stage's tile counter (see gemm_kernel)
   }
 }
 
@@ -508,13 +509,30 @@ __device__ __forceinline__ void gemm_wg_tile(const GemmOp& o, int lt, double (*w
 
 // ROLE only names the instance (0: the loop's products, 1: the closing core products), so
 // that a kernel trace tells the two apart.
+// Tiles are taken from a device counter (next to the stage's tile count, cleared by the
+// plan kernel), one at a time: a workgroup that drew shallow tiles takes more of them, so
+// the tiles' uneven depths (each matrix's rank) do not leave a tail of a few workgroups
+// with several deep tiles.  No lane-divergent branch may sit in this loop: with the draw
+// under `threadIdx.x == 0` and the exit on a plain LDS read, the compiler structured the
+// loop so that the drawing lane left it while the rest of its wave went on through the
+// barriers, which then never saw a new index.  So the draw is taken by the whole first
+// wave under a wave-uniform branch (lane 0 adds 1, the others 0, and every lane keeps lane
+// 0's old value), and the exit compares a readfirstlane value.
 template <int TR, int WN, int ROLE = 0, int PD = 1>
 __global__ __launch_bounds__(kPT) void gemm_kernel(const GemmOp* __restrict__ ops, const int* __restrict__ pnops,
-                                                   const int* __restrict__ pntiles) {
+                                                   int* __restrict__ pntiles) {
   __shared__ double wl[2][kKC * (16 * TR + 2)];
   __shared__ double red[kPT / 64];
+  __shared__ int g_sh;
   const int nops = *pnops, ntiles = *pntiles;
-  for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
+  int* next = pntiles + kNumStages;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  for (;;) {
+    if (wave == 0) g_sh = __builtin_amdgcn_readfirstlane(atomicAdd(next, threadIdx.x == 0 ? 1 : 0));
+    __syncthreads();
+    const int g = __builtin_amdgcn_readfirstlane(g_sh);
+    __syncthreads();  // every wave has read g_sh before the next draw overwrites it
+    if (g >= ntiles) break;
     const GemmOp& o = ops[find_op(ops, nops, g)];
     gemm_wg_tile<TR, WN, PD>(o, g - o.tile0, wl, red);
   }
