@@ -28,6 +28,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPT = 256;           // threads of the product and gather kernels
 constexpr int kGatherCols = 256;   // gather tile: one row x 256 columns
+constexpr int kGatherTrCols = 64;  // column-gather tile: every row (<= 64) x 64 columns
 constexpr int kKC = kGemmKChunk;   // product depth chunk
 
 struct GemmOp {
@@ -58,7 +59,8 @@ struct GatherOp {
   int64_t ldd;
   int rows, cols, tiles_c, f32;
   double scale;
-  int tile0, pad;   // pad: the op's tile count while the plan is built
+  int tile0, pad;
+  int tr, pad2;     // tr: column gather on the transposed tile (see gather_kernel)   // pad: the op's tile count while the plan is built
 };
 
 // Stage lists of one iteration.  Phase 0 (after the column selection): gathers GA and
@@ -146,9 +148,12 @@ __device__ __forceinline__ void set_gather(GatherOp* ops, int i, int k, const vo
   o.ldd = ldd;
   o.rows = rows;
   o.cols = cols;
-  o.tiles_c = (rows > 0 && cols > 0) ? ceil_div(cols, kGatherCols) : 0;
+  // dst row t = column ridx[t] of a row-major source: taken on tiles of every row x
+  // kGatherTrCols columns, which read along the source's rows
+  o.tr = (src && rs == 1 && ridx && !cidx && cs > 1 && rows <= 64) ? 1 : 0;
+  o.tiles_c = (rows > 0 && cols > 0) ? ceil_div(cols, o.tr ? kGatherTrCols : kGatherCols) : 0;
   o.scale = scale;
-  o.pad = rows > 0 ? rows * o.tiles_c : 0;
+  o.pad = rows > 0 ? (o.tr ? o.tiles_c : rows * o.tiles_c) : 0;
 }
 
 __device__ __forceinline__ void no_gather(GatherOp* ops, int i, int k) {
@@ -286,14 +291,59 @@ __device__ __forceinline__ int find_op(const OP* ops, int nops, int tile) {
   return lo;
 }
 
+// The loads of one column-gather tile (see gather_kernel): v[q] = src[(j0 + w + 4 q) cs + ct],
+// all issued before any is used.  Source rows past the tile are clamped to its last one,
+// so every load is in bounds and none sits under a branch; those values are never
+// written out.
+template <int Q, typename T>
+__device__ __forceinline__ void gather_tr_loads(const T* __restrict__ src, int64_t cs, int64_t ct, int j0, int nj,
+                                                int w, double (&v)[Q]) {
+  T x[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int jl = min(w + (kPT / 64) * q, nj - 1);
+    x[q] = src[static_cast<int64_t>(j0 + jl) * cs + ct];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = static_cast<double>(x[q]);
+}
+
 // dst[i][j] = scale * src[ridx[i] rs + cidx[j] cs] (identity where an index list is null);
-// with no src, dst[i][j] = scale * (i == j)
+// with no src, dst[i][j] = scale * (i == j).
+// Column gathers (tr: rs = 1, row indices, no column indices, at most 64 rows) run on
+// tiles of every row x kGatherTrCols columns: wave w reads source rows j0 + w + 4 q, lane t
+// the entry of column ridx[t], so a wave's loads stay in one source row; the tile is
+// turned in LDS and written one destination row (64 contiguous entries) per wave step.
+// The one-row tiles read a column of the source per wave, one source row per lane.
 __global__ __launch_bounds__(kPT) void gather_kernel(const GatherOp* __restrict__ ops, const int* __restrict__ pnops,
                                                      const int* __restrict__ pntiles) {
+  constexpr int kQ = kGatherTrCols / (kPT / 64);  // source rows per wave and tile
+  __shared__ double tb[64][kGatherTrCols + 1];
   const int nops = *pnops, ntiles = *pntiles;
   for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
     const GatherOp& o = ops[find_op(ops, nops, g)];
     const int lt = g - o.tile0;
+    if (o.tr) {
+      const int j0 = lt * kGatherTrCols;
+      const int nj = min(kGatherTrCols, o.cols - j0);
+      const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+      // lanes past the last row read row 0's column (in bounds; never written out)
+      const int64_t ct = o.ridx[t < o.rows ? t : 0];
+      double v[kQ];
+      if (o.f32)
+        gather_tr_loads<kQ>(static_cast<const float*>(o.src), o.cs, ct, j0, nj, w, v);
+      else
+        gather_tr_loads<kQ>(static_cast<const double*>(o.src), o.cs, ct, j0, nj, w, v);
+      __syncthreads();  // the previous tile's reads of tb are done
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) tb[t][w + (kPT / 64) * q] = v[q];
+      __syncthreads();
+      const int jl = threadIdx.x & 63;
+      if (jl < nj)
+        for (int tt = w; tt < o.rows; tt += kPT / 64)
+          o.dst[static_cast<int64_t>(tt) * o.ldd + j0 + jl] = o.scale * tb[tt][jl];
+      continue;
+    }
     const int i = lt / o.tiles_c;
     const int j = (lt % o.tiles_c) * kGatherCols + threadIdx.x;
     double* d = o.dst + static_cast<int64_t>(i) * o.ldd;
