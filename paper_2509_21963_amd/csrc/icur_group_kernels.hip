@@ -4,10 +4,12 @@
 // launch configuration never depends on the data (the same launches every iteration).
 //
 // Products are OUT(M x N) = beta X + alpha W(M x K) B(K x N) in FP64 on the FP64 matrix
-// cores (v_mfma_f64_16x16x4f64): tiles of 32 rows x 128 columns, the depth K per tile in
-// 32-deep chunks (W staged through LDS, B straight to registers), so the result of every
-// element is a fixed-order FP64 sum that does not depend on the grouping.  Products with
-// a block-triangular operand skip the depth range where that operand is zero.
+// cores (v_mfma_f64_16x16x4f64): tiles of 16 TR rows x 128 WN columns (shape chosen per
+// stage, 32 x 128 by default), the depth K per tile in 16-deep chunks that start at fixed
+// multiples (W staged through LDS, B straight to registers), so the result of every
+// element is a fixed-order FP64 sum that depends neither on the grouping nor on the tile
+// shape.  Products with a block-triangular operand skip the depth range where that
+// operand is zero.
 //
 // The core A(I,J)^{-1} is carried as two block-triangular inverses (A(I,J) = P Q with
 // P = Lc(I,:), Q = Ur(:,J); see BatchMat): each iteration appends one block row to
